@@ -1,0 +1,305 @@
+"""Hierarchical Particle-Mesh in FP64, step by step in the paper's order.
+
+TEST INFRASTRUCTURE ONLY (parity oracle); the product never imports this module.
+
+Steps (Sec. 1, enumerated list, and Sec. 2):
+  P2M  leaf effective masses from Cartesian multipoles: Eq. (2) then Eq. (5).
+  M2M  child-to-parent translation with the matrices T^C (Sec. 2.3).
+  M2L  source-to-target over the 189-cube interaction zone (Sec. 2.1). Two modes:
+         "direct": the definition, sum_Q sum_q g(r_p - r_q) M_q over every IZ gridlet node;
+         "fft":    the method, one zero-padded (8 N_g)^3 FFT of the IZ effective masses times the
+                   transform of the exact lattice Green function (Eq. 1), target gridlet read out.
+  L2L  parent-to-child: potential multipoles Eq. (6), polynomial Eq. (7) at the child nodes.
+  L2P  Eq. (7) at each particle, its gradient for the acceleration.
+  P2P  near zone (27 cubes) by direct summation (Sec. 1, item 1).
+
+Readings (the paper is silent): the potential kernel is g(r) = -G (r^2+eps^2)^{-1/2}; expansions
+are about the cell centre in units of the cell size; M2L starts at level 2 (a non-periodic root has
+no neighbours, so level-1 interaction zones are empty); the far-field acceleration is minus the
+analytic gradient of the Eq. (7) interpolant; the near-zone force is the exact softened force; a
+particle does not act on itself. Zones are cube-complete (see tree.py).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.fft as sfft
+
+from . import tables
+from .tree import Tree
+
+
+@dataclass
+class Problem:
+    ng: int = 4
+    softening: float = 1e-3
+    gconst: float = 1.0
+    box_lo: tuple = (0.0, 0.0, 0.0)
+    box_size: float = 1.0
+    uniform_depth: int = 0
+    leaf_capacity: int = 64
+    max_depth: int = 10
+
+
+# ---------------------------------------------------------------------------------------------
+# Single-cell operators
+# ---------------------------------------------------------------------------------------------
+
+def monomials(x: np.ndarray, ng: int) -> np.ndarray:
+    """(k, M) array of x^n over the raveled multi-indices n (x in any units)."""
+    nidx = tables.multi_index(ng)
+    out = np.ones((x.shape[0], nidx.shape[0]))
+    for ax in range(3):
+        out *= x[:, ax][:, None] ** nidx[:, ax][None, :]
+    return out
+
+
+def p2m(rel: np.ndarray, m: np.ndarray, ng: int, L: float) -> np.ndarray:
+    """Effective masses of a cell of size L from particles at offsets ``rel`` from its centre.
+
+    Eq. (2): Q_n = (1/n!) sum_j m_j r_j^n (Cartesian multipoles about the centre);
+    Eq. (5): M_p = sum_n B_pn (n!/L^n) Q_n.
+    """
+    nfact = tables.factorial_vector(ng)
+    nsum = tables.multi_index(ng).sum(axis=1)
+    q = (m @ monomials(rel, ng)) / nfact                      # Eq. (2)
+    return tables.inverse_3d(ng) @ (nfact / L ** nsum * q)    # Eq. (5)
+
+
+def m2m(children: dict, ng: int) -> np.ndarray:
+    """M^P = sum_C T^C M^C over the real children {octant: M^C} (Sec. 2.3)."""
+    out = np.zeros(ng ** 3)
+    for c, mc in children.items():
+        out += tables.child_to_parent(ng, c) @ mc
+    return out
+
+
+def potential_multipoles(phi: np.ndarray, ng: int) -> np.ndarray:
+    """Eq. (6): V_n = sum_p B_pn Phi_p."""
+    return tables.inverse_3d(ng).T @ phi
+
+
+def l2l(phi_parent: np.ndarray, octant: int, ng: int) -> np.ndarray:
+    """Parent contribution on a child gridlet: Phi^C_p = Phi^P((a^C + x_p)/2), Eq. (6)-(7)."""
+    v = potential_multipoles(phi_parent, ng)
+    a = np.asarray(tables.child_offset(octant))
+    u = (a[None, :] + tables.node_positions(ng)) / 2.0
+    return monomials(u, ng) @ v                              # Eq. (7)
+
+
+def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float):
+    """Eq. (7) at particles (offsets ``rel`` from the cell centre) and minus its gradient.
+
+    Returns (potential (k,), acceleration (k, 3)).
+    """
+    v = potential_multipoles(phi, ng)
+    x = rel / L
+    pot = monomials(x, ng) @ v
+    nidx = tables.multi_index(ng)
+    acc = np.zeros((x.shape[0], 3))
+    for ax in range(3):
+        dm = np.ones((x.shape[0], nidx.shape[0]))
+        for bx in range(3):
+            e = nidx[:, bx]
+            if bx == ax:
+                dm *= e[None, :] * x[:, bx][:, None] ** np.maximum(e - 1, 0)[None, :]
+            else:
+                dm *= x[:, bx][:, None] ** e[None, :]
+        acc[:, ax] = -(dm @ v) / L
+    return pot, acc
+
+
+def pair_sum(tpos: np.ndarray, tids: np.ndarray, spos: np.ndarray, sm: np.ndarray,
+             sids: np.ndarray, gconst: float, eps: float):
+    """Softened direct sum of sources on targets, skipping equal particle ids (no self force)."""
+    d = tpos[:, None, :] - spos[None, :, :]
+    r2 = np.einsum("tsk,tsk->ts", d, d) + eps * eps
+    same = tids[:, None] == sids[None, :]
+    inv = np.where(same, 0.0, 1.0 / np.sqrt(np.where(same, 1.0, r2)))
+    w = sm[None, :] * inv
+    pot = -gconst * w.sum(axis=1)
+    acc = -gconst * np.einsum("ts,tsk->tk", w * inv * inv, d)
+    return pot, acc
+
+
+# ---------------------------------------------------------------------------------------------
+# Whole method
+# ---------------------------------------------------------------------------------------------
+
+class HPM:
+    """One HPM evaluation. ``mode`` selects the M2L route: "fft" (the method) or "direct"."""
+
+    def __init__(self, x, y, z, m, prob: Problem, mode: str = "fft"):
+        self.prob = prob
+        self.mode = mode
+        pos = np.stack([np.asarray(x, np.float64), np.asarray(y, np.float64),
+                        np.asarray(z, np.float64)], axis=1)
+        self.tree = Tree(pos, prob.box_lo, prob.box_size, uniform_depth=prob.uniform_depth,
+                         leaf_capacity=prob.leaf_capacity, max_depth=prob.max_depth)
+        t = self.tree
+        self.pos = pos[t.perm]
+        self.m = np.asarray(m, np.float64)[t.perm]
+        self.ng = prob.ng
+        self.M = prob.ng ** 3
+        self._virtual = {}
+        self._ghat = {}
+        self.gridlets = {}
+        self.locals = {}
+        self._upsweep()
+
+    # ---- geometry helpers ------------------------------------------------------------------
+    def _cube_gridlet(self, l: int, q) -> np.ndarray | None:
+        """Effective masses of level-l cube position q: the real cell's, else P2M of the particles
+        inside it (a part of a coarser leaf), else None (empty)."""
+        t = self.tree
+        ci = t.real_cell(l, q)
+        if ci >= 0:
+            return self.gridlets[l][ci]
+        key = (l, tuple(q))
+        if key not in self._virtual:
+            b, e = t.cube_range(l, q)
+            if e > b:
+                self._virtual[key] = p2m(self.pos[b:e] - t.cube_centre(l, q), self.m[b:e],
+                                         self.ng, t.cube_size(l))
+            else:
+                self._virtual[key] = None
+        return self._virtual[key]
+
+    # ---- step 1 + 2: P2M at leaves, M2M up the tree ------------------------------------------
+    def _upsweep(self):
+        t, ng = self.tree, self.ng
+        for l in range(t.max_level, 1, -1):
+            lev = t.levels[l]
+            g = np.zeros((len(lev), self.M))
+            for i in range(len(lev)):
+                if lev.split[i]:
+                    kids = {c: self.gridlets[l + 1][k] for c, k in enumerate(lev.children[i]) if k >= 0}
+                    g[i] = m2m(kids, ng)
+                else:
+                    b, e = lev.pb[i], lev.pe[i]
+                    g[i] = p2m(self.pos[b:e] - t.cube_centre(l, lev.coords[i]), self.m[b:e], ng,
+                               t.cube_size(l))
+            self.gridlets[l] = g
+
+    # ---- step 3: source-to-target -------------------------------------------------------------
+    def _ghat_level(self, l: int) -> np.ndarray:
+        if l not in self._ghat:
+            h = self.tree.cube_size(l) / self.ng
+            glat = tables.green_lattice(self.ng, h, self.prob.gconst, self.prob.softening)
+            self._ghat[l] = sfft.rfftn(glat)
+        return self._ghat[l]
+
+    def m2l(self, l: int, coord) -> np.ndarray:
+        t, ng = self.tree, self.ng
+        coord = np.asarray(coord, dtype=np.int64)
+        sources = []
+        for q in t.interaction_positions(coord, l):
+            g = self._cube_gridlet(l, q)
+            if g is not None:
+                sources.append((np.asarray(q), g))
+        if not sources:
+            return np.zeros(self.M)
+        if self.mode == "direct":
+            return self._m2l_direct(l, coord, sources)
+        return self._m2l_fft(l, coord, sources)
+
+    def _m2l_direct(self, l, coord, sources):
+        t, ng = self.tree, self.ng
+        L = t.cube_size(l)
+        xp = tables.node_positions(ng)
+        tnodes = t.cube_centre(l, coord) + L * xp
+        out = np.zeros(self.M)
+        for q, g in sources:
+            snodes = t.cube_centre(l, q) + L * xp
+            d = tnodes[:, None, :] - snodes[None, :, :]
+            r2 = np.einsum("tsk,tsk->ts", d, d)
+            out += tables.green_physical(r2, self.prob.gconst, self.prob.softening) @ g
+        return out
+
+    def _m2l_fft(self, l, coord, sources):
+        ng = self.ng
+        n = 8 * ng
+        origin = 2 * ((coord >> 1) - 1)            # lower corner cube of the 6^3 block
+        grid = np.zeros((n, n, n))                 # [z, y, x]
+        for q, g in sources:
+            b = q - origin
+            grid[b[2] * ng:(b[2] + 1) * ng, b[1] * ng:(b[1] + 1) * ng,
+                 b[0] * ng:(b[0] + 1) * ng] = g.reshape(ng, ng, ng)
+        pot = sfft.irfftn(sfft.rfftn(grid) * self._ghat_level(l), s=grid.shape)
+        tb = coord - origin
+        return pot[tb[2] * ng:(tb[2] + 1) * ng, tb[1] * ng:(tb[1] + 1) * ng,
+                   tb[0] * ng:(tb[0] + 1) * ng].ravel().copy()
+
+    # ---- step 4: parent-to-child, level by level ------------------------------------------------
+    def local(self, l: int, i: int) -> np.ndarray:
+        """Gridlet potential of real cell i at level l >= 2 (from the far field only)."""
+        store = self.locals.setdefault(l, {})
+        if i not in store:
+            lev = self.tree.levels[l]
+            phi = self.m2l(l, lev.coords[i])
+            if l > 2:
+                par = int(lev.parent[i])
+                phi = phi + l2l(self.local(l - 1, par), int(lev.keys[i] & 7), self.ng)
+            store[i] = phi
+        return store[i]
+
+    # ---- leaves: far field at particles plus near zone ---------------------------------------
+    def evaluate(self, sample: np.ndarray | None = None):
+        """Potential and acceleration of every particle (or of the sorted slots in ``sample``).
+
+        Returns dict with sorted-order arrays: phi, acc, phi_far, acc_far, phi_near, acc_near,
+        and ``slots`` (the sorted slots evaluated).
+        """
+        t, p = self.tree, self.prob
+        n = t.n
+        want = np.ones(n, bool) if sample is None else np.zeros(n, bool)
+        if sample is not None:
+            want[np.asarray(sample)] = True
+        phi_far = np.zeros(n)
+        acc_far = np.zeros((n, 3))
+        phi_near = np.zeros(n)
+        acc_near = np.zeros((n, 3))
+        ids = np.arange(n)
+        for l, i in t.leaves():
+            lev = t.levels[l]
+            b, e = int(lev.pb[i]), int(lev.pe[i])
+            sel = np.nonzero(want[b:e])[0] + b
+            if sel.size == 0:
+                continue
+            if l >= 2:
+                pot, acc = l2p(self.local(l, i), self.pos[sel] - t.cube_centre(l, lev.coords[i]),
+                               self.ng, t.cube_size(l))
+                phi_far[sel] = pot
+                acc_far[sel] = acc
+            srcs = [t.cube_range(l, q) for q in t.near_positions(lev.coords[i], l)]
+            sidx = np.concatenate([np.arange(sb, se) for sb, se in srcs if se > sb])
+            pot, acc = pair_sum(self.pos[sel], ids[sel], self.pos[sidx], self.m[sidx], sidx,
+                                p.gconst, p.softening)
+            phi_near[sel] = pot
+            acc_near[sel] = acc
+        slots = np.nonzero(want)[0]
+        return dict(phi=phi_far + phi_near, acc=acc_far + acc_near, phi_far=phi_far,
+                    acc_far=acc_far, phi_near=phi_near, acc_near=acc_near, slots=slots)
+
+    def all_locals(self) -> dict:
+        """Gridlet potentials of every real cell at levels >= 2, as arrays per level."""
+        out = {}
+        for l in range(2, self.tree.max_level + 1):
+            out[l] = np.stack([self.local(l, i) for i in range(len(self.tree.levels[l]))]) \
+                if len(self.tree.levels[l]) else np.zeros((0, self.M))
+        return out
+
+
+def solve(x, y, z, m, prob: Problem, mode: str = "fft", sample: np.ndarray | None = None):
+    """Potentials and accelerations in INPUT order (all particles, or the input indices in
+    ``sample``). Returns (phi, acc, hpm) where phi/acc are indexed like ``sample`` (or all)."""
+    h = HPM(x, y, z, m, prob, mode)
+    inv = np.empty_like(h.tree.perm)
+    inv[h.tree.perm] = np.arange(h.tree.n)
+    if sample is None:
+        r = h.evaluate()
+        return r["phi"][inv], r["acc"][inv], h
+    slots = inv[np.asarray(sample)]
+    r = h.evaluate(slots)
+    return r["phi"][slots], r["acc"][slots], h
