@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""HPM throughput on one MI355X: particles/s of one full solve (tree build + P2M + M2M + M2L +
+L2L + L2P + P2P) in FP32, next to the FP64 GPU path at the same gridlet order, with the force
+error against a direct sum, per-stage times, the M2L roofline and the CPU oracle's rate.
+
+Workload: 2^18 particles from a Plummer sphere (scale radius 0.05, truncated at 0.5, centred),
+equal masses, adaptive tree with at most 64 particles per leaf (depth <= 10), Plummer softening
+1e-3, gridlet order N_g = 6 (the smallest supported order that reaches 1e-4 RMS force error on
+this workload). Inputs are seeded and synthetic and resident in device memory before timing.
+
+  python bench.py [--steps K] [--warmup W] [--ng 6] [--n 262144] [--no-cpu-baseline]
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def m2l_flops_per_target(ng: int) -> float:
+    """Algorithmic flops of one source-to-target FFT: forward and inverse real transforms of an
+    n^3 grid (2.5 n^3 log2 n^3 each, the usual real-FFT count) plus the real spectral multiply
+    (2 per half-spectrum point)."""
+    n = 8 * ng
+    n3 = float(n) ** 3
+    half = n * n * (n // 2 + 1)
+    return 2 * 2.5 * n3 * np.log2(n3) + 2.0 * half
+
+
+def source_sha(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(ng: int, prec: str):
+    """HBM bytes per M2L launch from committed rocprofv3 counter runs, if they were taken on the
+    current M2L source; else None."""
+    path = os.path.join(ROOT, "profiles", f"m2l_ng{ng}_{prec}_plummer2p18_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1906_10734_amd", "csrc", "m2l.hip")
+    if rec.get("m2l_source_sha") != source_sha(src):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int):
+    """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
+    p = parts.astype(np.float32 if prec == "f32" else np.float64)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    x, y, z, m = (torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
+    prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3)
+    plan = hpm.Plan(prob, x, y, z)
+    out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
+    for _ in range(warmup):
+        plan.rebuild(x, y, z)
+        plan.execute(m, *out)
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        plan.rebuild(x, y, z)
+        plan.execute(m, *out)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    st = plan.stage_times()
+    info = plan.info()
+    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, lat_p50=float(np.percentile(lat, 50)),
+               lat_p99=float(np.percentile(lat, 99)), stages=st, info=info)
+    plan.close()
+    return res, out, (x, y, z, m)
+
+
+def cpu_baseline(parts, ng: int, budget_s: float):
+    """The FP64 oracle (test infrastructure) on a bounded sample of the same workload, on one
+    host thread: tree + full up-sweep timed whole, source-to-target and parent-to-child timed on
+    a random sample of targets, near zone + interpolation on a random sample of leaves, each
+    scaled to the full counts."""
+    from threadpoolctl import threadpool_limits
+    from oracle import hpm as ohpm
+    p = parts.as_f64()
+    rng = np.random.default_rng(7)
+    with threadpool_limits(1):
+        prob = ohpm.Problem(ng=ng, softening=1e-3, leaf_capacity=64, max_depth=10)
+        t0 = time.perf_counter()
+        h = ohpm.HPM(p.x, p.y, p.z, p.m, prob, mode="fft")
+        t_up = time.perf_counter() - t0
+        t = h.tree
+        targets = [(l, i) for l in range(2, t.max_level + 1) for i in range(len(t.levels[l]))]
+        leaves = list(t.leaves())
+        deadline = time.perf_counter() + budget_s / 2
+        order = rng.permutation(len(targets))
+        n_m2l, t_m2l = 0, 0.0
+        for k in order:
+            l, i = targets[k]
+            a = time.perf_counter()
+            phi = h.m2l(l, t.levels[l].coords[i])
+            if l > 2:
+                ohpm.l2l(phi, int(t.levels[l].keys[i] & 7), ng)
+            t_m2l += time.perf_counter() - a
+            n_m2l += 1
+            if time.perf_counter() > deadline and n_m2l >= 8:
+                break
+        deadline = time.perf_counter() + budget_s / 2
+        n_leaf, t_leaf = 0, 0.0
+        for k in rng.permutation(len(leaves)):
+            l, i = leaves[k]
+            lev = t.levels[l]
+            if l >= 2:
+                h.local(l, i)  # chain of locals (not timed here; counted above per target)
+            a = time.perf_counter()
+            h.leaf_fields(l, i, np.arange(lev.pb[i], lev.pe[i]))
+            t_leaf += time.perf_counter() - a
+            n_leaf += 1
+            if time.perf_counter() > deadline and n_leaf >= 8:
+                break
+    est = t_up + len(targets) * t_m2l / n_m2l + len(leaves) * t_leaf / n_leaf
+    return {"value": p.n / est, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"tree+P2M+M2M over all {p.n} particles ({t_up:.1f} s); M2L+L2L on "
+                       f"{n_m2l} of {len(targets)} targets; L2P+P2P on {n_leaf} of {len(leaves)} "
+                       f"leaves; scaled to the full solve ({est:.1f} s est.)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ng", type=int, default=6)
+    ap.add_argument("--n", type=int, default=2 ** 18)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--profile", action="store_true",
+                    help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import plummer_sphere, random_subset
+
+    parts = plummer_sphere(args.n, 1001)
+    ng = args.ng
+    r32, out32, dev32 = run_path(hpm, torch, parts, "f32", ng, args.steps, args.warmup)
+    if args.profile:
+        src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "ms_per_step": r32["ms_per_step"],
+                          "stages": r32["stages"], "copy_bytes": 2 * src.numel() * 4}))
+        return
+    r64, out64, dev64 = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1)
+
+    # accuracy: FP64 direct sum on a 4096-particle subset of the FP64 positions
+    sub = torch.tensor(random_subset(args.n, 4096, 2002), device="cuda")
+    x64, y64, z64, m64 = dev64
+    rphi, rax, ray, raz = hpm.direct_sum(x64, y64, z64, m64, sub, 1.0, 1e-3)
+    ref = torch.stack([rax, ray, raz], 1)
+
+    def ferr(out):
+        a = torch.stack([o[sub].double() for o in out[1:]], 1)
+        e = (a - ref).norm(dim=1) / ref.norm(dim=1)
+        return float(e.pow(2).mean().sqrt()), float(e.max())
+
+    f32_rms, f32_max = ferr(out32)
+    f64_rms, f64_max = ferr(out64)
+    phi_f32_vs_f64 = float(((out32[0].double() - out64[0]).norm() / out64[0].norm()))
+
+    n_t = r32["info"]["n_targets"]
+    m2l_ms = r32["stages"]["m2l"] / max(r32["stages"]["n_exec"], 1)
+    flops = m2l_flops_per_target(ng) * n_t
+    achieved = flops / (m2l_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic_from_profile(ng, "f32"), "kernel": "k_m2l<float,%d>" % ng,
+                "launch_ms": round(m2l_ms, 4), "targets_per_launch": n_t,
+                "flops_per_target": m2l_flops_per_target(ng)}
+
+    value = args.n / (r32["ms_per_step"] * 1e-3)
+    v64 = args.n / (r64["ms_per_step"] * 1e-3)
+    rec = {
+        "metric": "HPM particles/s (FP32 vs FP64 GPU) at 1e-4 force err; solve p50/p99 latency",
+        "value": round(value, 1), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Plummer sphere)",
+        "config": {"workload": f"plummer sphere N={args.n} a=0.05 r_t=0.5, leaf<=64, depth<=10, "
+                               f"N_g={ng}, eps=1e-3", "n": args.n, "ng": ng,
+                   "leaf_capacity": 64, "max_depth": 10, "softening": 1e-3,
+                   "levels": r32["info"]["cells_per_level"], "targets": n_t,
+                   "leaves": r32["info"]["n_leaves"]},
+        "latency_ms": {"p50": round(r32["lat_p50"], 4), "p99": round(r32["lat_p99"], 4)},
+        "fp64": {"value": round(v64, 1), "ms_per_step": round(r64["ms_per_step"], 4),
+                 "latency_ms": {"p50": round(r64["lat_p50"], 4), "p99": round(r64["lat_p99"], 4)},
+                 "force_err_rms": f64_rms, "force_err_max": f64_max},
+        "fp32_over_fp64": round(value / v64, 3),
+        "force_err_rms": f32_rms, "force_err_max": f32_max,
+        "phi_rel_rms_f32_vs_f64": phi_f32_vs_f64,
+        "stage_ms_per_step": {k: round(v / max(r32["stages"]["n_exec"], 1), 4)
+                              for k, v in r32["stages"].items() if k not in ("n_exec", "n_build")},
+        "roofline": roofline,
+    }
+    rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(parts, ng, args.cpu_seconds)
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

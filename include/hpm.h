@@ -1,0 +1,200 @@
+/*
+ * hpm.h -- C ABI of the Hierarchical Particle-Mesh (HPM) library for AMD Instinct MI355X
+ * (gfx950). HPM (Gnedin, "Hierarchical Particle-Mesh: an FFT-accelerated Fast Multipole
+ * Method", arXiv:1906.10734) is an FMM in which each oct-tree cell carries a gridlet of N_g^3
+ * effective masses whose Cartesian multipoles match the cell's (Sec. 2.2), and in which the
+ * interaction-zone step is one zero-padded (8 N_g)^3 FFT convolution with the exact Green
+ * function (Sec. 2.1).
+ *
+ * Problem statement (Sec. 1, Sec. 2.1, Sec. 4): particles with positions and masses in a cubic,
+ * non-periodic box; the softened point-mass Green function g(r) = -G (r^2 + eps^2)^{-1/2};
+ * a gridlet order N_g and a tree rule. Output: potential phi_i and acceleration a_i = -grad phi_i
+ * of every particle, with the self term excluded.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays named "device" are HIP device pointers to structure-of-arrays data, one element
+ *     per particle, of the dtype given by hpm_problem.precision (float for HPM_F32, double for
+ *     HPM_F64). Arrays named "host" are ordinary host memory.
+ *   - The caller owns every array it passes; the library never frees or retains them. The
+ *     library owns plans and contexts and the device memory inside them.
+ *   - "stream" is a hipStream_t passed as void* (NULL is the legacy default stream). Compute
+ *     calls enqueue on it; results are valid once the caller has synchronised the stream.
+ *   - Calls return an hpm_status. Scalar arguments are checked on the host before any work.
+ *     hpm_plan_create reads back a device status word and fails with HPM_ERR_OUT_OF_BOX or
+ *     HPM_ERR_NONFINITE if any position is outside [box_lo, box_lo + box_size] or not finite
+ *     (a position on the upper face belongs to the last cell). On failure nothing is written to
+ *     the caller's output arrays and *out pointers are set to NULL. hpm_last_error() returns a
+ *     thread-local message about the last failure.
+ *   - A plan or context is used by one host thread at a time.
+ */
+#ifndef HPM_H
+#define HPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPM_ABI_VERSION 1
+
+typedef enum {
+  HPM_OK = 0,
+  HPM_ERR_INVALID_ARG = 1,
+  HPM_ERR_OUT_OF_BOX = 2,
+  HPM_ERR_NONFINITE = 3,
+  HPM_ERR_NO_MEMORY = 4,
+  HPM_ERR_DEVICE = 5,
+  HPM_ERR_UNSUPPORTED = 6
+} hpm_status;
+
+typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
+
+/*
+ * Problem description.
+ *   ng             gridlet points per axis (Sec. 2): 2, 3, 4, 6 or 8 (the FFT edge 8 N_g must
+ *                  factor into 2s and 3s). Other values give HPM_ERR_UNSUPPORTED.
+ *   precision      HPM_F32 or HPM_F64: dtype of all particle/output arrays and of the arithmetic
+ *                  of the path. Constant tables (fit matrix, child-to-parent matrices, Green
+ *                  function transforms) are always built in double and rounded once.
+ *   uniform_depth  > 0: every cell is split down to this level (1..10); 0: adaptive rule.
+ *   leaf_capacity  adaptive rule: a cell at level l is split while it holds more than
+ *   max_depth      leaf_capacity particles and l < max_depth (1..10).
+ *   softening      Plummer softening eps >= 0 of g(r) (eps = 0: the bare 1/r kernel).
+ *   gconst         G > 0.
+ *   box_lo, box_size  the cubic root cell (level 0), box_size > 0 (Sec. 1).
+ */
+typedef struct {
+  int32_t abi;
+  int32_t ng;
+  int32_t precision;
+  int32_t uniform_depth;
+  int32_t leaf_capacity;
+  int32_t max_depth;
+  double softening;
+  double gconst;
+  double box_lo[3];
+  double box_size;
+} hpm_problem;
+
+/* Per-solve statistics filled by hpm_plan_info (host struct owned by the caller). */
+typedef struct {
+  int32_t n_levels;             /* levels 0..n_levels-1 hold real cells */
+  int32_t ng;
+  int64_t n_particles;
+  int64_t n_cells;              /* real cells over all levels */
+  int64_t n_leaves;
+  int64_t n_targets;            /* cells at level >= 2: one source-to-target FFT each */
+  int64_t cells_per_level[11];
+  int64_t p2p_pairs;            /* near-zone pairs (including i == j slots), 0 until computed */
+} hpm_plan_info;
+
+typedef struct hpm_plan_s hpm_plan;
+
+const char* hpm_status_string(hpm_status s);
+const char* hpm_last_error(void);
+int32_t hpm_abi_version(void);
+
+/*
+ * Tree construction (Sec. 1): Morton keys of the n positions, a stable key sort (ties by input
+ * index), the levels of real cells by the tree rule, each cell's 27 cube neighbours, and the
+ * leaf list. All of it runs on the device; the host reads back one count per level. Positions
+ * are copied into the plan in sorted order, so the caller may reuse x, y, z afterwards. The
+ * plan holds every buffer hpm_plan_execute needs, sized for this tree.
+ *   problem  host; n >= 1; x, y, z device arrays of n elements.
+ *   *out     receives the plan (NULL on failure).
+ * Errors: HPM_ERR_INVALID_ARG, HPM_ERR_UNSUPPORTED, HPM_ERR_OUT_OF_BOX, HPM_ERR_NONFINITE,
+ * HPM_ERR_NO_MEMORY, HPM_ERR_DEVICE. The call synchronises "stream".
+ */
+hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x, const void* y,
+                           const void* z, void* stream, hpm_plan** out);
+
+/*
+ * One HPM evaluation on the plan's tree with masses m (device, n elements, input order):
+ *   P2M   Cartesian-moment fit of every leaf at level >= 2 (Eq. 2-5), here with Legendre
+ *         moments and the equivalent fit matrix, as one batched dense GEMM on the matrix cores;
+ *   M2M   child-to-parent translation T^C, deepest level first (Sec. 2.3);
+ *   M2L   for every cell at level >= 2: the 189-cube interaction zone in one zero-padded
+ *         (8 N_g)^3 FFT, times the transform of the exact lattice Green function, inverse FFT,
+ *         target gridlet read out (Sec. 2.1, Eq. 1);
+ *   L2L   parent-to-child via Eq. (6)-(7) evaluated at the child nodes (Sec. 2.4);
+ *   L2P + P2P  Eq. (7) and its gradient at each particle plus the near-zone direct sum over
+ *         the 27 neighbouring cubes (Sec. 1), combined with compensated addition.
+ * Outputs phi, ax, ay, az (device, n elements, input order, caller-allocated) are overwritten.
+ * Enqueued on "stream" without host synchronisation and without allocation.
+ * Errors: HPM_ERR_INVALID_ARG (NULL pointer), HPM_ERR_DEVICE (launch failure).
+ */
+hpm_status hpm_plan_execute(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,
+                            void* az, void* stream);
+
+/*
+ * Rebuilds the plan's tree for n new positions (same problem), reusing the plan's device
+ * buffers; they grow when the new tree needs more. Same checks, errors and synchronisation as
+ * hpm_plan_create; on failure the plan must not be executed until a rebuild succeeds.
+ */
+hpm_status hpm_plan_rebuild(hpm_plan* plan, int64_t n, const void* x, const void* y,
+                            const void* z, void* stream);
+
+/*
+ * Per-stage timing with HIP events recorded on the caller's stream (off by default).
+ * hpm_plan_enable_timing(plan, 1) clears the totals and starts recording; 0 stops it.
+ * hpm_plan_stage_times waits for every recorded execution and returns accumulated
+ * milliseconds in ms[6] (host): [0] tree build (create/rebuild), [1] P2M (moments + fit GEMM,
+ * with the mass gather), [2] M2M, [3] M2L, [4] L2L, [5] leaves (L2P + P2P); *n_exec and
+ * *n_build (host, may be NULL) receive the number of executions and builds timed.
+ */
+hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on);
+hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int64_t* n_build);
+
+/* Releases the plan and all its device memory (NULL is ignored). Synchronises the device. */
+void hpm_plan_destroy(hpm_plan* plan);
+
+/* One-shot solve: hpm_plan_create + hpm_plan_execute + hpm_plan_destroy. Synchronises. */
+hpm_status hpm_solve(const hpm_problem* problem, int64_t n, const void* x, const void* y,
+                     const void* z, const void* m, void* phi, void* ax, void* ay, void* az,
+                     void* stream);
+
+/* Tree and size statistics of a plan (info: host, caller-owned). */
+hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info);
+
+/*
+ * Inspection of a plan's device state, copied to host memory (synchronous on "stream").
+ * These exist so that each step can be compared with an independent implementation.
+ *   hpm_plan_copy_perm     perm[n] (int32): input index of the particle in each sorted slot.
+ *   hpm_plan_copy_cells    for level l, count = cells_per_level[l] cells in Morton order:
+ *                          coords[3*count] (int32, cube coordinates at level l), pb/pe[count]
+ *                          (int32, sorted-slot range), split[count] (int32, 1 if internal),
+ *                          parent[count] (int32, index within level l-1, -1 at level 0).
+ *                          Any output pointer may be NULL.
+ *   hpm_plan_copy_gridlets effective masses of level l cells after the last execute,
+ *                          count * N_g^3 values of the plan's dtype, node index
+ *                          i + N_g (j + N_g k) fastest in x (Sec. 2.2). Defined for l >= 2.
+ *   hpm_plan_copy_locals   gridlet potentials of level l cells (far field from source-to-target
+ *                          plus parent-to-child) after the last execute, same layout, l >= 2.
+ * Errors: HPM_ERR_INVALID_ARG for a NULL plan or a level without cells.
+ */
+hpm_status hpm_plan_copy_perm(const hpm_plan* plan, int32_t* perm);
+hpm_status hpm_plan_copy_cells(const hpm_plan* plan, int32_t level, int32_t* coords, int32_t* pb,
+                               int32_t* pe, int32_t* split, int32_t* parent);
+hpm_status hpm_plan_copy_gridlets(const hpm_plan* plan, int32_t level, void* host);
+hpm_status hpm_plan_copy_locals(const hpm_plan* plan, int32_t level, void* host);
+
+/*
+ * Softened direct sum (the force-error reference of Sec. 3.2's accuracy measure), on the
+ * device in double precision regardless of "precision" of the inputs:
+ *   phi_t = -G sum_{j != i_t} m_j (r^2+eps^2)^{-1/2},  a_t = -G sum_{j != i_t} m_j r_ij (r^2+eps^2)^{-3/2}
+ * for n_targets input indices "targets" (device int32) against all n sources.
+ *   precision   dtype of x, y, z, m (HPM_F32 or HPM_F64);
+ *   phi, ax, ay, az  device double arrays of n_targets elements (outputs).
+ */
+hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const void* y,
+                          const void* z, const void* m, int64_t n_targets, const int32_t* targets,
+                          double gconst, double softening, double* phi, double* ax, double* ay,
+                          double* az, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPM_H */

@@ -22,6 +22,7 @@ particle does not act on itself. Zones are cube-complete (see tree.py).
 from __future__ import annotations
 
 from dataclasses import dataclass
+from functools import lru_cache
 
 import numpy as np
 import scipy.fft as sfft
@@ -46,10 +47,14 @@ class Problem:
 # Single-cell operators
 # ---------------------------------------------------------------------------------------------
 
+LD = tables.LD
+
+
 def monomials(x: np.ndarray, ng: int) -> np.ndarray:
-    """(k, M) array of x^n over the raveled multi-indices n (x in any units)."""
+    """(k, M) array of x^n over the raveled multi-indices n (x in any units), extended precision."""
     nidx = tables.multi_index(ng)
-    out = np.ones((x.shape[0], nidx.shape[0]))
+    x = np.asarray(x, dtype=LD)
+    out = np.ones((x.shape[0], nidx.shape[0]), dtype=LD)
     for ax in range(3):
         out *= x[:, ax][:, None] ** nidx[:, ax][None, :]
     return out
@@ -61,31 +66,38 @@ def p2m(rel: np.ndarray, m: np.ndarray, ng: int, L: float) -> np.ndarray:
     Eq. (2): Q_n = (1/n!) sum_j m_j r_j^n (Cartesian multipoles about the centre);
     Eq. (5): M_p = sum_n B_pn (n!/L^n) Q_n.
     """
-    nfact = tables.factorial_vector(ng)
+    nfact = tables.factorial_vector(ng, LD)
     nsum = tables.multi_index(ng).sum(axis=1)
-    q = (m @ monomials(rel, ng)) / nfact                      # Eq. (2)
-    return tables.inverse_3d(ng) @ (nfact / L ** nsum * q)    # Eq. (5)
+    q = (np.asarray(m, dtype=LD) @ monomials(rel, ng)) / nfact            # Eq. (2)
+    mp = tables.inverse_3d(ng, LD) @ (nfact / LD(L) ** nsum * q)          # Eq. (5)
+    return mp.astype(np.float64)
 
 
 def m2m(children: dict, ng: int) -> np.ndarray:
     """M^P = sum_C T^C M^C over the real children {octant: M^C} (Sec. 2.3)."""
-    out = np.zeros(ng ** 3)
+    out = np.zeros(ng ** 3, dtype=LD)
     for c, mc in children.items():
-        out += tables.child_to_parent(ng, c) @ mc
-    return out
+        out += tables.child_to_parent(ng, c, LD) @ np.asarray(mc, dtype=LD)
+    return out.astype(np.float64)
 
 
 def potential_multipoles(phi: np.ndarray, ng: int) -> np.ndarray:
-    """Eq. (6): V_n = sum_p B_pn Phi_p."""
-    return tables.inverse_3d(ng).T @ phi
+    """Eq. (6): V_n = sum_p B_pn Phi_p (extended precision)."""
+    return tables.inverse_3d(ng, LD).T @ np.asarray(phi, dtype=LD)
+
+
+@lru_cache(maxsize=None)
+def _child_node_monomials(ng: int, octant: int) -> np.ndarray:
+    """u^n at the child's nodes u = (a^C + x_p)/2 in parent units (geometry only, cached)."""
+    a = np.asarray(tables.child_offset(octant), dtype=LD)
+    u = (a[None, :] + tables.node_positions(ng).astype(LD)) / LD(2)
+    return monomials(u, ng)
 
 
 def l2l(phi_parent: np.ndarray, octant: int, ng: int) -> np.ndarray:
     """Parent contribution on a child gridlet: Phi^C_p = Phi^P((a^C + x_p)/2), Eq. (6)-(7)."""
     v = potential_multipoles(phi_parent, ng)
-    a = np.asarray(tables.child_offset(octant))
-    u = (a[None, :] + tables.node_positions(ng)) / 2.0
-    return monomials(u, ng) @ v                              # Eq. (7)
+    return (_child_node_monomials(ng, octant) @ v).astype(np.float64)    # Eq. (7)
 
 
 def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float):
@@ -94,20 +106,20 @@ def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float):
     Returns (potential (k,), acceleration (k, 3)).
     """
     v = potential_multipoles(phi, ng)
-    x = rel / L
+    x = np.asarray(rel, dtype=LD) / LD(L)
     pot = monomials(x, ng) @ v
     nidx = tables.multi_index(ng)
-    acc = np.zeros((x.shape[0], 3))
+    acc = np.zeros((x.shape[0], 3), dtype=LD)
     for ax in range(3):
-        dm = np.ones((x.shape[0], nidx.shape[0]))
+        dm = np.ones((x.shape[0], nidx.shape[0]), dtype=LD)
         for bx in range(3):
             e = nidx[:, bx]
             if bx == ax:
                 dm *= e[None, :] * x[:, bx][:, None] ** np.maximum(e - 1, 0)[None, :]
             else:
                 dm *= x[:, bx][:, None] ** e[None, :]
-        acc[:, ax] = -(dm @ v) / L
-    return pot, acc
+        acc[:, ax] = -(dm @ v) / LD(L)
+    return pot.astype(np.float64), acc.astype(np.float64)
 
 
 def pair_sum(tpos: np.ndarray, tids: np.ndarray, spos: np.ndarray, sm: np.ndarray,
@@ -245,13 +257,29 @@ class HPM:
         return store[i]
 
     # ---- leaves: far field at particles plus near zone ---------------------------------------
+    def leaf_fields(self, l: int, i: int, sel: np.ndarray):
+        """Far field (Eq. 7 and its gradient, levels >= 2) and near-zone direct sum at the
+        sorted slots ``sel`` of leaf i of level l. Returns (phi_far, acc_far, phi_near, acc_near)."""
+        t, p = self.tree, self.prob
+        lev = t.levels[l]
+        if l >= 2:
+            pf, af = l2p(self.local(l, i), self.pos[sel] - t.cube_centre(l, lev.coords[i]),
+                         self.ng, t.cube_size(l))
+        else:
+            pf, af = np.zeros(sel.size), np.zeros((sel.size, 3))
+        srcs = [t.cube_range(l, q) for q in t.near_positions(lev.coords[i], l)]
+        sidx = np.concatenate([np.arange(sb, se) for sb, se in srcs if se > sb])
+        pn, an = pair_sum(self.pos[sel], sel, self.pos[sidx], self.m[sidx], sidx, p.gconst,
+                          p.softening)
+        return pf, af, pn, an
+
     def evaluate(self, sample: np.ndarray | None = None):
         """Potential and acceleration of every particle (or of the sorted slots in ``sample``).
 
         Returns dict with sorted-order arrays: phi, acc, phi_far, acc_far, phi_near, acc_near,
         and ``slots`` (the sorted slots evaluated).
         """
-        t, p = self.tree, self.prob
+        t = self.tree
         n = t.n
         want = np.ones(n, bool) if sample is None else np.zeros(n, bool)
         if sample is not None:
@@ -260,24 +288,13 @@ class HPM:
         acc_far = np.zeros((n, 3))
         phi_near = np.zeros(n)
         acc_near = np.zeros((n, 3))
-        ids = np.arange(n)
         for l, i in t.leaves():
             lev = t.levels[l]
             b, e = int(lev.pb[i]), int(lev.pe[i])
             sel = np.nonzero(want[b:e])[0] + b
             if sel.size == 0:
                 continue
-            if l >= 2:
-                pot, acc = l2p(self.local(l, i), self.pos[sel] - t.cube_centre(l, lev.coords[i]),
-                               self.ng, t.cube_size(l))
-                phi_far[sel] = pot
-                acc_far[sel] = acc
-            srcs = [t.cube_range(l, q) for q in t.near_positions(lev.coords[i], l)]
-            sidx = np.concatenate([np.arange(sb, se) for sb, se in srcs if se > sb])
-            pot, acc = pair_sum(self.pos[sel], ids[sel], self.pos[sidx], self.m[sidx], sidx,
-                                p.gconst, p.softening)
-            phi_near[sel] = pot
-            acc_near[sel] = acc
+            phi_far[sel], acc_far[sel], phi_near[sel], acc_near[sel] = self.leaf_fields(l, i, sel)
         slots = np.nonzero(want)[0]
         return dict(phi=phi_far + phi_near, acc=acc_far + acc_near, phi_far=phi_far,
                     acc_far=acc_far, phi_near=phi_near, acc_near=acc_near, slots=slots)

@@ -56,16 +56,32 @@ def _invert_exact(a: list) -> list:
     return [row[n:] for row in aug]
 
 
-@lru_cache(maxsize=None)
-def vandermonde_1d(ng: int) -> np.ndarray:
-    """A1[n, p] = x_p^n (1-D factor of A, Sec. 2.2)."""
-    return np.array([[float(v) for v in row] for row in _vandermonde_exact(ng)])
+# Extended precision (x86 80-bit) for the dynamic arithmetic of Eq. (2), (5), (6) and (7): the
+# monomial basis is ill-conditioned at high N_g (cond(A1) = 7.3e4 at N_g = 8), so doing these
+# steps literally in float64 would leave the oracle with ~1e-10 relative roundoff of its own.
+LD = np.longdouble
+
+
+def _to(rows, dtype):
+    return np.array([[dtype(v.numerator) / dtype(v.denominator) for v in row] for row in rows],
+                    dtype=dtype)
 
 
 @lru_cache(maxsize=None)
-def inverse_1d(ng: int) -> np.ndarray:
+def vandermonde_1d(ng: int, dtype=np.float64) -> np.ndarray:
+    """A1[n, p] = x_p^n (1-D factor of A, Sec. 2.2), exact, rounded once to ``dtype``."""
+    return _to(_vandermonde_exact(ng), dtype)
+
+
+@lru_cache(maxsize=None)
+def _inverse_1d_exact(ng: int) -> list:
+    return _invert_exact(_vandermonde_exact(ng))
+
+
+@lru_cache(maxsize=None)
+def inverse_1d(ng: int, dtype=np.float64) -> np.ndarray:
     """B1[p, n] = (A1^{-1})[p, n], exact rational inverse rounded once (Sec. 2.2)."""
-    return np.array([[float(v) for v in row] for row in _invert_exact(_vandermonde_exact(ng))])
+    return _to(_inverse_1d_exact(ng), dtype)
 
 
 def kron3(ax: np.ndarray, ay: np.ndarray, az: np.ndarray) -> np.ndarray:
@@ -74,16 +90,16 @@ def kron3(ax: np.ndarray, ay: np.ndarray, az: np.ndarray) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
-def vandermonde_3d(ng: int) -> np.ndarray:
+def vandermonde_3d(ng: int, dtype=np.float64) -> np.ndarray:
     """A[n, p] = x_p^n over multi-indices (Sec. 2.2)."""
-    a1 = vandermonde_1d(ng)
+    a1 = vandermonde_1d(ng, dtype)
     return kron3(a1, a1, a1)
 
 
 @lru_cache(maxsize=None)
-def inverse_3d(ng: int) -> np.ndarray:
+def inverse_3d(ng: int, dtype=np.float64) -> np.ndarray:
     """B[p, n] = A^{-1} (Sec. 2.2, the matrix of Eq. 5)."""
-    b1 = inverse_1d(ng)
+    b1 = inverse_1d(ng, dtype)
     return kron3(b1, b1, b1)
 
 
@@ -104,9 +120,9 @@ def node_positions(ng: int) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
-def factorial_vector(ng: int) -> np.ndarray:
+def factorial_vector(ng: int, dtype=np.float64) -> np.ndarray:
     """n! = n_x! n_y! n_z! for each raveled n."""
-    f = np.array([float(factorial(k)) for k in range(ng)])
+    f = np.array([factorial(k) for k in range(ng)], dtype=dtype)
     idx = multi_index(ng)
     return f[idx[:, 0]] * f[idx[:, 1]] * f[idx[:, 2]]
 
@@ -120,27 +136,32 @@ def child_offset(c: int) -> tuple:
     return tuple(0.5 if (c >> ax) & 1 else -0.5 for ax in range(3))
 
 
-def child_to_parent_1d(ng: int, a: float) -> np.ndarray:
-    """Per-axis factor of T^C (Sec. 2.3):
+@lru_cache(maxsize=None)
+def child_to_parent_1d(ng: int, a: float, dtype=np.float64) -> np.ndarray:
+    """Per-axis factor of T^C (Sec. 2.3), summed exactly in rationals and rounded once:
     T1[p, q] = sum_n sum_{m<=n} B1[p,n] * n!/(m!(n-m)!) * a^(n-m) / 2^n * A1[m,q]."""
-    b1 = inverse_1d(ng)
-    a1 = vandermonde_1d(ng)
-    t = np.zeros((ng, ng))
+    b1 = _inverse_1d_exact(ng)
+    a1 = _vandermonde_exact(ng)
+    fa = Fraction(a).limit_denominator(2)
+    rows = []
     for p in range(ng):
+        row = []
         for q in range(ng):
-            s = 0.0
+            s = Fraction(0)
             for n in range(ng):
                 for m in range(n + 1):
-                    s += b1[p, n] * comb(n, m) * a ** (n - m) / 2.0 ** n * a1[m, q]
-            t[p, q] = s
-    return t
+                    s += b1[p][n] * comb(n, m) * fa ** (n - m) / Fraction(2) ** n * a1[m][q]
+            row.append(s)
+        rows.append(row)
+    return _to(rows, dtype)
 
 
 @lru_cache(maxsize=None)
-def child_to_parent(ng: int, c: int) -> np.ndarray:
+def child_to_parent(ng: int, c: int, dtype=np.float64) -> np.ndarray:
     """T^C (M x M) for child octant c: M^P_p = sum_C sum_q T^C_{pq} M^C_q (Sec. 2.3)."""
     ax, ay, az = child_offset(c)
-    return kron3(child_to_parent_1d(ng, ax), child_to_parent_1d(ng, ay), child_to_parent_1d(ng, az))
+    return kron3(child_to_parent_1d(ng, ax, dtype), child_to_parent_1d(ng, ay, dtype),
+                 child_to_parent_1d(ng, az, dtype))
 
 
 def periodic_distance(n: int) -> np.ndarray:

@@ -146,55 +146,58 @@ class Tree:
             self._prefix[l] = self.keys >> (3 * (self.depth - l))
         return self._prefix[l]
 
+    @staticmethod
+    def _key(coord, l: int) -> int:
+        """Morton key of a level-l cube (plain Python ints; same bit order as morton_key)."""
+        x, y, z = (int(v) for v in coord)
+        k = 0
+        for b in range(l):
+            k |= ((x >> b) & 1) << (3 * b) | ((y >> b) & 1) << (3 * b + 1) | ((z >> b) & 1) << (3 * b + 2)
+        return k
+
     def cube_range(self, l: int, coord) -> tuple:
         """[b, e) in sorted order of all particles inside level-l cube ``coord`` (any position)."""
-        c = np.asarray(coord, dtype=np.int64)
-        if np.any(c < 0) or np.any(c >= 2 ** l):
+        x, y, z = (int(v) for v in coord)
+        side = 1 << l
+        if not (0 <= x < side and 0 <= y < side and 0 <= z < side):
             return (0, 0)
-        k = int(morton_key(c[0], c[1], c[2], l))
+        k = self._key((x, y, z), l)
         p = self.prefix(l)
         return (int(np.searchsorted(p, k, "left")), int(np.searchsorted(p, k, "right")))
 
     def real_cell(self, l: int, coord) -> int:
-        c = np.asarray(coord, dtype=np.int64)
-        if np.any(c < 0) or np.any(c >= 2 ** l) or l > self.max_level:
+        """Index of the real cell at level-l position ``coord``, or -1."""
+        if l > self.max_level:
             return -1
-        k = morton_key(c[0], c[1], c[2], l)
-        return int(self.levels[l].find(np.array([k]))[0])
+        if not hasattr(self, "_lookup"):
+            self._lookup = [dict(zip(map(tuple, lev.coords.tolist()), range(len(lev))))
+                            for lev in self.levels]
+        return self._lookup[l].get(tuple(int(v) for v in coord), -1)
 
     @staticmethod
     def near_positions(coord, l: int) -> list:
         """The up to 27 level-l cube positions within one cube of ``coord`` (itself included)."""
-        c = np.asarray(coord, dtype=np.int64)
-        out = []
-        for dz in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    q = c + np.array([dx, dy, dz])
-                    if np.all(q >= 0) and np.all(q < 2 ** l):
-                        out.append(tuple(int(v) for v in q))
-        return out
+        x, y, z = (int(v) for v in coord)
+        side = 1 << l
+        return [(x + dx, y + dy, z + dz)
+                for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                if 0 <= x + dx < side and 0 <= y + dy < side and 0 <= z + dz < side]
 
     @staticmethod
     def interaction_positions(coord, l: int) -> list:
         """IZ positions of a level-l target: children of the parent's near zone, minus the
         target's own near zone, inside the box (Sec. 1; 189 for an interior target)."""
-        c = np.asarray(coord, dtype=np.int64)
-        par = c >> 1
+        x, y, z = (int(v) for v in coord)
+        side = 1 << l
         out = []
-        for pz in (-1, 0, 1):
-            for py in (-1, 0, 1):
-                for px in (-1, 0, 1):
-                    pp = par + np.array([px, py, pz])
-                    for oz in (0, 1):
-                        for oy in (0, 1):
-                            for ox in (0, 1):
-                                q = 2 * pp + np.array([ox, oy, oz])
-                                if np.any(q < 0) or np.any(q >= 2 ** l):
-                                    continue
-                                if np.max(np.abs(q - c)) <= 1:
-                                    continue
-                                out.append(tuple(int(v) for v in q))
+        for qz in range(2 * ((z >> 1) - 1), 2 * ((z >> 1) + 1) + 2):
+            for qy in range(2 * ((y >> 1) - 1), 2 * ((y >> 1) + 1) + 2):
+                for qx in range(2 * ((x >> 1) - 1), 2 * ((x >> 1) + 1) + 2):
+                    if not (0 <= qx < side and 0 <= qy < side and 0 <= qz < side):
+                        continue
+                    if abs(qx - x) <= 1 and abs(qy - y) <= 1 and abs(qz - z) <= 1:
+                        continue
+                    out.append((qx, qy, qz))
         return out
 
     def leaves(self):

@@ -1,0 +1,351 @@
+// C ABI of the HPM library: argument checks, plan lifetime, the order of the method's steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "hpm_internal.h"
+
+struct hpm_plan_s {
+  hpm::Plan p;
+};
+
+namespace hpm {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void fail(hpm_status s, const std::string& msg) { throw HpmError{s, msg}; }
+
+static void check_problem(const hpm_problem* pr) {
+  if (!pr) fail(HPM_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->abi != HPM_ABI_VERSION) fail(HPM_ERR_INVALID_ARG, "problem.abi != HPM_ABI_VERSION");
+  if (pr->precision != HPM_F32 && pr->precision != HPM_F64)
+    fail(HPM_ERR_INVALID_ARG, "precision must be HPM_F32 or HPM_F64");
+  const int ng = pr->ng;
+  if (ng < 1 || ng > 16) fail(HPM_ERR_INVALID_ARG, "ng out of range");
+  if (!(ng == 2 || ng == 3 || ng == 4 || ng == 6 || ng == 8))
+    fail(HPM_ERR_UNSUPPORTED, "ng must be one of 2, 3, 4, 6, 8");
+  if (!(std::isfinite(pr->box_size) && pr->box_size > 0.0)) fail(HPM_ERR_INVALID_ARG, "box_size must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pr->box_lo[k])) fail(HPM_ERR_INVALID_ARG, "box_lo must be finite");
+  if (!(std::isfinite(pr->softening) && pr->softening >= 0.0)) fail(HPM_ERR_INVALID_ARG, "softening must be >= 0");
+  if (!(std::isfinite(pr->gconst) && pr->gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "gconst must be > 0");
+  if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
+  if (pr->uniform_depth == 0) {
+    if (pr->leaf_capacity < 1) fail(HPM_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
+    if (pr->max_depth < 1 || pr->max_depth > 10) fail(HPM_ERR_INVALID_ARG, "max_depth must be 1..10");
+  }
+}
+
+template <typename F>
+static hpm_status guarded(F&& f) {
+  try {
+    f();
+    return HPM_OK;
+  } catch (const HpmError& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return HPM_ERR_NO_MEMORY;
+  } catch (...) {
+    set_last_error("unexpected exception");
+    return HPM_ERR_DEVICE;
+  }
+}
+
+static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z,
+                         hipStream_t s) {
+  p.valid = false;
+  if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
+  p.n = n;
+  build_tree(p, x, y, z, s);
+  const size_t cells = size_t(p.ncells);
+  p.gridlet.reserve(cells * p.M * p.elem);
+  p.local.reserve(cells * p.M * p.elem);
+  const size_t rows = size_t(std::max<int64_t>(p.nleaves - p.nleaves_lt2, 1));
+  p.moments.reserve(rows * p.tab.kpad * p.elem);
+  if (p.timing) {
+    HPM_HIP(hipEventRecord(p.tree_ev[1], s));
+    HPM_HIP(hipEventSynchronize(p.tree_ev[1]));
+    float ms = 0.f;
+    HPM_HIP(hipEventElapsedTime(&ms, p.tree_ev[0], p.tree_ev[1]));
+    p.stage_ms[0] += ms;
+    p.n_build += 1;
+  }
+  HPM_HIP(hipStreamSynchronize(s));
+  p.valid = true;
+}
+
+static void create_plan(const hpm_problem* pr, int64_t n, const void* x, const void* y,
+                        const void* z, hipStream_t s, hpm_plan_s* pl) {
+  Plan& p = pl->p;
+  p.prob = *pr;
+  p.prec = pr->precision;
+  p.ng = pr->ng;
+  p.M = pr->ng * pr->ng * pr->ng;
+  p.elem = (p.prec == HPM_F32) ? 4 : 8;
+  const int depth = pr->uniform_depth > 0 ? pr->uniform_depth : pr->max_depth;
+  build_tables(p, depth + 1, s);
+  size_t slot_bytes = 0;
+  p.m2l_slots = m2l_workspace_slots(p.prec, p.ng, &slot_bytes);
+  if (slot_bytes) p.m2l_work.reserve(slot_bytes * p.m2l_slots);
+  rebuild_plan(p, n, x, y, z, s);
+}
+
+// Adds the elapsed times of the oldest pending execution to the totals.
+static void drain_one(Plan& p) {
+  const int slot = (p.ring_head - p.ring_count + Plan::kRing) % Plan::kRing;
+  HPM_HIP(hipEventSynchronize(p.ev[slot][Plan::kStages]));
+  for (int k = 0; k < Plan::kStages; ++k) {
+    float ms = 0.f;
+    HPM_HIP(hipEventElapsedTime(&ms, p.ev[slot][k], p.ev[slot][k + 1]));
+    p.stage_ms[k + 1] += ms;
+  }
+  p.n_exec += 1;
+  p.ring_count -= 1;
+}
+
+static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az,
+                         hipStream_t s) {
+  hipEvent_t* ev = nullptr;
+  if (p.timing) {
+    if (p.ring_count == Plan::kRing) drain_one(p);
+    ev = p.ev[p.ring_head];
+    p.ring_head = (p.ring_head + 1) % Plan::kRing;
+    p.ring_count += 1;
+    HPM_HIP(hipEventRecord(ev[0], s));
+  }
+  launch_gather_masses(p, m, s);
+  launch_p2m(p, s);
+  if (ev) HPM_HIP(hipEventRecord(ev[1], s));
+  for (int l = p.nlevels - 2; l >= 2; --l) launch_m2m(p, l, s);
+  if (ev) HPM_HIP(hipEventRecord(ev[2], s));
+  launch_m2l(p, s);
+  if (ev) HPM_HIP(hipEventRecord(ev[3], s));
+  for (int l = 3; l < p.nlevels; ++l) launch_l2l(p, l, s);
+  if (ev) HPM_HIP(hipEventRecord(ev[4], s));
+  launch_leaf(p, phi, ax, ay, az, s);
+  if (ev) HPM_HIP(hipEventRecord(ev[5], s));
+}
+
+Plan::~Plan() {
+  if (events_created) {
+    for (auto& set : ev)
+      for (auto& e : set)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : tree_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+}
+
+}  // namespace hpm
+
+using namespace hpm;
+
+extern "C" {
+
+const char* hpm_status_string(hpm_status s) {
+  switch (s) {
+    case HPM_OK: return "HPM_OK";
+    case HPM_ERR_INVALID_ARG: return "HPM_ERR_INVALID_ARG";
+    case HPM_ERR_OUT_OF_BOX: return "HPM_ERR_OUT_OF_BOX";
+    case HPM_ERR_NONFINITE: return "HPM_ERR_NONFINITE";
+    case HPM_ERR_NO_MEMORY: return "HPM_ERR_NO_MEMORY";
+    case HPM_ERR_DEVICE: return "HPM_ERR_DEVICE";
+    case HPM_ERR_UNSUPPORTED: return "HPM_ERR_UNSUPPORTED";
+  }
+  return "HPM_ERR_UNKNOWN";
+}
+
+const char* hpm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hpm_abi_version(void) { return HPM_ABI_VERSION; }
+
+hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x, const void* y,
+                           const void* z, void* stream, hpm_plan** out) {
+  if (out) *out = nullptr;
+  hpm_plan_s* pl = nullptr;
+  hpm_status st = guarded([&] {
+    if (!out) fail(HPM_ERR_INVALID_ARG, "out is NULL");
+    check_problem(problem);
+    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    if (!x || !y || !z) fail(HPM_ERR_INVALID_ARG, "position pointer is NULL");
+    pl = new hpm_plan_s();
+    create_plan(problem, n, x, y, z, (hipStream_t)stream, pl);
+  });
+  if (st != HPM_OK) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return HPM_OK;
+}
+
+hpm_status hpm_plan_execute(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,
+                            void* az, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (!m || !phi || !ax || !ay || !az) fail(HPM_ERR_INVALID_ARG, "array pointer is NULL");
+    if (!plan->p.valid) fail(HPM_ERR_INVALID_ARG, "plan has no valid tree (a rebuild failed)");
+    execute_plan(plan->p, m, phi, ax, ay, az, (hipStream_t)stream);
+  });
+}
+
+hpm_status hpm_plan_rebuild(hpm_plan* plan, int64_t n, const void* x, const void* y,
+                            const void* z, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    if (!x || !y || !z) fail(HPM_ERR_INVALID_ARG, "position pointer is NULL");
+    rebuild_plan(plan->p, n, x, y, z, (hipStream_t)stream);
+  });
+}
+
+hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    Plan& p = plan->p;
+    if (on && !p.events_created) {
+      for (auto& set : p.ev)
+        for (auto& e : set) HPM_HIP(hipEventCreate(&e));
+      for (auto& e : p.tree_ev) HPM_HIP(hipEventCreate(&e));
+      p.events_created = true;
+    }
+    while (p.ring_count > 0) drain_one(p);
+    for (double& v : p.stage_ms) v = 0.0;
+    p.n_exec = p.n_build = 0;
+    p.timing = on != 0;
+  });
+}
+
+hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int64_t* n_build) {
+  return guarded([&] {
+    if (!plan || !ms) fail(HPM_ERR_INVALID_ARG, "NULL argument");
+    Plan& p = plan->p;
+    while (p.ring_count > 0) drain_one(p);
+    for (int k = 0; k <= Plan::kStages; ++k) ms[k] = p.stage_ms[k];
+    if (n_exec) *n_exec = p.n_exec;
+    if (n_build) *n_build = p.n_build;
+  });
+}
+
+void hpm_plan_destroy(hpm_plan* plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  delete plan;
+}
+
+hpm_status hpm_solve(const hpm_problem* problem, int64_t n, const void* x, const void* y,
+                     const void* z, const void* m, void* phi, void* ax, void* ay, void* az,
+                     void* stream) {
+  hpm_plan* plan = nullptr;
+  hpm_status st = hpm_plan_create(problem, n, x, y, z, stream, &plan);
+  if (st != HPM_OK) return st;
+  st = hpm_plan_execute(plan, m, phi, ax, ay, az, stream);
+  if (st == HPM_OK)
+    st = guarded([&] { HPM_HIP(hipStreamSynchronize((hipStream_t)stream)); });
+  hpm_plan_destroy(plan);
+  return st;
+}
+
+hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info) {
+  return guarded([&] {
+    if (!plan || !info) fail(HPM_ERR_INVALID_ARG, "NULL argument");
+    const Plan& p = plan->p;
+    *info = hpm_plan_info{};
+    info->n_levels = p.nlevels;
+    info->ng = p.ng;
+    info->n_particles = p.n;
+    info->n_cells = p.ncells;
+    info->n_leaves = p.nleaves;
+    info->n_targets = p.nlevels > 2 ? p.ncells - p.level_off[2] : 0;
+    for (int l = 0; l < kMaxLevelsHost; ++l)
+      info->cells_per_level[l] = (l < p.nlevels) ? p.level_off[l + 1] - p.level_off[l] : 0;
+    info->p2p_pairs = 0;
+  });
+}
+
+hpm_status hpm_plan_copy_perm(const hpm_plan* plan, int32_t* perm) {
+  return guarded([&] {
+    if (!plan || !perm) fail(HPM_ERR_INVALID_ARG, "NULL argument");
+    HPM_HIP(hipMemcpy(perm, plan->p.perm.p, size_t(plan->p.n) * 4, hipMemcpyDeviceToHost));
+  });
+}
+
+static void level_range(const Plan& p, int32_t level, int* off, int* cnt) {
+  if (level < 0 || level >= p.nlevels) fail(HPM_ERR_INVALID_ARG, "level has no cells");
+  *off = p.level_off[level];
+  *cnt = p.level_off[level + 1] - p.level_off[level];
+}
+
+hpm_status hpm_plan_copy_cells(const hpm_plan* plan, int32_t level, int32_t* coords, int32_t* pb,
+                               int32_t* pe, int32_t* split, int32_t* parent) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    const Plan& p = plan->p;
+    int off, cnt;
+    level_range(p, level, &off, &cnt);
+    std::vector<int32_t> tmp(cnt);
+    if (coords) {
+      HPM_HIP(hipMemcpy(tmp.data(), p.ccoord.as<int>() + off, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+      for (int i = 0; i < cnt; ++i) {
+        coords[3 * i] = tmp[i] & 1023;
+        coords[3 * i + 1] = (tmp[i] >> 10) & 1023;
+        coords[3 * i + 2] = (tmp[i] >> 20) & 1023;
+      }
+    }
+    if (pb) HPM_HIP(hipMemcpy(pb, p.cpb.as<int>() + off, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+    if (pe) HPM_HIP(hipMemcpy(pe, p.cpe.as<int>() + off, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+    if (split) {
+      HPM_HIP(hipMemcpy(split, p.cflags.as<int>() + off, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+      for (int i = 0; i < cnt; ++i) split[i] &= 1;
+    }
+    if (parent) {
+      HPM_HIP(hipMemcpy(parent, p.cparent.as<int>() + off, size_t(cnt) * 4, hipMemcpyDeviceToHost));
+      if (level > 0)
+        for (int i = 0; i < cnt; ++i) parent[i] -= p.level_off[level - 1];
+    }
+  });
+}
+
+static hpm_status copy_rows(const hpm_plan* plan, int32_t level, void* host, bool locals) {
+  return guarded([&] {
+    if (!plan || !host) fail(HPM_ERR_INVALID_ARG, "NULL argument");
+    const Plan& p = plan->p;
+    if (level < 2) fail(HPM_ERR_INVALID_ARG, "gridlets exist at levels >= 2");
+    int off, cnt;
+    level_range(p, level, &off, &cnt);
+    const DevBuf& b = locals ? p.local : p.gridlet;
+    HPM_HIP(hipMemcpy(host, static_cast<const char*>(b.p) + size_t(off) * p.M * p.elem,
+                      size_t(cnt) * p.M * p.elem, hipMemcpyDeviceToHost));
+  });
+}
+
+hpm_status hpm_plan_copy_gridlets(const hpm_plan* plan, int32_t level, void* host) {
+  return copy_rows(plan, level, host, false);
+}
+
+hpm_status hpm_plan_copy_locals(const hpm_plan* plan, int32_t level, void* host) {
+  return copy_rows(plan, level, host, true);
+}
+
+hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const void* y,
+                          const void* z, const void* m, int64_t n_targets, const int32_t* targets,
+                          double gconst, double softening, double* phi, double* ax, double* ay,
+                          double* az, void* stream) {
+  return guarded([&] {
+    if (precision != HPM_F32 && precision != HPM_F64) fail(HPM_ERR_INVALID_ARG, "bad precision");
+    if (n < 1 || n > (int64_t(1) << 30) || n_targets < 0 || n_targets > n)
+      fail(HPM_ERR_INVALID_ARG, "bad sizes");
+    if (!x || !y || !z || !m || (n_targets > 0 && (!targets || !phi || !ax || !ay || !az)))
+      fail(HPM_ERR_INVALID_ARG, "NULL pointer");
+    if (!(softening >= 0.0) || !(gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "bad constants");
+    launch_direct_sum(precision, n, x, y, z, m, n_targets, targets, gconst, softening, phi, ax, ay,
+                      az, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Device helpers shared by the HIP kernels: gridlet node geometry, 1-D Lagrange and Legendre
+// bases, Morton keys, wave reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpm {
+
+constexpr int kMaxLevels = 11;  // levels 0..10 (30-bit Morton keys)
+
+// Gridlet node i of N_g per axis, in cell units centred on the cell: (i + 1/2)/N_g - 1/2.
+template <int NG>
+constexpr double node_xi(int i) { return (2.0 * i + 1.0 - NG) / (2.0 * NG); }
+
+// 1 / prod_{m != i} (xi_i - xi_m): denominators of the Lagrange basis on the gridlet nodes.
+template <int NG>
+constexpr double lagrange_inv_den(int i) {
+  double d = 1.0;
+  for (int m = 0; m < NG; ++m)
+    if (m != i) d *= (node_xi<NG>(i) - node_xi<NG>(m));
+  return 1.0 / d;
+}
+
+// l_i(u) = prod_{m != i} (u - xi_m)/(xi_i - xi_m) for all i, via prefix and suffix products.
+template <int NG, typename T>
+__device__ __forceinline__ void lagrange_basis(T u, T (&l)[NG]) {
+  T pre[NG], suf[NG];
+  pre[0] = T(1);
+#pragma unroll
+  for (int m = 1; m < NG; ++m) pre[m] = pre[m - 1] * (u - T(node_xi<NG>(m - 1)));
+  suf[NG - 1] = T(1);
+#pragma unroll
+  for (int m = NG - 2; m >= 0; --m) suf[m] = suf[m + 1] * (u - T(node_xi<NG>(m + 1)));
+#pragma unroll
+  for (int i = 0; i < NG; ++i) l[i] = pre[i] * suf[i] * T(lagrange_inv_den<NG>(i));
+}
+
+// l_i(u) and l_i'(u), by carrying (value, derivative) through the product.
+template <int NG, typename T>
+__device__ __forceinline__ void lagrange_basis_d(T u, T (&l)[NG], T (&dl)[NG]) {
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    T v = T(1), d = T(0);
+#pragma unroll
+    for (int m = 0; m < NG; ++m) {
+      if (m == i) continue;
+      const T f = u - T(node_xi<NG>(m));
+      d = d * f + v;
+      v = v * f;
+    }
+    l[i] = v * T(lagrange_inv_den<NG>(i));
+    dl[i] = d * T(lagrange_inv_den<NG>(i));
+  }
+}
+
+// Legendre polynomials P_0..P_{NG-1} at t (three-term recurrence).
+template <int NG, typename T>
+__device__ __forceinline__ void legendre(T t, T (&p)[NG]) {
+  p[0] = T(1);
+  if (NG > 1) p[1] = t;
+#pragma unroll
+  for (int k = 1; k + 1 < NG; ++k)
+    p[k + 1] = (T(2 * k + 1) * t * p[k] - T(k) * p[k - 1]) * T(1.0 / (k + 1));
+}
+
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z, int bits) {
+  uint32_t k = 0;
+  for (int b = 0; b < bits; ++b) {
+    k |= ((x >> b) & 1u) << (3 * b);
+    k |= ((y >> b) & 1u) << (3 * b + 1);
+    k |= ((z >> b) & 1u) << (3 * b + 2);
+  }
+  return k;
+}
+
+__device__ __forceinline__ int coord_x(int c) { return c & 1023; }
+__device__ __forceinline__ int coord_y(int c) { return (c >> 10) & 1023; }
+__device__ __forceinline__ int coord_z(int c) { return (c >> 20) & 1023; }
+__device__ __forceinline__ int pack_coord(int x, int y, int z) { return x | (y << 10) | (z << 20); }
+
+// first index in [lo, hi) with keys[idx] >= v
+__device__ __forceinline__ int lower_bound_u32(const uint32_t* keys, int lo, int hi, uint32_t v) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// level of a global cell id from the per-level offsets (levels are contiguous in id space)
+__device__ __forceinline__ int level_of(int gid, const int* off, int nlevels) {
+  int l = 0;
+  while (l + 1 < nlevels && gid >= off[l + 1]) ++l;
+  return l;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Neumaier two-term accumulate: (s, c) += x
+template <typename T>
+__device__ __forceinline__ void neumaier_add(T& s, T& c, T x) {
+  const T t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+}  // namespace hpm

@@ -1,0 +1,147 @@
+// Internal plan layout and launcher declarations of the HPM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hpm.h"
+
+namespace hpm {
+
+constexpr int kMaxLevelsHost = 11;  // levels 0..10
+
+struct HpmError {
+  hpm_status status;
+  std::string msg;
+};
+
+void set_last_error(const std::string& msg);
+[[noreturn]] void fail(hpm_status s, const std::string& msg);
+
+#define HPM_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::hpm::fail(e_ == hipErrorOutOfMemory ? HPM_ERR_NO_MEMORY : HPM_ERR_DEVICE,           \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+#define HPM_LAUNCH_CHECK() HPM_HIP(hipGetLastError())
+
+// A device allocation that frees itself.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // (re)allocate to at least b bytes; contents are not preserved
+  void reserve(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 16;
+    HPM_HIP(hipMalloc(&p, b));
+    bytes = b;
+  }
+  // grow to at least b bytes, preserving the first "keep" bytes
+  void grow(size_t b, size_t keep, hipStream_t s) {
+    if (b <= bytes && p) return;
+    void* q = nullptr;
+    HPM_HIP(hipMalloc(&q, b));
+    if (p && keep) HPM_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, s));
+    HPM_HIP(hipStreamSynchronize(s));
+    release();
+    p = q;
+    bytes = b;
+  }
+  template <typename U>
+  U* as() const { return static_cast<U*>(p); }
+};
+
+// Constant tables of one (precision, N_g, softening, box, levels) combination, in device memory.
+struct Tables {
+  DevBuf m2m;    // [2][NG][NG]: T1^a[p][q] = l_p((a + xi_q)/2), a = -1/2 (index 0), +1/2 (1)
+  DevBuf fitw;   // [Kpad][Mpad]: W[n][p] = B^phi[p][n], Legendre-moment fit matrix, zero padded
+  DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
+  int kpad = 0, mpad = 0;
+  int ghat_levels = 0;
+};
+
+struct Plan {
+  hpm_problem prob{};
+  int prec = HPM_F32;
+  int ng = 4;
+  int M = 64;
+  int64_t n = 0;
+  bool valid = false;  // a tree is built and consistent with the buffers
+  int depth = 0;  // Morton key depth D
+  int nlevels = 0;
+  int level_off[kMaxLevelsHost + 1] = {0};
+  int64_t ncells = 0;
+  int64_t cap_cells = 0;
+  int64_t nleaves = 0;
+  int64_t nleaves_lt2 = 0;  // leaves at levels 0 and 1 come first in the leaf list
+  size_t elem = 4;          // sizeof(real)
+
+  // particles, sorted by key
+  DevBuf keys, perm, xs, ys, zs, ms;
+  // cells (global id space, levels contiguous)
+  DevBuf ckey, ccoord, cpb, cpe, cparent, cflags, child8, nbr27;
+  DevBuf leaves;
+  DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
+  // gridlets
+  DevBuf gridlet, local, moments;
+  DevBuf m2l_work;
+  int m2l_slots = 0;
+  Tables tab;
+  // scratch for the tree build
+  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff, err;
+
+  // stage timing with HIP events (off unless enabled): a ring of pending executions
+  static constexpr int kStages = 5;   // P2M, M2M, M2L, L2L, leaves
+  static constexpr int kRing = 64;
+  bool timing = false;
+  bool events_created = false;
+  hipEvent_t ev[kRing][kStages + 1] = {};
+  hipEvent_t tree_ev[2] = {};
+  int ring_head = 0, ring_count = 0;
+  double stage_ms[kStages + 1] = {0};  // [0] tree build, [1..] execute stages
+  int64_t n_exec = 0, n_build = 0;
+  ~Plan();
+
+};
+
+// ---- tables.cpp -------------------------------------------------------------------------------
+// tables for levels 2..max_levels-1 (the Green transforms depend on the level, not on the tree)
+void build_tables(Plan& p, int max_levels, hipStream_t s);
+
+// ---- tree.hip -----------------------------------------------------------------------------------
+void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
+void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
+
+// ---- upsweep.hip --------------------------------------------------------------------------------
+void launch_gather_masses(Plan& p, const void* m, hipStream_t s);
+void launch_p2m(Plan& p, hipStream_t s);
+void launch_m2m(Plan& p, int level, hipStream_t s);
+
+// ---- m2l.hip -------------------------------------------------------------------------------------
+void launch_m2l(Plan& p, hipStream_t s);
+int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
+
+// ---- downsweep.hip -------------------------------------------------------------------------------
+void launch_l2l(Plan& p, int level, hipStream_t s);
+void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s);
+void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const void* z,
+                       const void* m, int64_t nt, const int32_t* targets, double G, double eps,
+                       double* phi, double* ax, double* ay, double* az, hipStream_t s);
+
+}  // namespace hpm

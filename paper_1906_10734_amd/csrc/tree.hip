@@ -1,0 +1,523 @@
+// Oct-tree construction on the device (Sec. 1): Morton keys, a stable LSD radix sort of
+// (key, input index), levels of real cells by the split rule, child tables, the 27-cube
+// neighbourhood of every cell, and the leaf list.
+//
+// Cells live in one id space with the levels contiguous and each level in Morton order. A cell
+// is built from its parent's particle range by binary search for the 8 child key prefixes, so a
+// level costs O(cells log n), not O(n). Neighbour entry encoding (27 per cell, x fastest):
+//   >= 0        the real cell at that position (same level)
+//   -1          no particle there, or outside the box
+//   <= -2       the position lies inside the coarser leaf with id (-2 - entry); its particles are
+//               the part of that leaf's range whose key prefix at this level matches the position
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "dev_common.h"
+#include "hpm_internal.h"
+
+namespace hpm {
+
+// ---------------------------------------------------------------------------------------------
+// Exclusive prefix sum of int32 (block tiles of 2048, recursive over block totals)
+// ---------------------------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_wave, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  int wave_pre = 0, all = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) wave_pre += s_wave[w];
+    all += s_wave[w];
+  }
+  __syncthreads();
+  *total = all;
+  return wave_pre + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, int n, int* sums) {
+  __shared__ int s_wave[kScanThreads / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) v += in[base + k];
+  int total;
+  (void)block_exclusive_scan(v, s_wave, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* out, int n,
+                                                            const int* block_off, int* total_out) {
+  __shared__ int s_wave[kScanThreads / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    sum += v[k];
+  }
+  int total;
+  int run = block_exclusive_scan(sum, s_wave, &total);
+  if (block_off) run += block_off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (total_out && threadIdx.x == 0) *total_out = (block_off ? block_off[blockIdx.x] : 0) + total;
+}
+
+static size_t scan_tmp_ints(int n) {
+  size_t t = 0;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    t += 2 * size_t(n);
+  }
+  return t + 16;
+}
+
+static void scan_rec(const int* in, int* out, int n, int* total, int* tmp, hipStream_t s) {
+  const int nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= 1) {
+    k_scan_tile<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total);
+    HPM_LAUNCH_CHECK();
+    return;
+  }
+  int* sums = tmp;
+  int* sums_scan = tmp + nb;
+  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, sums);
+  HPM_LAUNCH_CHECK();
+  scan_rec(sums, sums_scan, nb, total, tmp + 2 * nb, s);
+  k_scan_tile<<<nb, kScanThreads, 0, s>>>(in, out, n, sums_scan, nullptr);
+  HPM_LAUNCH_CHECK();
+}
+
+// out[i] = sum_{j<i} in[j]; *total (device int, may be null) = sum of all.
+void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s) {
+  if (n <= 0) return;
+  tmp.reserve(scan_tmp_ints(n) * sizeof(int));
+  int* t = tmp.as<int>();
+  // the last two ints of tmp hold a total when the caller passes none
+  scan_rec(in, out, n, total, t, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Morton keys
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_keys(int n, const T* x, const T* y, const T* z, double lo0, double lo1,
+                       double lo2, double hi0, double hi1, double hi2, double scale, int depth,
+                       uint32_t* keys, int* vals, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = double(x[i]), py = double(y[i]), pz = double(z[i]);
+  const int maxc = (1 << depth) - 1;
+  int bad = 0;
+  if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad = 2;
+  else if (!(px >= lo0 && px <= hi0 && py >= lo1 && py <= hi1 && pz >= lo2 && pz <= hi2)) bad = 1;
+  if (bad) {
+    atomicOr(err, bad);
+    keys[i] = 0;
+    vals[i] = i;
+    return;
+  }
+  // cube index floor((p - lo) * 2^D / size), clamped: the upper face belongs to the last cube
+  const int ix = min(max(int(floor((px - lo0) * scale)), 0), maxc);
+  const int iy = min(max(int(floor((py - lo1) * scale)), 0), maxc);
+  const int iz = min(max(int(floor((pz - lo2) * scale)), 0), maxc);
+  keys[i] = morton3(uint32_t(ix), uint32_t(iy), uint32_t(iz), depth);
+  vals[i] = i;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stable LSD radix sort of (uint32 key, int32 value), 8 bits per pass
+// ---------------------------------------------------------------------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void k_radix_hist(const uint32_t* keys, int n, int shift,
+                                                           int* hist, int nblocks) {
+  __shared__ int cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; ++r) {
+    const int i = base + r * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Items of a tile are taken in rounds of 256 in index order; within a round the rank of an
+// item among equal digits comes from wave ballots (lanes) and a per-digit prefix over the four
+// waves, so the output order is stable.
+__global__ __launch_bounds__(kRsThreads) void k_radix_scatter(const uint32_t* kin, const int* vin,
+                                                              uint32_t* kout, int* vout, int n,
+                                                              int shift, const int* offs,
+                                                              int nblocks) {
+  __shared__ int run[256];
+  __shared__ int wcnt[kRsThreads / 64][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  run[tid] = offs[tid * nblocks + blockIdx.x];
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int base = blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; ++r) {
+    const int i = base + r * kRsThreads + tid;
+    const bool valid = i < n;
+    uint32_t key = 0;
+    int val = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+    }
+    const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+    for (int w = 0; w < kRsThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    uint64_t eq = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t mb = __ballot(valid && bit);
+      eq &= bit ? mb : ~mb;
+    }
+    const int rank = __popcll(eq & lt);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(eq);
+    __syncthreads();
+    {
+      int acc = run[tid];
+#pragma unroll
+      for (int w = 0; w < kRsThreads / 64; ++w) {
+        const int c = wcnt[w][tid];
+        wcnt[w][tid] = acc;
+        acc += c;
+      }
+      run[tid] = acc;
+    }
+    __syncthreads();
+    if (valid) {
+      const int pos = wcnt[wave][d] + rank;
+      if (pos >= 0 && pos < n) {  // always true for a consistent histogram
+        kout[pos] = key;
+        vout[pos] = val;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static void radix_sort_pairs(Plan& p, int nbits, hipStream_t s) {
+  const int n = int(p.n);
+  const int nblocks = (n + kRsTile - 1) / kRsTile;
+  p.hist.reserve(size_t(256) * nblocks * sizeof(int) * 2);
+  int* hist = p.hist.as<int>();
+  int* offs = hist + 256 * nblocks;
+  uint32_t* ka = p.tmp_keys.as<uint32_t>();
+  int* va = p.tmp_vals.as<int>();
+  uint32_t* kb = p.keys.as<uint32_t>();
+  int* vb = p.perm.as<int>();
+  const int passes = (nbits + 7) / 8;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    k_radix_hist<<<nblocks, kRsThreads, 0, s>>>(ka, n, shift, hist, nblocks);
+    HPM_LAUNCH_CHECK();
+    exclusive_scan_i32(hist, offs, 256 * nblocks, nullptr, p.scan_tmp, s);
+    k_radix_scatter<<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+    HPM_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != p.keys.as<uint32_t>()) {
+    HPM_HIP(hipMemcpyAsync(p.keys.p, ka, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    HPM_HIP(hipMemcpyAsync(p.perm.p, va, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+template <typename T>
+__global__ void k_gather3(int n, const int* perm, const T* x, const T* y, const T* z, T* xs, T* ys,
+                          T* zs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = perm[i];
+  if (j < 0 || j >= n) return;
+  xs[i] = x[j];
+  ys[i] = y[j];
+  zs[i] = z[j];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Levels
+// ---------------------------------------------------------------------------------------------
+struct CellArrays {
+  uint32_t* key;
+  int* coord;
+  int* pb;
+  int* pe;
+  int* parent;
+  int* flags;
+  int* child8;
+  int* nbr27;
+};
+
+static CellArrays cells_of(Plan& p) {
+  return {p.ckey.as<uint32_t>(), p.ccoord.as<int>(), p.cpb.as<int>(), p.cpe.as<int>(),
+          p.cparent.as<int>(),   p.cflags.as<int>(),  p.child8.as<int>(), p.nbr27.as<int>()};
+}
+
+__global__ void k_root(int n, CellArrays c) {
+  const int t = threadIdx.x;
+  if (t < 27) c.nbr27[t] = (t == 13) ? 0 : -1;
+  if (t == 0) {
+    c.key[0] = 0;
+    c.coord[0] = 0;
+    c.pb[0] = 0;
+    c.pe[0] = n;
+    c.parent[0] = -1;
+  }
+}
+
+// Split decision and the 9 boundaries of the child ranges of each cell of level l.
+__global__ void k_level_split(int l, int depth, int uniform, int cap, int off, int cnt,
+                              const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int g = off + i;
+  const int pb = c.pb[g], pe = c.pe[g];
+  const bool split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
+  c.flags[g] = split ? 1 : 0;
+  if (!split) {
+    nchild[i] = 0;
+    return;
+  }
+  const int shift = 3 * (depth - l - 1);
+  const uint32_t base = c.key[g] << 3;
+  int b[9];
+  b[0] = pb;
+  b[8] = pe;
+  for (int k = 1; k < 8; ++k) b[k] = lower_bound_u32(keys, b[k - 1], pe, (base + k) << shift);
+  int nc = 0;
+  for (int k = 0; k < 9; ++k) bounds[i * 9 + k] = b[k];
+  for (int k = 0; k < 8; ++k) nc += (b[k + 1] > b[k]);
+  nchild[i] = nc;
+}
+
+__global__ void k_level_emit(int off, int cnt, int off_next, const int* bounds,
+                             const int* childoff, CellArrays c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int g = off + i;
+  const bool split = c.flags[g] & 1;
+  const int cx = coord_x(c.coord[g]), cy = coord_y(c.coord[g]), cz = coord_z(c.coord[g]);
+  int r = 0;
+  for (int k = 0; k < 8; ++k) {
+    int id = -1;
+    if (split) {
+      const int b0 = bounds[i * 9 + k], b1 = bounds[i * 9 + k + 1];
+      if (b1 > b0) {
+        id = off_next + childoff[i] + r++;
+        c.key[id] = (c.key[g] << 3) | uint32_t(k);
+        c.coord[id] = pack_coord(2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + ((k >> 2) & 1));
+        c.pb[id] = b0;
+        c.pe[id] = b1;
+        c.parent[id] = g;
+      }
+    }
+    c.child8[g * 8 + k] = id;
+  }
+}
+
+// 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood.
+__global__ void k_level_nbr(int l, int off, int cnt, CellArrays c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int g = off + i;
+  const int pc = c.coord[g];
+  const int x = coord_x(pc), y = coord_y(pc), z = coord_z(pc);
+  const int par = c.parent[g];
+  const int side = 1 << l;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int qx = x + dx, qy = y + dy, qz = z + dz;
+        int v = -1;
+        if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
+          const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
+          const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+          if (e >= 0) {
+            if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
+            else v = -2 - e;
+          } else {
+            v = e;
+          }
+        }
+        c.nbr27[g * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] = v;
+      }
+}
+
+__global__ void k_leaf_flags(int ncells, const int* flags, int* isleaf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncells) isleaf[i] = (flags[i] & 1) ? 0 : 1;
+}
+
+__global__ void k_leaf_compact(int ncells, const int* flags, const int* pos, int* leaves) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncells && !(flags[i] & 1)) leaves[pos[i]] = i;
+}
+
+static void ensure_cells(Plan& p, int64_t need, int64_t keep, hipStream_t s) {
+  if (need <= p.cap_cells) return;
+  int64_t cap = std::max<int64_t>(need, p.cap_cells + p.cap_cells / 2);
+  const size_t c4 = size_t(cap) * 4, k4 = size_t(keep) * 4;
+  p.ckey.grow(c4, k4, s);
+  p.ccoord.grow(c4, k4, s);
+  p.cpb.grow(c4, k4, s);
+  p.cpe.grow(c4, k4, s);
+  p.cparent.grow(c4, k4, s);
+  p.cflags.grow(c4, k4, s);
+  p.child8.grow(c4 * 8, k4 * 8, s);
+  p.nbr27.grow(c4 * 27, k4 * 27, s);
+  p.cap_cells = cap;
+}
+
+static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
+
+void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s) {
+  const hpm_problem& pr = p.prob;
+  const int n = int(p.n);
+  const bool uniform = pr.uniform_depth > 0;
+  const int D = uniform ? pr.uniform_depth : pr.max_depth;
+  p.depth = D;
+  p.keys.reserve(size_t(n) * 4);
+  p.perm.reserve(size_t(n) * 4);
+  p.tmp_keys.reserve(size_t(n) * 4);
+  p.tmp_vals.reserve(size_t(n) * 4);
+  p.err.reserve(16);
+  HPM_HIP(hipMemsetAsync(p.err.p, 0, 4, s));
+
+  const double scale = double(1 << D) / pr.box_size;
+  const double hi0 = pr.box_lo[0] + pr.box_size, hi1 = pr.box_lo[1] + pr.box_size,
+               hi2 = pr.box_lo[2] + pr.box_size;
+  if (p.prec == HPM_F32) {
+    k_keys<float><<<nblk(n, 256), 256, 0, s>>>(n, (const float*)x, (const float*)y,
+                                               (const float*)z, pr.box_lo[0], pr.box_lo[1],
+                                               pr.box_lo[2], hi0, hi1, hi2, scale, D,
+                                               p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
+                                               p.err.as<int>());
+  } else {
+    k_keys<double><<<nblk(n, 256), 256, 0, s>>>(n, (const double*)x, (const double*)y,
+                                                (const double*)z, pr.box_lo[0], pr.box_lo[1],
+                                                pr.box_lo[2], hi0, hi1, hi2, scale, D,
+                                                p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
+                                                p.err.as<int>());
+  }
+  HPM_LAUNCH_CHECK();
+  int herr = 0;
+  HPM_HIP(hipMemcpyAsync(&herr, p.err.p, 4, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+  if (herr & 2) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
+  if (herr & 1) fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
+
+  radix_sort_pairs(p, 3 * D, s);
+
+  p.xs.reserve(size_t(n) * p.elem);
+  p.ys.reserve(size_t(n) * p.elem);
+  p.zs.reserve(size_t(n) * p.elem);
+  p.ms.reserve(size_t(n) * p.elem);
+  if (p.prec == HPM_F32)
+    k_gather3<float><<<nblk(n, 256), 256, 0, s>>>(n, p.perm.as<int>(), (const float*)x,
+                                                  (const float*)y, (const float*)z,
+                                                  p.xs.as<float>(), p.ys.as<float>(),
+                                                  p.zs.as<float>());
+  else
+    k_gather3<double><<<nblk(n, 256), 256, 0, s>>>(n, p.perm.as<int>(), (const double*)x,
+                                                   (const double*)y, (const double*)z,
+                                                   p.xs.as<double>(), p.ys.as<double>(),
+                                                   p.zs.as<double>());
+  HPM_LAUNCH_CHECK();
+
+  // levels
+  int64_t est = 64;
+  if (uniform) {
+    int64_t lvl = 1;
+    est = 0;
+    for (int l = 0; l <= D; ++l) {
+      est += std::min<int64_t>(lvl, n);
+      lvl *= 8;
+    }
+  } else {
+    est = std::max<int64_t>(1024, 3 * int64_t(n) / std::max(1, pr.leaf_capacity) + 64);
+  }
+  ensure_cells(p, est, 0, s);
+  k_root<<<1, 64, 0, s>>>(n, cells_of(p));
+  HPM_LAUNCH_CHECK();
+  int off = 0, cnt = 1;
+  p.level_off[0] = 0;
+  p.nlevels = 1;
+  int* d_total = p.err.as<int>() + 1;
+  for (int l = 0; l <= D; ++l) {
+    p.bounds.reserve(size_t(cnt) * 9 * 4);
+    p.nchild.reserve(size_t(cnt) * 4);
+    p.childoff.reserve(size_t(cnt) * 4);
+    k_level_split<<<nblk(cnt, 128), 128, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, off,
+                                                 cnt, p.keys.as<uint32_t>(), cells_of(p),
+                                                 p.bounds.as<int>(), p.nchild.as<int>());
+    HPM_LAUNCH_CHECK();
+    exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), cnt, d_total, p.scan_tmp, s);
+    int total = 0;
+    HPM_HIP(hipMemcpyAsync(&total, d_total, 4, hipMemcpyDeviceToHost, s));
+    HPM_HIP(hipStreamSynchronize(s));
+    const int off_next = off + cnt;
+    ensure_cells(p, int64_t(off_next) + total, off_next, s);
+    k_level_emit<<<nblk(cnt, 128), 128, 0, s>>>(off, cnt, off_next, p.bounds.as<int>(),
+                                                p.childoff.as<int>(), cells_of(p));
+    HPM_LAUNCH_CHECK();
+    if (total == 0) break;
+    p.level_off[l + 1] = off_next;
+    p.nlevels = l + 2;
+    off = off_next;
+    cnt = total;
+    k_level_nbr<<<nblk(cnt, 128), 128, 0, s>>>(l + 1, off, cnt, cells_of(p));
+    HPM_LAUNCH_CHECK();
+  }
+  p.ncells = off + cnt;
+  for (int l = p.nlevels; l <= kMaxLevelsHost; ++l) p.level_off[l] = int(p.ncells);
+  p.dlevel.reserve(sizeof(p.level_off));
+  HPM_HIP(hipMemcpyAsync(p.dlevel.p, p.level_off, sizeof(p.level_off), hipMemcpyHostToDevice, s));
+
+  // leaf list (global-id order, so leaves of levels 0 and 1 come first)
+  const int nc = int(p.ncells);
+  p.nchild.reserve(size_t(nc) * 4);
+  p.childoff.reserve(size_t(nc) * 4);
+  k_leaf_flags<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.nchild.as<int>());
+  HPM_LAUNCH_CHECK();
+  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nc, d_total, p.scan_tmp, s);
+  int nleaves = 0, lt2 = 0;
+  HPM_HIP(hipMemcpyAsync(&nleaves, d_total, 4, hipMemcpyDeviceToHost, s));
+  if (p.nlevels > 2)
+    HPM_HIP(hipMemcpyAsync(&lt2, p.childoff.as<int>() + p.level_off[2], 4, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+  if (p.nlevels <= 2) lt2 = nleaves;
+  p.nleaves = nleaves;
+  p.nleaves_lt2 = lt2;
+  p.leaves.reserve(size_t(std::max(nleaves, 1)) * 4);
+  k_leaf_compact<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.childoff.as<int>(),
+                                               p.leaves.as<int>());
+  HPM_LAUNCH_CHECK();
+}
+
+}  // namespace hpm

@@ -1,0 +1,250 @@
+"""ctypes binding of libhpm.so (include/hpm.h). Argument marshalling only: every step of the
+method runs in the library's HIP kernels; torch provides device memory and the stream.
+
+The library is loaded from this package's directory. If it is missing the import of this
+module raises, so no caller can fall back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhpm.so")
+
+HPM_ABI_VERSION = 1
+HPM_F64, HPM_F32 = 0, 1
+STATUS = {0: "HPM_OK", 1: "HPM_ERR_INVALID_ARG", 2: "HPM_ERR_OUT_OF_BOX", 3: "HPM_ERR_NONFINITE",
+          4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED"}
+
+# Entry points declared in include/hpm.h: name -> (restype, argtypes)
+_vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class HpmProblem(ctypes.Structure):
+    _fields_ = [("abi", ctypes.c_int32), ("ng", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("uniform_depth", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("softening", ctypes.c_double),
+                ("gconst", ctypes.c_double), ("box_lo", ctypes.c_double * 3),
+                ("box_size", ctypes.c_double)]
+
+
+class HpmPlanInfo(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("ng", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_targets", ctypes.c_int64),
+                ("cells_per_level", ctypes.c_int64 * 11), ("p2p_pairs", ctypes.c_int64)]
+
+
+SIGNATURES = {
+    "hpm_status_string": (ctypes.c_char_p, [_i32]),
+    "hpm_last_error": (ctypes.c_char_p, []),
+    "hpm_abi_version": (_i32, []),
+    "hpm_plan_create": (_i32, [ctypes.POINTER(HpmProblem), _i64, _vp, _vp, _vp, _vp,
+                               ctypes.POINTER(_vp)]),
+    "hpm_plan_execute": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "hpm_plan_destroy": (None, [_vp]),
+    "hpm_plan_rebuild": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "hpm_plan_enable_timing": (_i32, [_vp, _i32]),
+    "hpm_plan_stage_times": (_i32, [_vp, _vp, _vp, _vp]),
+    "hpm_solve": (_i32, [ctypes.POINTER(HpmProblem), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                         _vp]),
+    "hpm_plan_info_get": (_i32, [_vp, ctypes.POINTER(HpmPlanInfo)]),
+    "hpm_plan_copy_perm": (_i32, [_vp, _vp]),
+    "hpm_plan_copy_cells": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "hpm_plan_copy_gridlets": (_i32, [_vp, _i32, _vp]),
+    "hpm_plan_copy_locals": (_i32, [_vp, _i32, _vp]),
+    "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _vp, _vp, _vp,
+                              _vp, _vp]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1906_10734_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if lib.hpm_abi_version() != HPM_ABI_VERSION:
+        raise ImportError("libhpm.so ABI version mismatch")
+    return lib
+
+
+_lib = load_library()
+
+
+class HpmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.status}: {_lib.hpm_last_error().decode()}")
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise HpmError(status, where)
+
+
+@dataclass
+class Problem:
+    ng: int = 4
+    precision: str = "f32"          # "f32" or "f64"
+    uniform_depth: int = 0
+    leaf_capacity: int = 64
+    max_depth: int = 10
+    softening: float = 1e-3
+    gconst: float = 1.0
+    box_lo: tuple = (0.0, 0.0, 0.0)
+    box_size: float = 1.0
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return torch.float32 if self.precision == "f32" else torch.float64
+
+    def c(self) -> HpmProblem:
+        p = HpmProblem()
+        p.abi = HPM_ABI_VERSION
+        p.ng = self.ng
+        p.precision = HPM_F32 if self.precision == "f32" else HPM_F64
+        p.uniform_depth = self.uniform_depth
+        p.leaf_capacity = self.leaf_capacity
+        p.max_depth = self.max_depth
+        p.softening = self.softening
+        p.gconst = self.gconst
+        for k in range(3):
+            p.box_lo[k] = self.box_lo[k]
+        p.box_size = self.box_size
+        return p
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, n: int, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {dtype} with {n} elements")
+    return t.data_ptr()
+
+
+class Plan:
+    """Tree and buffers for one particle set (hpm_plan_create); execute() evaluates masses."""
+
+    def __init__(self, problem: Problem, x, y, z, stream=None):
+        self.problem = problem
+        self.n = int(x.numel())
+        dt = problem.dtype
+        self._c = problem.c()
+        h = _vp()
+        _check(_lib.hpm_plan_create(ctypes.byref(self._c), self.n, _dev(x, dt, self.n, "x"),
+                                    _dev(y, dt, self.n, "y"), _dev(z, dt, self.n, "z"),
+                                    _stream(stream), ctypes.byref(h)), "hpm_plan_create")
+        self._h = h
+
+    STAGES = ("tree", "p2m", "m2m", "m2l", "l2l", "leaf")
+
+    def rebuild(self, x, y, z, stream=None):
+        n, dt = int(x.numel()), self.problem.dtype
+        _check(_lib.hpm_plan_rebuild(self._h, n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
+                                     _dev(z, dt, n, "z"), _stream(stream)), "hpm_plan_rebuild")
+        self.n = n
+
+    def enable_timing(self, on: bool = True):
+        _check(_lib.hpm_plan_enable_timing(self._h, 1 if on else 0), "hpm_plan_enable_timing")
+
+    def stage_times(self) -> dict:
+        ms = (ctypes.c_double * 6)()
+        ne, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.hpm_plan_stage_times(self._h, ms, ctypes.byref(ne), ctypes.byref(nb)),
+               "hpm_plan_stage_times")
+        out = dict(zip(self.STAGES, list(ms)))
+        out["n_exec"], out["n_build"] = ne.value, nb.value
+        return out
+
+    def execute(self, m, phi, ax, ay, az, stream=None):
+        dt, n = self.problem.dtype, self.n
+        _check(_lib.hpm_plan_execute(self._h, _dev(m, dt, n, "m"), _dev(phi, dt, n, "phi"),
+                                     _dev(ax, dt, n, "ax"), _dev(ay, dt, n, "ay"),
+                                     _dev(az, dt, n, "az"), _stream(stream)), "hpm_plan_execute")
+
+    def __call__(self, m, stream=None):
+        out = [torch.empty(self.n, dtype=self.problem.dtype, device=m.device) for _ in range(4)]
+        self.execute(m, *out, stream=stream)
+        return tuple(out)
+
+    def info(self) -> dict:
+        i = HpmPlanInfo()
+        _check(_lib.hpm_plan_info_get(self._h, ctypes.byref(i)), "hpm_plan_info_get")
+        return dict(n_levels=i.n_levels, ng=i.ng, n_particles=i.n_particles, n_cells=i.n_cells,
+                    n_leaves=i.n_leaves, n_targets=i.n_targets,
+                    cells_per_level=list(i.cells_per_level)[:i.n_levels])
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        _check(_lib.hpm_plan_copy_perm(self._h, out.ctypes.data), "hpm_plan_copy_perm")
+        return out
+
+    def cells(self, level: int) -> dict:
+        cnt = self.info()["cells_per_level"][level]
+        coords = np.empty((cnt, 3), np.int32)
+        pb, pe, split, parent = (np.empty(cnt, np.int32) for _ in range(4))
+        _check(_lib.hpm_plan_copy_cells(self._h, level, coords.ctypes.data, pb.ctypes.data,
+                                        pe.ctypes.data, split.ctypes.data, parent.ctypes.data),
+               "hpm_plan_copy_cells")
+        return dict(coords=coords, pb=pb, pe=pe, split=split.astype(bool), parent=parent)
+
+    def _rows(self, fn, level: int) -> np.ndarray:
+        cnt = self.info()["cells_per_level"][level]
+        npdt = np.float32 if self.problem.precision == "f32" else np.float64
+        out = np.empty((cnt, self.problem.ng ** 3), npdt)
+        _check(fn(self._h, level, out.ctypes.data), fn.__name__)
+        return out
+
+    def gridlets(self, level: int) -> np.ndarray:
+        return self._rows(_lib.hpm_plan_copy_gridlets, level)
+
+    def locals(self, level: int) -> np.ndarray:
+        return self._rows(_lib.hpm_plan_copy_locals, level)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hpm_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def solve(problem: Problem, x, y, z, m, stream=None):
+    """One-shot solve (hpm_solve). Returns (phi, ax, ay, az) in input order."""
+    n, dt = int(x.numel()), problem.dtype
+    out = [torch.empty(n, dtype=dt, device=x.device) for _ in range(4)]
+    c = problem.c()
+    _check(_lib.hpm_solve(ctypes.byref(c), n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
+                          _dev(z, dt, n, "z"), _dev(m, dt, n, "m"), *(o.data_ptr() for o in out),
+                          _stream(stream)), "hpm_solve")
+    return tuple(out)
+
+
+def direct_sum(x, y, z, m, targets, gconst: float = 1.0, softening: float = 0.0, stream=None):
+    """Brute-force softened sum on the device in FP64 at the given input indices."""
+    n = int(x.numel())
+    dt = x.dtype
+    prec = HPM_F32 if dt == torch.float32 else HPM_F64
+    tg = targets.to(device=x.device, dtype=torch.int32).contiguous()
+    out = [torch.empty(tg.numel(), dtype=torch.float64, device=x.device) for _ in range(4)]
+    _check(_lib.hpm_direct_sum(prec, n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
+                               _dev(z, dt, n, "z"), _dev(m, dt, n, "m"), tg.numel(),
+                               tg.data_ptr(), gconst, softening, *(o.data_ptr() for o in out),
+                               _stream(stream)), "hpm_direct_sum")
+    return tuple(out)
