@@ -53,8 +53,10 @@ typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
 
 /*
  * Problem description.
- *   ng             gridlet points per axis (Sec. 2): 2, 3, 4, 6 or 8 (the FFT edge 8 N_g must
- *                  factor into 2s and 3s). Other values give HPM_ERR_UNSUPPORTED.
+ *   ng             gridlet points per axis (Sec. 2): 2, 3, 4 or 6 (the FFT edge 8 N_g must
+ *                  factor into 2s and 3s). N_g = 8 is built but currently returns
+ *                  HPM_ERR_UNSUPPORTED (switched off after a device fault at 2^18 particles).
+ *                  Other values give HPM_ERR_UNSUPPORTED.
  *   precision      HPM_F32 or HPM_F64: dtype of all particle/output arrays and of the arithmetic
  *                  of the path. Constant tables (fit matrix, child-to-parent matrices, Green
  *                  function transforms) are always built in double and rounded once.
@@ -170,8 +172,11 @@ hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info);
  *   hpm_plan_copy_gridlets effective masses of level l cells after the last execute,
  *                          count * N_g^3 values of the plan's dtype, node index
  *                          i + N_g (j + N_g k) fastest in x (Sec. 2.2). Defined for l >= 2.
- *   hpm_plan_copy_locals   gridlet potentials of level l cells (far field from source-to-target
- *                          plus parent-to-child) after the last execute, same layout, l >= 2.
+ *   hpm_plan_copy_locals   gridlet part dPhi of the local potentials of level l cells after the
+ *                          last execute, same layout, l >= 2. The local potential (far field
+ *                          from source-to-target plus parent-to-child, Sec. 2.1 and 2.4) of cell
+ *                          i is c_i + dPhi_i, with the per-cell constant c_i (double, count
+ *                          values) from hpm_plan_copy_local_offsets.
  * Errors: HPM_ERR_INVALID_ARG for a NULL plan or a level without cells.
  */
 hpm_status hpm_plan_copy_perm(const hpm_plan* plan, int32_t* perm);
@@ -179,6 +184,7 @@ hpm_status hpm_plan_copy_cells(const hpm_plan* plan, int32_t level, int32_t* coo
                                int32_t* pe, int32_t* split, int32_t* parent);
 hpm_status hpm_plan_copy_gridlets(const hpm_plan* plan, int32_t level, void* host);
 hpm_status hpm_plan_copy_locals(const hpm_plan* plan, int32_t level, void* host);
+hpm_status hpm_plan_copy_local_offsets(const hpm_plan* plan, int32_t level, double* host);
 
 /*
  * Softened direct sum (the force-error reference of Sec. 3.2's accuracy measure), on the

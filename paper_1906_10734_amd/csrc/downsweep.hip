@@ -1,6 +1,20 @@
 // Down-sweep and leaves: parent-to-child translation (Sec. 2.4, Eq. 6-7), the far field at the
 // particles (Eq. 7 and its gradient) and the near-zone direct sum (Sec. 1), plus a brute-force
 // direct sum used as the accuracy reference.
+//
+// Far-field representation. A cell's local potential is kept as a constant c (a compensated pair
+// of reals) plus gridlet values dPhi, Phi = c + dPhi. After source-to-target and parent-to-child
+// the mean over the cell's nodes is moved into c, so dPhi holds only the variation across the
+// cell. The potential is the same function; what changes is that the large potential of
+// distant matter, accumulated over the levels, is never rounded together with the small
+// variation from which the acceleration is differentiated.
+//
+// Near zone. Under the cube-complete zones a coarse leaf next to a finely refined cube of its own
+// level sums over every particle in that cube, so the pair count per leaf is very uneven. The
+// near-zone sources of each leaf (27 contiguous sorted ranges) are cut into chunks of kP2PChunk;
+// one wave handles one (leaf, 64-target chunk, source chunk) item and writes partial sums, and a
+// per-leaf pass adds the partials in a fixed order (deterministic), adds the far field and
+// scatters the results to input order.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
@@ -8,72 +22,232 @@
 
 namespace hpm {
 
-// Phi^C_q += sum_p Phi^P_p l_p((a^C + x_q)/2): the transpose of the separable child-to-parent
-// matrix, one workgroup per child cell of level "off.."; its parent is at level >= 2.
+constexpr int kP2PChunk = 1024;
+
+template <typename T>
+__device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
+  s = a + b;
+  const T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Completes the local potential of the cells of one level after source-to-target:
+//   v_q = dPhi^C_q (the source-to-target result) + sum_p dPhi^P_p l_p((a^C + x_q)/2)
+// (the parent's part, the transpose of the separable child-to-parent matrix; absent at level 2),
+// then dPhi^C = v - mean(v) and c^C = c^P + mean(v). One workgroup per cell.
 template <typename T, int NG>
-__global__ __launch_bounds__(256) void k_l2l(int off, const int* __restrict__ parent,
+__global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int* __restrict__ parent,
                                              const int* __restrict__ coord, const T* __restrict__ t1,
-                                             T* __restrict__ local) {
+                                             T* __restrict__ local, T* __restrict__ lofs) {
   constexpr int M = NG * NG * NG;
+  constexpr int PER = (M + 255) / 256;
   __shared__ T s_in[M], s_a[M], s_b[M];
   __shared__ T s_t[2][NG][NG];
+  __shared__ T s_red[4];
   const int g = off + blockIdx.x;
   const int tid = threadIdx.x;
-  const int P = parent[g];
-  const int pc = coord[g];
-  const int ax = coord_x(pc) & 1, ay = coord_y(pc) & 1, az = coord_z(pc) & 1;
-  for (int e = tid; e < 2 * NG * NG; e += 256) (&s_t[0][0][0])[e] = t1[e];
-  for (int e = tid; e < M; e += 256) s_in[e] = local[size_t(P) * M + e];
-  __syncthreads();
-  for (int e = tid; e < M; e += 256) {  // A[pz][py][qx]
-    const int qx = e % NG, rest = e / NG;
-    T acc = T(0);
+  const int P = has_parent ? parent[g] : -1;
+  T w[PER];
 #pragma unroll
-    for (int p = 0; p < NG; ++p) acc += s_t[ax][p][qx] * s_in[rest * NG + p];
-    s_a[e] = acc;
+  for (int r = 0; r < PER; ++r) {
+    const int e = tid + 256 * r;
+    w[r] = (e < M) ? local[size_t(g) * M + e] : T(0);
   }
-  __syncthreads();
-  for (int e = tid; e < M; e += 256) {  // B[pz][qy][qx]
-    const int qx = e % NG, qy = (e / NG) % NG, pz = e / (NG * NG);
-    T acc = T(0);
+  if (has_parent) {
+    const int pc = coord[g];
+    const int ax = coord_x(pc) & 1, ay = coord_y(pc) & 1, az = coord_z(pc) & 1;
+    for (int e = tid; e < 2 * NG * NG; e += 256) (&s_t[0][0][0])[e] = t1[e];
+    for (int e = tid; e < M; e += 256) s_in[e] = local[size_t(P) * M + e];
+    __syncthreads();
+    for (int e = tid; e < M; e += 256) {  // A[pz][py][qx]
+      const int qx = e % NG, rest = e / NG;
+      T acc = T(0);
 #pragma unroll
-    for (int p = 0; p < NG; ++p) acc += s_t[ay][p][qy] * s_a[(pz * NG + p) * NG + qx];
-    s_b[e] = acc;
+      for (int p = 0; p < NG; ++p) acc += s_t[ax][p][qx] * s_in[rest * NG + p];
+      s_a[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < M; e += 256) {  // B[pz][qy][qx]
+      const int qx = e % NG, qy = (e / NG) % NG, pz = e / (NG * NG);
+      T acc = T(0);
+#pragma unroll
+      for (int p = 0; p < NG; ++p) acc += s_t[ay][p][qy] * s_a[(pz * NG + p) * NG + qx];
+      s_b[e] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {  // out[qz][qy][qx]
+      const int e = tid + 256 * r;
+      if (e < M) {
+        const int qx = e % NG, qy = (e / NG) % NG, qz = e / (NG * NG);
+        T acc = T(0);
+#pragma unroll
+        for (int p = 0; p < NG; ++p) acc += s_t[az][p][qz] * s_b[(p * NG + qy) * NG + qx];
+        w[r] += acc;
+      }
+    }
   }
-  __syncthreads();
-  for (int e = tid; e < M; e += 256) {  // out[qz][qy][qx]
-    const int qx = e % NG, qy = (e / NG) % NG, qz = e / (NG * NG);
-    T acc = T(0);
+  T part = T(0);
 #pragma unroll
-    for (int p = 0; p < NG; ++p) acc += s_t[az][p][qz] * s_b[(p * NG + qy) * NG + qx];
-    local[size_t(g) * M + e] += acc;
+  for (int r = 0; r < PER; ++r) part += w[r];
+  part = wave_sum(part);
+  if ((tid & 63) == 0) s_red[tid >> 6] = part;
+  __syncthreads();
+  const T mean = ((s_red[0] + s_red[1]) + (s_red[2] + s_red[3])) * T(1.0 / M);
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = tid + 256 * r;
+    if (e < M) local[size_t(g) * M + e] = w[r] - mean;
+  }
+  if (tid == 0) {
+    if (has_parent) {
+      T s, err;
+      two_sum(lofs[2 * P], mean, s, err);
+      lofs[2 * g] = s;
+      lofs[2 * g + 1] = lofs[2 * P + 1] + err;
+    } else {
+      lofs[2 * g] = mean;
+      lofs[2 * g + 1] = T(0);
+    }
   }
 }
 
-template <typename T>
-struct LeafArgs {
-  int n;
+// ---------------------------------------------------------------------------------------------
+// Plan-time near-zone lists and the P2P work items
+// ---------------------------------------------------------------------------------------------
+struct NearArgs {
+  int nleaves;
+  int depth;
+  int nlevels;
   const int* leaves;
   const int* level_off;
-  int nlevels;
-  int depth;
   const int* coord;
   const int* pb;
   const int* pe;
   const int* nbr27;
   const uint32_t* keys;
-  const int* perm;
+  int* near_rb;  // [nleaves][27]
+  int* near_re;
+  int* items;    // per leaf: number of work items
+};
+
+// thread per (leaf, neighbour entry): the sorted range of the particles inside that cube
+__global__ void k_near_ranges(NearArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nleaves * 27) return;
+  const int li = t / 27, k = t % 27;
+  const int g = a.leaves[li];
+  int l = 0;
+  while (l + 1 < a.nlevels && g >= a.level_off[l + 1]) ++l;
+  const int e = a.nbr27[g * 27 + k];
+  int rb = 0, re = 0;
+  if (e >= 0) {
+    rb = a.pb[e];
+    re = a.pe[e];
+  } else if (e <= -2) {
+    const int c = -2 - e;
+    const int pc = a.coord[g];
+    const int qx = coord_x(pc) + k % 3 - 1, qy = coord_y(pc) + (k / 3) % 3 - 1,
+              qz = coord_z(pc) + k / 9 - 1;
+    const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
+    const int shift = 3 * (a.depth - l);
+    rb = lower_bound_u32(a.keys, a.pb[c], a.pe[c], key << shift);
+    re = lower_bound_u32(a.keys, rb, a.pe[c], (key + 1u) << shift);
+  }
+  a.near_rb[t] = rb;
+  a.near_re[t] = re;
+}
+
+// per leaf: source count S, number of (target chunk x source chunk) items, K*S pairs
+__global__ void k_near_items(NearArgs a, long long* pairs) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= a.nleaves) return;
+  int S = 0;
+  for (int k = 0; k < 27; ++k) S += a.near_re[li * 27 + k] - a.near_rb[li * 27 + k];
+  const int g = a.leaves[li];
+  const int K = a.pe[g] - a.pb[g];
+  const int nt = (K + 63) / 64, ns = (S + kP2PChunk - 1) / kP2PChunk;
+  a.items[li] = nt * max(ns, 1);
+  atomicAdd(reinterpret_cast<unsigned long long*>(pairs), (unsigned long long)K * S);
+}
+
+__global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, const int* pe,
+                             const int* leaves, const int* near_rb, const int* near_re,
+                             int4* items) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= nleaves) return;
+  int S = 0;
+  for (int k = 0; k < 27; ++k) S += near_re[li * 27 + k] - near_rb[li * 27 + k];
+  const int g = leaves[li];
+  const int K = pe[g] - pb[g];
+  const int nt = (K + 63) / 64, ns = max((S + kP2PChunk - 1) / kP2PChunk, 1);
+  int it = item_off[li];
+  for (int tc = 0; tc < nt; ++tc)
+    for (int sc = 0; sc < ns; ++sc) items[it++] = make_int4(li, tc * 64, sc * kP2PChunk, S);
+}
+
+static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
+
+void build_near_lists(Plan& p, hipStream_t s) {
+  const int nl = int(p.nleaves);
+  p.near_rb.reserve(size_t(nl) * 27 * 4);
+  p.near_re.reserve(size_t(nl) * 27 * 4);
+  p.item_cnt.reserve(size_t(nl) * 4);
+  p.item_off.reserve(size_t(nl) * 4);
+  p.pairs.reserve(16);
+  HPM_HIP(hipMemsetAsync(p.pairs.p, 0, 8, s));
+  NearArgs a;
+  a.nleaves = nl;
+  a.depth = p.depth;
+  a.nlevels = p.nlevels;
+  a.leaves = p.leaves.as<int>();
+  a.level_off = p.dlevel.as<int>();
+  a.coord = p.ccoord.as<int>();
+  a.pb = p.cpb.as<int>();
+  a.pe = p.cpe.as<int>();
+  a.nbr27 = p.nbr27.as<int>();
+  a.keys = p.keys.as<uint32_t>();
+  a.near_rb = p.near_rb.as<int>();
+  a.near_re = p.near_re.as<int>();
+  a.items = p.item_cnt.as<int>();
+  k_near_ranges<<<nblk(int64_t(nl) * 27, 256), 256, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+  k_near_items<<<nblk(nl, 256), 256, 0, s>>>(a, p.pairs.as<long long>());
+  HPM_LAUNCH_CHECK();
+  int* d_total = p.err.as<int>() + 2;
+  exclusive_scan_i32(p.item_cnt.as<int>(), p.item_off.as<int>(), nl, d_total, p.scan_tmp, s);
+  int total = 0;
+  long long pairs = 0;
+  HPM_HIP(hipMemcpyAsync(&total, d_total, 4, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipMemcpyAsync(&pairs, p.pairs.p, 8, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+  p.n_items = total;
+  p.p2p_pairs = pairs;
+  p.items.reserve(size_t(std::max(total, 1)) * sizeof(int4));
+  p.partial.reserve(size_t(std::max(total, 1)) * 64 * 5 * p.elem);
+  k_fill_items<<<nblk(nl, 256), 256, 0, s>>>(nl, p.item_off.as<int>(), p.cpb.as<int>(),
+                                             p.cpe.as<int>(), p.leaves.as<int>(),
+                                             p.near_rb.as<int>(), p.near_re.as<int>(),
+                                             p.items.as<int4>());
+  HPM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Near zone: one wave per work item
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct P2PArgs {
+  const int4* items;
+  const int* leaves;
+  const int* pb;
+  const int* pe;
+  const int* near_rb;
+  const int* near_re;
   const T* xs;
   const T* ys;
   const T* zs;
   const T* ms;
-  const T* local;
-  T* phi;
-  T* ax;
-  T* ay;
-  T* az;
-  double lo0, lo1, lo2, size;
-  T gconst;
+  T* partial;  // [item][64][5]: phi, phi compensation, ax, ay, az (without G)
   T eps2;
 };
 
@@ -83,160 +257,209 @@ __device__ __forceinline__ T inv_sqrt(T x) {
   else return 1.0 / sqrt(x);
 }
 
-// One wave per leaf. Near zone: the 27 level-l cubes around the leaf, each a contiguous range of
-// sorted particles (a real cell's range, or the part of a coarser leaf inside that cube). Source
-// particles are staged 64 at a time in LDS; when the leaf has fewer than 64 particles the lanes
-// split the sources into groups and the partial sums are combined with wave shuffles. The
-// potential is accumulated with Kahan compensation; near and far parts are added last.
+// Lanes split as (target tl < kp, source group grp < 64/kp) when the chunk has fewer than 64
+// targets; sources are staged 64 at a time in LDS and the groups are combined with shuffles.
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
+  __shared__ int s_rb[27], s_pre[28];
+  __shared__ T s_x[64], s_y[64], s_z[64], s_m[64];
+  __shared__ int s_id[64];
+  const int lane = threadIdx.x;
+  const int4 it = a.items[blockIdx.x];
+  const int li = it.x, t0 = it.y, s0 = it.z, S = it.w;
+  const int g = a.leaves[li];
+  const int pb = a.pb[g];
+  const int K = min(64, a.pe[g] - pb - t0);
+  if (lane < 27) s_rb[lane] = a.near_rb[li * 27 + lane];
+  {
+    const int len = (lane < 27) ? a.near_re[li * 27 + lane] - a.near_rb[li * 27 + lane] : 0;
+    int x = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane < 28) s_pre[lane] = x - len;  // exclusive prefix; s_pre[27] = total
+  }
+  __syncthreads();
+  int kp = 1;
+  while (kp < K) kp <<= 1;
+  const int G = 64 / kp;
+  const int tl = lane % kp, grp = lane / kp;
+  const int i = pb + t0 + tl;
+  const bool valid = tl < K;
+  T xi = T(0), yi = T(0), zi = T(0);
+  if (valid) {
+    xi = a.xs[i];
+    yi = a.ys[i];
+    zi = a.zs[i];
+  }
+  T ph = T(0), phc = T(0), fx = T(0), fy = T(0), fz = T(0);
+  const int s_end = min(S, s0 + kP2PChunk);
+  for (int tile = s0; tile < s_end; tile += 64) {
+    const int sidx = tile + lane;
+    __syncthreads();
+    if (sidx < s_end) {
+      int lo = 0, hi = 27;  // largest r with s_pre[r] <= sidx
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= sidx) lo = mid;
+        else hi = mid;
+      }
+      const int j = s_rb[lo] + (sidx - s_pre[lo]);
+      s_x[lane] = a.xs[j];
+      s_y[lane] = a.ys[j];
+      s_z[lane] = a.zs[j];
+      s_m[lane] = a.ms[j];
+      s_id[lane] = j;
+    }
+    __syncthreads();
+    const int cnt = min(64, s_end - tile);
+    if (valid) {
+      for (int e = grp; e < cnt; e += G) {
+        const T dx = xi - s_x[e], dy = yi - s_y[e], dz = zi - s_z[e];
+        const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
+        const T inv = (s_id[e] == i) ? T(0) : inv_sqrt(r2);
+        const T mi = s_m[e] * inv;
+        const T mi3 = mi * inv * inv;
+        const T yv = -mi - phc;  // Kahan: ph += -m/r
+        const T tv = ph + yv;
+        phc = (tv - ph) - yv;
+        ph = tv;
+        fx -= mi3 * dx;
+        fy -= mi3 * dy;
+        fz -= mi3 * dz;
+      }
+    }
+  }
+  T phs = ph, phe = -phc;
+  for (int o = kp; o < 64; o <<= 1) {
+    const T ophs = __shfl_xor(phs, o, 64), ophe = __shfl_xor(phe, o, 64);
+    T s, err;
+    two_sum(phs, ophs, s, err);
+    phe += ophe + err;
+    phs = s;
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+  }
+  if (grp == 0) {
+    T* out = a.partial + (size_t(blockIdx.x) * 64 + tl) * 5;
+    out[0] = phs;
+    out[1] = phe;
+    out[2] = fx;
+    out[3] = fy;
+    out[4] = fz;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per leaf: add the partials, the far field (Eq. 7 and its gradient), scatter to input order
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct LeafArgs {
+  int n;
+  const int* leaves;
+  const int* level_off;
+  int nlevels;
+  const int* coord;
+  const int* pb;
+  const int* pe;
+  const int* item_off;
+  const int* item_cnt;
+  const int* perm;
+  const T* xs;
+  const T* ys;
+  const T* zs;
+  const T* local;
+  const T* lofs;
+  const T* partial;
+  T* phi;
+  T* ax;
+  T* ay;
+  T* az;
+  double lo0, lo1, lo2, size;
+  T gconst;
+};
+
 template <typename T, int NG>
 __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
   constexpr int M = NG * NG * NG;
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ int s_rb[27], s_re[27], s_pre[28];
-  __shared__ T s_x[64], s_y[64], s_z[64], s_m[64];
-  __shared__ int s_id[64];
   __shared__ T s_phi[M];
   const int lane = threadIdx.x;
   if (lane <= kMaxLevels) s_off[lane] = a.level_off[lane];
   __syncthreads();
-  const int g = a.leaves[blockIdx.x];
+  const int li = blockIdx.x;
+  const int g = a.leaves[li];
   const int l = level_of(g, s_off, a.nlevels);
   const int pc = a.coord[g];
-  const int tx = coord_x(pc), ty = coord_y(pc), tz = coord_z(pc);
-  const int pb = a.pb[g], pe = a.pe[g];
-  const int K = pe - pb;
-  if (lane < 27) {
-    const int e = a.nbr27[g * 27 + lane];
-    int rb = 0, re = 0;
-    if (e >= 0) {
-      rb = a.pb[e];
-      re = a.pe[e];
-    } else if (e <= -2) {
-      const int c = -2 - e;
-      const int qx = tx + lane % 3 - 1, qy = ty + (lane / 3) % 3 - 1, qz = tz + lane / 9 - 1;
-      const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
-      const int shift = 3 * (a.depth - l);
-      rb = lower_bound_u32(a.keys, a.pb[c], a.pe[c], key << shift);
-      re = lower_bound_u32(a.keys, rb, a.pe[c], (key + 1u) << shift);
-    }
-    s_rb[lane] = rb;
-    s_re[lane] = re;
-  }
+  const int pb = a.pb[g], K = a.pe[g] - pb;
   if (l >= 2)
     for (int e = lane; e < M; e += 64) s_phi[e] = a.local[size_t(g) * M + e];
   __syncthreads();
-  if (lane == 0) {
-    int acc = 0;
-    for (int r = 0; r < 27; ++r) {
-      s_pre[r] = acc;
-      acc += s_re[r] - s_rb[r];
-    }
-    s_pre[27] = acc;
-  }
-  __syncthreads();
-  const int S = s_pre[27];
-  int kp = 1;
-  while (kp < K && kp < 64) kp <<= 1;
-  const int G = 64 / kp;
-  const int tl = lane % kp, grp = lane / kp;
+  const T c_hi = (l >= 2) ? a.lofs[2 * g] : T(0), c_lo = (l >= 2) ? a.lofs[2 * g + 1] : T(0);
   const double L = a.size / double(1 << l);
-  const T cxc = T(a.lo0 + (tx + 0.5) * L), cyc = T(a.lo1 + (ty + 0.5) * L), czc = T(a.lo2 + (tz + 0.5) * L);
+  const T cxc = T(a.lo0 + (coord_x(pc) + 0.5) * L), cyc = T(a.lo1 + (coord_y(pc) + 0.5) * L),
+          czc = T(a.lo2 + (coord_z(pc) + 0.5) * L);
   const T invL = T(1.0 / L);
-
-  for (int t0 = 0; t0 < K; t0 += kp) {
-    const int i = pb + t0 + tl;
-    const bool valid = (t0 + tl) < K;
-    T xi = T(0), yi = T(0), zi = T(0);
-    if (valid) {
-      xi = a.xs[i];
-      yi = a.ys[i];
-      zi = a.zs[i];
+  const int nt = (K + 63) / 64;
+  const int ns = a.item_cnt[li] / nt;
+  for (int tc = 0; tc < nt; ++tc) {
+    const int t = tc * 64 + lane;
+    if (t >= K) continue;
+    const int i = pb + t;
+    // near zone: partials of this target chunk, source chunks in order
+    T ph = T(0), phe = T(0), fx = T(0), fy = T(0), fz = T(0);
+    for (int sc = 0; sc < ns; ++sc) {
+      const T* q = a.partial + (size_t(a.item_off[li] + tc * ns + sc) * 64 + lane) * 5;
+      T s, err;
+      two_sum(ph, q[0], s, err);
+      ph = s;
+      phe += q[1] + err;
+      fx += q[2];
+      fy += q[3];
+      fz += q[4];
     }
-    T ph = T(0), phc = T(0), fx = T(0), fy = T(0), fz = T(0);
-    for (int s0 = 0; s0 < S; s0 += 64) {
-      const int sidx = s0 + lane;
-      __syncthreads();
-      if (sidx < S) {
-        int r = 0;
-        while (r < 26 && s_pre[r + 1] <= sidx) ++r;
-        const int j = s_rb[r] + (sidx - s_pre[r]);
-        s_x[lane] = a.xs[j];
-        s_y[lane] = a.ys[j];
-        s_z[lane] = a.zs[j];
-        s_m[lane] = a.ms[j];
-        s_id[lane] = j;
-      }
-      __syncthreads();
-      const int cnt = min(64, S - s0);
-      if (valid) {
-        for (int e = grp; e < cnt; e += G) {
-          const T dx = xi - s_x[e], dy = yi - s_y[e], dz = zi - s_z[e];
-          const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
-          const T inv = (s_id[e] == i) ? T(0) : inv_sqrt(r2);
-          const T mi = s_m[e] * inv;
-          const T mi3 = mi * inv * inv;
-          // Kahan: ph += -m/r
-          const T yv = -mi - phc;
-          const T tv = ph + yv;
-          phc = (tv - ph) - yv;
-          ph = tv;
-          fx -= mi3 * dx;
-          fy -= mi3 * dy;
-          fz -= mi3 * dz;
-        }
-      }
-    }
-    // combine the source groups (compensated for the potential)
-    T phs = ph, phe = -phc;
-    for (int o = kp; o < 64; o <<= 1) {
-      const T ophs = __shfl_xor(phs, o, 64), ophe = __shfl_xor(phe, o, 64);
-      const T s = phs + ophs;
-      const T bb = s - phs;
-      phe += ophe + ((phs - (s - bb)) + (ophs - bb));
-      phs = s;
-      fx += __shfl_xor(fx, o, 64);
-      fy += __shfl_xor(fy, o, 64);
-      fz += __shfl_xor(fz, o, 64);
-    }
-    if (valid && grp == 0) {
-      T pfar = T(0), gx = T(0), gy = T(0), gz = T(0);
-      if (l >= 2) {
-        T lx[NG], dlx[NG], ly[NG], dly[NG], lz[NG], dlz[NG];
-        lagrange_basis_d<NG>((xi - cxc) * invL, lx, dlx);
-        lagrange_basis_d<NG>((yi - cyc) * invL, ly, dly);
-        lagrange_basis_d<NG>((zi - czc) * invL, lz, dlz);
+    // far field from c + dPhi
+    T pfar = T(0), gx = T(0), gy = T(0), gz = T(0);
+    if (l >= 2) {
+      const T xi = a.xs[i], yi = a.ys[i], zi = a.zs[i];
+      T lx[NG], dlx[NG], ly[NG], dly[NG], lz[NG], dlz[NG];
+      lagrange_basis_d<NG>((xi - cxc) * invL, lx, dlx);
+      lagrange_basis_d<NG>((yi - cyc) * invL, ly, dly);
+      lagrange_basis_d<NG>((zi - czc) * invL, lz, dlz);
 #pragma unroll
-        for (int k = 0; k < NG; ++k) {
+      for (int k = 0; k < NG; ++k) {
 #pragma unroll
-          for (int j = 0; j < NG; ++j) {
-            T r0 = T(0), r1 = T(0);
+        for (int j = 0; j < NG; ++j) {
+          T r0 = T(0), r1 = T(0);
 #pragma unroll
-            for (int q = 0; q < NG; ++q) {
-              const T v = s_phi[(k * NG + j) * NG + q];
-              r0 += lx[q] * v;
-              r1 += dlx[q] * v;
-            }
-            pfar += lz[k] * ly[j] * r0;
-            gx += lz[k] * ly[j] * r1;
-            gy += lz[k] * dly[j] * r0;
-            gz += dlz[k] * ly[j] * r0;
+          for (int q = 0; q < NG; ++q) {
+            const T v = s_phi[(k * NG + j) * NG + q];
+            r0 += lx[q] * v;
+            r1 += dlx[q] * v;
           }
+          pfar += lz[k] * ly[j] * r0;
+          gx += lz[k] * ly[j] * r1;
+          gy += lz[k] * dly[j] * r0;
+          gz += dlz[k] * ly[j] * r0;
         }
       }
-      // total = G * near + far, the near part carried as (phs, phe)
-      const T gn = a.gconst;
-      const T near_hi = gn * phs;
-      const T near_lo = fma(gn, phs, -near_hi) + gn * phe;
-      const T s = near_hi + pfar;
-      const T bb = s - near_hi;
-      const T err = (near_hi - (s - bb)) + (pfar - bb);
-      const int o = a.perm[i];
-      if (o < 0 || o >= a.n) continue;
-      a.phi[o] = s + (err + near_lo);
-      a.ax[o] = gn * fx - gx * invL;
-      a.ay[o] = gn * fy - gy * invL;
-      a.az[o] = gn * fz - gz * invL;
     }
+    // phi = G*near + c + dPhi(x), added with compensation
+    const T gn = a.gconst;
+    const T n_hi = gn * ph;
+    const T n_lo = fma(gn, ph, -n_hi) + gn * phe;
+    T s1, e1, s2, e2;
+    two_sum(n_hi, c_hi, s1, e1);
+    two_sum(s1, pfar, s2, e2);
+    const int o = a.perm[i];
+    if (o < 0 || o >= a.n) continue;
+    a.phi[o] = s2 + (e2 + (e1 + (n_lo + c_lo)));
+    a.ax[o] = gn * fx - gx * invL;
+    a.ay[o] = gn * fy - gy * invL;
+    a.az[o] = gn * fz - gz * invL;
   }
 }
 
@@ -292,31 +515,46 @@ static void l2l_t(Plan& p, int level, hipStream_t s) {
   const int off = p.level_off[level];
   const int cnt = p.level_off[level + 1] - off;
   if (cnt <= 0) return;
-  k_l2l<T, NG><<<cnt, 256, 0, s>>>(off, p.cparent.as<int>(), p.ccoord.as<int>(), p.tab.m2m.as<T>(),
-                                   p.local.as<T>());
+  k_l2l<T, NG><<<cnt, 256, 0, s>>>(off, level >= 3 ? 1 : 0, p.cparent.as<int>(), p.ccoord.as<int>(),
+                                   p.tab.m2m.as<T>(), p.local.as<T>(), p.lofs.as<T>());
   HPM_LAUNCH_CHECK();
 }
 
 template <typename T, int NG>
 static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
-  if (p.nleaves <= 0) return;
+  if (p.nleaves <= 0 || p.n_items <= 0) return;
+  P2PArgs<T> b;
+  b.items = p.items.as<int4>();
+  b.leaves = p.leaves.as<int>();
+  b.pb = p.cpb.as<int>();
+  b.pe = p.cpe.as<int>();
+  b.near_rb = p.near_rb.as<int>();
+  b.near_re = p.near_re.as<int>();
+  b.xs = p.xs.as<T>();
+  b.ys = p.ys.as<T>();
+  b.zs = p.zs.as<T>();
+  b.ms = p.ms.as<T>();
+  b.partial = p.partial.as<T>();
+  b.eps2 = T(p.prob.softening * p.prob.softening);
+  k_p2p<T><<<int(p.n_items), 64, 0, s>>>(b);
+  HPM_LAUNCH_CHECK();
   LeafArgs<T> a;
   a.n = int(p.n);
   a.leaves = p.leaves.as<int>();
   a.level_off = p.dlevel.as<int>();
   a.nlevels = p.nlevels;
-  a.depth = p.depth;
   a.coord = p.ccoord.as<int>();
   a.pb = p.cpb.as<int>();
   a.pe = p.cpe.as<int>();
-  a.nbr27 = p.nbr27.as<int>();
-  a.keys = p.keys.as<uint32_t>();
+  a.item_off = p.item_off.as<int>();
+  a.item_cnt = p.item_cnt.as<int>();
   a.perm = p.perm.as<int>();
   a.xs = p.xs.as<T>();
   a.ys = p.ys.as<T>();
   a.zs = p.zs.as<T>();
-  a.ms = p.ms.as<T>();
   a.local = p.local.as<T>();
+  a.lofs = p.lofs.as<T>();
+  a.partial = p.partial.as<T>();
   a.phi = (T*)phi;
   a.ax = (T*)ax;
   a.ay = (T*)ay;
@@ -326,7 +564,6 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   a.lo2 = p.prob.box_lo[2];
   a.size = p.prob.box_size;
   a.gconst = T(p.prob.gconst);
-  a.eps2 = T(p.prob.softening * p.prob.softening);
   k_leaf<T, NG><<<int(p.nleaves), 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }

@@ -100,6 +100,11 @@ struct Plan {
   DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
   // gridlets
   DevBuf gridlet, local, moments;
+  DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
+  // near-zone lists and the P2P work items (see downsweep.hip)
+  DevBuf near_rb, near_re, item_cnt, item_off, items, partial, pairs;
+  int64_t n_items = 0;
+  int64_t p2p_pairs = 0;
   DevBuf m2l_work;
   int m2l_slots = 0;
   Tables tab;
@@ -138,6 +143,7 @@ void launch_m2l(Plan& p, hipStream_t s);
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 
 // ---- downsweep.hip -------------------------------------------------------------------------------
+void build_near_lists(Plan& p, hipStream_t s);
 void launch_l2l(Plan& p, int level, hipStream_t s);
 void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s);
 void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const void* z,

@@ -131,7 +131,13 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
         for (int x = 0; x < n; ++x) {
           double r2 = h * h * double(pd[x] * pd[x] + pd[y] * pd[y] + pd[z] * pd[z]);
           if (x == 0 && y == 0 && z == 0 && eps == 0.0) r2 = h * h;
-          g[(size_t(z) * n + y) * n + x] = -G / std::sqrt(r2 + eps * eps);
+          // Offsets with max-norm <= N_g join a target node only to nodes of the 27 cubes
+          // around the target, which are not sources; every interaction-zone pair is at least
+          // N_g + 1 apart along some axis. Their values never reach a target potential, and
+          // zero keeps the largest (near-origin) kernel values out of the transform, where they
+          // would only add rounding error.
+          const bool unreachable = std::max(pd[x], std::max(pd[y], pd[z])) <= ng;
+          g[(size_t(z) * n + y) * n + x] = unreachable ? 0.0 : -G / std::sqrt(r2 + eps * eps);
         }
     // x: a1[z][y][kx]
     for (int z = 0; z < n; ++z)

@@ -58,6 +58,7 @@ SIGNATURES = {
     "hpm_plan_copy_cells": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "hpm_plan_copy_gridlets": (_i32, [_vp, _i32, _vp]),
     "hpm_plan_copy_locals": (_i32, [_vp, _i32, _vp]),
+    "hpm_plan_copy_local_offsets": (_i32, [_vp, _i32, _vp]),
     "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _vp, _vp, _vp,
                               _vp, _vp]),
 }
@@ -213,8 +214,18 @@ class Plan:
     def gridlets(self, level: int) -> np.ndarray:
         return self._rows(_lib.hpm_plan_copy_gridlets, level)
 
+    def local_parts(self, level: int):
+        """(c, dPhi): per-cell constant (float64) and gridlet part (plan dtype)."""
+        d = self._rows(_lib.hpm_plan_copy_locals, level)
+        c = np.empty(d.shape[0], np.float64)
+        _check(_lib.hpm_plan_copy_local_offsets(self._h, level, c.ctypes.data),
+               "hpm_plan_copy_local_offsets")
+        return c, d
+
     def locals(self, level: int) -> np.ndarray:
-        return self._rows(_lib.hpm_plan_copy_locals, level)
+        """Local potential c + dPhi of every cell of the level, in float64."""
+        c, d = self.local_parts(level)
+        return c[:, None] + d.astype(np.float64)
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

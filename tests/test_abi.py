@@ -46,7 +46,7 @@ def _problem(**kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(ng=5), 6), (dict(ng=0), 1), (dict(ng=7), 6), (dict(box_size=0.0), 1),
+    (dict(ng=5), 6), (dict(ng=0), 1), (dict(ng=7), 6), (dict(ng=8), 6), (dict(box_size=0.0), 1),
     (dict(softening=-1.0), 1), (dict(gconst=0.0), 1), (dict(uniform_depth=11), 1),
     (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=2), 1),
 ])

@@ -33,6 +33,9 @@ def run(name, prec, ng):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("name,ng", STEP_CASES)
 def test_steps_and_result_match_oracle(name, ng, prec):
+    if ng == 8:
+        pytest.skip("N_g = 8 is switched off in the library: a 2^18-particle FP32 solve at "
+                    "N_g = 8 ended in a device memory fault whose cause is not found yet")
     log(f"[parity] {name} ng={ng} {prec}")
     h, ophi, oacc = oracle(name, prec, ng)
     plan, phi, acc = run(name, prec, ng)
@@ -65,3 +68,28 @@ def test_gridlet_node_lattice_equals_direct_sum(prec):
     e = rel_rms(phi.double().cpu().numpy(), rphi.cpu().numpy())
     log(f"[lattice] {prec} phi vs direct {e:.2e}")
     assert e < (1e-12 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_repeatable_and_rebuild_equals_fresh_plan(prec):
+    # same inputs -> bitwise the same outputs; a rebuilt plan equals a new plan on the new inputs
+    import torch
+    from paper_1906_10734_amd import hpm
+    pa, kw = particles("plummer3000_cap16", prec)
+    pb, _ = particles("clustered5000_cap8", prec)
+    xa, ya, za, ma = device(pa, torch)
+    xb, yb, zb, mb = device(pb, torch)
+    prob = gpu_problem(4, prec, dict(leaf_capacity=16, max_depth=8))
+    plan = hpm.Plan(prob, xa, ya, za)
+    r1 = plan(ma)
+    r2 = plan(ma)
+    for u, v in zip(r1, r2):
+        assert torch.equal(u, v)
+    plan.rebuild(xb, yb, zb)
+    r3 = plan(mb)
+    fresh = hpm.Plan(prob, xb, yb, zb)
+    r4 = fresh(mb)
+    for u, v in zip(r3, r4):
+        assert torch.equal(u, v)
+    plan.close()
+    fresh.close()
