@@ -41,6 +41,15 @@ def m2l_flops_per_target(ng: int) -> float:
     return 2 * 2.5 * n3 * np.log2(n3) + 2.0 * half
 
 
+def m2l_bytes_per_target(ng: int, elem: int) -> float:
+    """Effective bytes of one source-to-target FFT, the usual FFT bandwidth convention: one read
+    and one write of the n^2 (n/2+1) complex half-spectrum per transform pass, two passes each
+    way (4 H complex values of 2 * elem bytes)."""
+    n = 8 * ng
+    half = n * n * (n // 2 + 1)
+    return 4.0 * half * 2 * elem
+
+
 def source_sha(path: str) -> str:
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -151,7 +160,7 @@ def main():
     ap.add_argument("--n", type=int, default=2 ** 18)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--profile", action="store_true",
                     help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -195,12 +204,16 @@ def main():
     n_t = r32["info"]["n_targets"]
     m2l_ms = r32["stages"]["m2l"] / max(r32["stages"]["n_exec"], 1)
     flops = m2l_flops_per_target(ng) * n_t
-    achieved = flops / (m2l_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic_from_profile(ng, "f32"), "kernel": "k_m2l<float,%d>" % ng,
-                "launch_ms": round(m2l_ms, 4), "targets_per_launch": n_t,
-                "flops_per_target": m2l_flops_per_target(ng)}
+    nbytes = m2l_bytes_per_target(ng, 4) * n_t
+    gbs = nbytes / (m2l_ms * 1e-3) / 1e9
+    tflops = flops / (m2l_ms * 1e-3) / 1e12
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(ng, "f32"),
+                "kernel": "k_m2l<float,%d>" % ng, "launch_ms": round(m2l_ms, 4),
+                "targets_per_launch": n_t, "bytes_per_target": m2l_bytes_per_target(ng, 4),
+                "valu": {"achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / PEAK_FP32_TFLOPS, 4),
+                         "flops_per_target": m2l_flops_per_target(ng)}}
 
     value = args.n / (r32["ms_per_step"] * 1e-3)
     v64 = args.n / (r64["ms_per_step"] * 1e-3)
