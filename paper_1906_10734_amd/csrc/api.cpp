@@ -66,10 +66,11 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
   p.n = n;
   build_tree(p, x, y, z, s);
+  build_virtual(p, s);
   const size_t cells = size_t(p.ncells);
-  p.gridlet.reserve(cells * p.M * p.elem);
+  p.gridlet.reserve((cells + size_t(p.nvirt)) * p.M * p.elem);
   p.local.reserve(cells * p.M * p.elem);
-  const size_t rows = size_t(std::max<int64_t>(p.nleaves - p.nleaves_lt2, 1));
+  const size_t rows = size_t(std::max<int64_t>({p.nleaves - p.nleaves_lt2, p.nvirt, 1}));
   p.moments.reserve(rows * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
   build_near_lists(p, s);

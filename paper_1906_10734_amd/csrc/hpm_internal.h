@@ -72,6 +72,8 @@ struct Tables {
   DevBuf m2m;    // [2][NG][NG]: T1^a[p][q] = l_p((a + xi_q)/2), a = -1/2 (index 0), +1/2 (1)
   DevBuf fitw;   // [Kpad][Mpad]: W[n][p] = B^phi[p][n], Legendre-moment fit matrix, zero padded
   DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
+  DevBuf gxy;    // [levels 2..L][4 N_g][n/2+1][n/2+1]: Green function transformed along x and y
+                 // only, at z offsets d < 4 N_g, [d][ky][kx], / n^2
   int kpad = 0, mpad = 0;
   int ghat_levels = 0;
 };
@@ -97,6 +99,12 @@ struct Plan {
   // cells (global id space, levels contiguous)
   DevBuf ckey, ccoord, cpb, cpe, cparent, cflags, child8, nbr27;
   DevBuf leaves;
+  // virtual cubes (interaction-zone cubes inside coarser leaves), cell ids ncells .. ncells+nvirt-1
+  int64_t nvirt = 0;
+  DevBuf vkeys;   // [nvirt] sorted cube ids (1 << 3l | level-l Morton key)
+  DevBuf vlevel;  // [nvirt] level
+  DevBuf vlist;   // [nvirt] cell id ncells + v
+  DevBuf vids, vtmp;  // enumeration scratch
   DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
   // gridlets
   DevBuf gridlet, local, moments;
@@ -132,6 +140,8 @@ void build_tables(Plan& p, int max_levels, hipStream_t s);
 // ---- tree.hip -----------------------------------------------------------------------------------
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
 void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
+// lists the virtual cubes of the current tree and appends them to the cell arrays
+void build_virtual(Plan& p, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------
 void launch_gather_masses(Plan& p, const void* m, hipStream_t s);

@@ -19,13 +19,14 @@
 //   x^-1 : rows (y', z'), Hermitian half spectrum -> the N_g target x values
 // The line buffer ("stage", layout [z < 6N_g][y < n][kx <= n/2] complex) lives in LDS when it
 // fits, else in a per-workgroup slice of global memory. Cubes of the interaction zone that are
-// not cells of the tree but lie inside a coarser leaf get their effective masses here, from the
-// particles inside them (Lagrange weights, the closed form of Eq. 5).
+// not cells of the tree but lie inside a coarser leaf ("virtual" cubes) have their effective
+// masses fitted once per solve, beside the leaves'; they are found here by their cube id.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
 #include "fft.h"
 #include "hpm_internal.h"
+#include "zones.h"
 
 namespace hpm {
 
@@ -52,29 +53,107 @@ struct M2LArgs {
   const int* flags;
   const int* child8;
   const int* nbr27;
-  const int* pb;
-  const int* pe;
-  const uint32_t* keys;
-  const T* xs;
-  const T* ys;
-  const T* zs;
-  const T* ms;
+  const uint32_t* vkeys;  // sorted ids of the virtual cubes, whose gridlets follow the cells'
+  int nvirt;
+  int ncells;
   const T* gridlet;
   T* local;
   const T* ghat;
+  const T* gxy;
   cplx<T>* work;
   double lo0, lo1, lo2, size;
 };
 
 constexpr int fold_k(int k, int n) { return k <= n / 2 ? k : n - k; }
 
+struct TargetGeom {
+  int g, l, tx, ty, tz, cx, cy, cz, par;
+  double L;
+};
+
+__device__ __forceinline__ TargetGeom target_geom(int g, const int* s_off, int nlevels,
+                                                  const int* coord, const int* parent, double size) {
+  TargetGeom t;
+  t.g = g;
+  t.l = level_of(g, s_off, nlevels);
+  const int pc = coord[g];
+  t.tx = coord_x(pc);
+  t.ty = coord_y(pc);
+  t.tz = coord_z(pc);
+  t.cx = t.tx & 1;
+  t.cy = t.ty & 1;
+  t.cz = t.tz & 1;
+  t.par = parent[g];
+  t.L = size / double(1 << t.l);
+  return t;
+}
+
+// Source of block cube "slot" (< 216) of target t: the gridlet id of a real cell (>= 0) or of a
+// virtual cube (ncells + v), or -1 (near zone, empty, outside the box).
+template <typename T>
+__device__ __forceinline__ int resolve_slot(const M2LArgs<T>& a, const TargetGeom& t, int slot) {
+  const IzSlot z = iz_slot(t.tx, t.ty, t.tz, t.l, t.par, slot, a.nbr27, a.flags, a.child8);
+  if (z.coarse < 0) return z.real;
+  const uint32_t id = cube_id(t.l, z.key);
+  int lo = 0, hi = a.nvirt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a.vkeys[mid] < id) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < a.nvirt && a.vkeys[lo] == id) ? a.ncells + lo : -1;
+}
+
+// Sum of v[B .. B+N) as a balanced binary tree of compile-time shape.
+template <int B, int N, typename T, int L>
+__device__ __forceinline__ T tree_sum(const T (&v)[L]) {
+  if constexpr (N == 1) return v[B];
+  else return tree_sum<B, N / 2>(v) + tree_sum<B + N / 2, N - N / 2>(v);
+}
+
+// x pass of the two source rows (y0, zr) and (y0 + 1, zr) of the block grid (y0 even): the
+// gridlet rows of the six cubes along x are gathered into one complex line (first row real,
+// second imaginary), transformed, and split into the half spectra A and B of the two real rows.
+template <typename T, int NG>
+__device__ __forceinline__ void xpass_rows(const M2LArgs<T>& a, int y0, int zr, const int* s_src,
+                                           cplx<T> (&A)[4 * NG + 1], cplx<T> (&B)[4 * NG + 1]) {
+  constexpr int n = 8 * NG, M = NG * NG * NG, H = 4 * NG + 1;
+  cplx<T> line[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) line[k] = {T(0), T(0)};
+  const int bz = zr / NG, kz = zr % NG;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int yr = y0 + half;
+    const int by = yr / NG, jy = yr % NG;
+#pragma unroll
+    for (int bx = 0; bx < 6; ++bx) {
+      const int src = s_src[bx + 6 * (by + 6 * bz)];
+      if (src >= 0) {
+        const T* gsrc = a.gridlet + size_t(src) * M + (kz * NG + jy) * NG;
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+          if (half == 0) line[bx * NG + i].re = gsrc[i];
+          else line[bx * NG + i].im = gsrc[i];
+        }
+      }
+    }
+  }
+  cplx<T> zf[n];
+  fft<n, -1>(line, zf);
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const cplx<T> z1 = zf[k], z2 = zf[(n - k) % n];
+    A[k] = {T(0.5) * (z1.re + z2.re), T(0.5) * (z1.im - z2.im)};
+    B[k] = {T(0.5) * (z1.im + z2.im), T(0.5) * (z2.re - z1.re)};
+  }
+}
+
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
   using S = M2LShape<T, NG>;
   constexpr int n = S::n, H = S::H, W = S::W, M = S::M;
   __shared__ int s_src[216];
-  __shared__ int s_vb[216];
-  __shared__ int s_ve[216];
   __shared__ int s_off[kMaxLevels + 1];
   cplx<T>* stage;
   if constexpr (S::lds) {
@@ -92,109 +171,25 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
   const int t_begin = int((int64_t(a.ntargets) * xcd) / 8);
   const int t_end = int((int64_t(a.ntargets) * (xcd + 1)) / 8);
 
-  for (int t = t_begin + j; t < t_end; t += per) {
-    const int g = a.first_target + t;
+  for (int ti = t_begin + j; ti < t_end; ti += per) {
     __syncthreads();
-    const int l = level_of(g, s_off, a.nlevels);
-    const int pc = a.coord[g];
-    const int tx = coord_x(pc), ty = coord_y(pc), tz = coord_z(pc);
-    const int cx = tx & 1, cy = ty & 1, cz = tz & 1;
-    const int par = a.parent[g];
-    const double L = a.size / double(1 << l);
-
-    // ---- resolve the 216 cubes of the block -------------------------------------------------
-    if (tid < 216) {
-      const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
-      int src = -1, vb = 0, ve = 0;
-      const bool near = abs(bx - 2 - cx) <= 1 && abs(by - 2 - cy) <= 1 && abs(bz - 2 - cz) <= 1;
-      if (!near) {
-        const int e = a.nbr27[par * 27 + (bx >> 1) + 3 * (by >> 1) + 9 * (bz >> 1)];
-        const int oct = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
-        int coarse = -1;
-        if (e >= 0) {
-          if (a.flags[e] & 1) src = a.child8[e * 8 + oct];
-          else coarse = e;
-        } else if (e <= -2) {
-          coarse = -2 - e;
-        }
-        if (coarse >= 0) {
-          const int qx = 2 * ((tx >> 1) - 1) + bx, qy = 2 * ((ty >> 1) - 1) + by,
-                    qz = 2 * ((tz >> 1) - 1) + bz;
-          const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
-          const int shift = 3 * (a.depth - l);
-          const int cb = a.pb[coarse], ce = a.pe[coarse];
-          vb = lower_bound_u32(a.keys, cb, ce, key << shift);
-          ve = lower_bound_u32(a.keys, vb, ce, (key + 1u) << shift);
-          src = (ve > vb) ? -2 : -1;
-        }
-      }
-      s_src[tid] = src;
-      s_vb[tid] = vb;
-      s_ve[tid] = ve;
-    }
+    const TargetGeom t = target_geom(a.first_target + ti, s_off, a.nlevels, a.coord, a.parent, a.size);
+    const int g = t.g, l = t.l, cx = t.cx, cy = t.cy, cz = t.cz;
+    if (tid < 216) s_src[tid] = resolve_slot(a, t, tid);
     __syncthreads();
 
     // ---- x: gather two rows, real-to-complex --------------------------------------------------
     for (int w = tid; w < W * W / 2; w += blockDim.x) {
       const int r0 = 2 * w;
       const int y0 = r0 % W, zr = r0 / W;  // rows (y0, zr) and (y0 + 1, zr)
-      cplx<T> line[n];
-#pragma unroll
-      for (int k = 0; k < n; ++k) line[k] = {T(0), T(0)};
-      const int bz = zr / NG, kz = zr % NG;
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int yr = y0 + half;
-        const int by = yr / NG, jy = yr % NG;
-#pragma unroll
-        for (int bx = 0; bx < 6; ++bx) {
-          const int s = bx + 6 * (by + 6 * bz);
-          const int src = s_src[s];
-          T v[NG];
-#pragma unroll
-          for (int i = 0; i < NG; ++i) v[i] = T(0);
-          if (src >= 0) {
-            const T* gsrc = a.gridlet + size_t(src) * M + (kz * NG + jy) * NG;
-#pragma unroll
-            for (int i = 0; i < NG; ++i) v[i] = gsrc[i];
-          } else if (src == -2) {
-            const int qx = 2 * ((tx >> 1) - 1) + bx, qy = 2 * ((ty >> 1) - 1) + by,
-                      qz = 2 * ((tz >> 1) - 1) + bz;
-            const T ccx = T(a.lo0 + (qx + 0.5) * L), ccy = T(a.lo1 + (qy + 0.5) * L),
-                    ccz = T(a.lo2 + (qz + 0.5) * L);
-            const T invL = T(1.0 / L);
-            for (int p = s_vb[s]; p < s_ve[s]; ++p) {
-              T lx[NG], ly[NG], lz[NG];
-              lagrange_basis<NG>((a.xs[p] - ccx) * invL, lx);
-              lagrange_basis<NG>((a.ys[p] - ccy) * invL, ly);
-              lagrange_basis<NG>((a.zs[p] - ccz) * invL, lz);
-              T wyz = a.ms[p];
-#pragma unroll
-              for (int q = 0; q < NG; ++q) wyz = (q == jy) ? wyz * ly[q] : wyz;
-              T wz = T(0);
-#pragma unroll
-              for (int q = 0; q < NG; ++q) wz = (q == kz) ? lz[q] : wz;
-              wyz *= wz;
-#pragma unroll
-              for (int i = 0; i < NG; ++i) v[i] += wyz * lx[i];
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < NG; ++i) {
-            if (half == 0) line[bx * NG + i].re = v[i];
-            else line[bx * NG + i].im = v[i];
-          }
-        }
-      }
-      cplx<T> zf[n];
-      fft<n, -1>(line, zf);
+      cplx<T> A[H], B[H];
+      xpass_rows<T, NG>(a, y0, zr, s_src, A, B);
       cplx<T>* row0 = stage + (size_t(zr) * n + y0) * H;
       cplx<T>* row1 = row0 + H;
 #pragma unroll
       for (int k = 0; k < H; ++k) {
-        const cplx<T> z1 = zf[k], z2 = zf[(n - k) % n];
-        row0[k] = {T(0.5) * (z1.re + z2.re), T(0.5) * (z1.im - z2.im)};
-        row1[k] = {T(0.5) * (z1.im + z2.im), T(0.5) * (z2.re - z1.re)};
+        row0[k] = A[k];
+        row1[k] = B[k];
       }
     }
     __syncthreads();
@@ -277,13 +272,218 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// z-slab variant: the same convolution, streamed over the source z rows.
+//
+// The source grid is taken ZB z-rows (one "slab") at a time. Each slab is transformed along x
+// (two real rows per complex FFT, half spectrum kx <= n/2) and along y (all n values of ky) in
+// LDS. Along z the convolution is written out in real space: for the N_g target z values Z and
+// a source row z, the kernel is the Green function transformed along x and y only, at the
+// offset |Z - z| < 4 N_g (no wrap-around), so
+//     P(Z, ky, kx) = sum_z Gxy(|Z - z|, ky, kx) S(z, ky, kx)
+// accumulates in registers, one (ky, kx) entry per thread slot, slab by slab. Once every slab
+// is in, the N_g planes P(Z) go through the inverse y transform (N_g target y values kept) and
+// the Hermitian inverse x transform (N_g target x values kept). Nothing but the source gridlets
+// and the N_g^3 outputs crosses the memory hierarchy, and the forward z transform, the Green
+// multiply and the inverse z transform of the full-grid kernel are replaced by N_g x 6 N_g
+// real multiply-adds per (ky, kx) entry.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int NG>
+struct SlabShape {
+  static constexpr int n = 8 * NG, H = n / 2 + 1, W = 6 * NG, M = NG * NG * NG;
+  static constexpr int NT = 512;            // threads per workgroup
+  static constexpr int ZB = NG;             // source z rows per slab (one block layer)
+  static constexpr int D = 4 * NG;          // z offsets |Z - z| < 4 N_g
+  static constexpr int ENT = n * H;         // (ky, kx) entries of a plane
+  static constexpr int PER = (ENT + NT - 1) / NT;
+  static constexpr int NJ = NG + ZB - 1;    // distinct offsets Z - z within one slab
+  static constexpr size_t slab_bytes = size_t(ZB) * n * H * sizeof(cplx<T>);
+  static constexpr size_t green_bytes = size_t(D) * H * H * sizeof(T);
+  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<T>);
+  static constexpr bool green_lds = slab_bytes + red_bytes + green_bytes <= 150 * 1024;
+  static constexpr bool fits = slab_bytes + red_bytes <= 150 * 1024;
+};
+
+template <typename T, int NG>
+__global__ __launch_bounds__(512) void k_m2l_slab(M2LArgs<T> a) {
+  using S = SlabShape<T, NG>;
+  constexpr int n = S::n, H = S::H, W = S::W, M = S::M, NT = S::NT, ZB = S::ZB, D = S::D,
+                PER = S::PER, NJ = S::NJ, ENT = S::ENT;
+  static_assert(S::fits, "slab buffers exceed the LDS budget");
+  static_assert(W % ZB == 0 && W % 2 == 0, "slab shape");
+  __shared__ int s_src[216];
+  __shared__ int s_off[kMaxLevels + 1];
+  __shared__ cplx<T> slab[ZB * n * H];       // [zb][ky (y before the y pass)][kx]
+  __shared__ cplx<T> red[NG * NG * H];       // after y^-1: [Z][Y][kx]
+  __shared__ T s_green[S::green_lds ? D * H * H : 1];  // [d][ky folded][kx]
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  int green_level = -1;
+
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, jb = blockIdx.x >> 3;
+  const int t_begin = int((int64_t(a.ntargets) * xcd) / 8);
+  const int t_end = int((int64_t(a.ntargets) * (xcd + 1)) / 8);
+
+  for (int ti = t_begin + jb; ti < t_end; ti += per) {
+    __syncthreads();
+    const TargetGeom t = target_geom(a.first_target + ti, s_off, a.nlevels, a.coord, a.parent, a.size);
+    if (tid < 216) s_src[tid] = resolve_slot(a, t, tid);
+    const T* gtab_g = a.gxy + size_t(t.l - 2) * D * H * H;
+    if constexpr (S::green_lds) {
+      if (t.l != green_level) {  // block-uniform: every thread sees the same target
+        for (int e = tid; e < D * H * H; e += NT) s_green[e] = gtab_g[e];
+        green_level = t.l;
+      }
+    }
+    __syncthreads();
+    const T* gtab = S::green_lds ? s_green : gtab_g;
+    const int Zt = (2 + t.cz) * NG;
+
+    T pr[PER][NG], pi[PER][NG];
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+#pragma unroll
+      for (int zz = 0; zz < NG; ++zz) pr[r][zz] = pi[r][zz] = T(0);
+
+    for (int z0 = 0; z0 < W; z0 += ZB) {
+      // x: rows (zb, y) of the slab, y fastest, two rows per line
+      for (int w = tid; w < ZB * W / 2; w += NT) {
+        const int r0 = 2 * w, zb = r0 / W, y0 = r0 % W;
+        cplx<T> A[H], B[H];
+        xpass_rows<T, NG>(a, y0, z0 + zb, s_src, A, B);
+        cplx<T>* row = slab + (size_t(zb) * n + y0) * H;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+          row[k] = A[k];
+          row[H + k] = B[k];
+        }
+      }
+      __syncthreads();
+      // y: columns (zb, kx); rows y >= 6 N_g are zero
+      for (int w = tid; w < ZB * H; w += NT) {
+        const int kx = w % H, zb = w / H;
+        cplx<T>* col = slab + size_t(zb) * n * H + kx;
+        cplx<T> in[n], out[n];
+#pragma unroll
+        for (int y = 0; y < n; ++y) in[y] = (y < W) ? col[size_t(y) * H] : cplx<T>{T(0), T(0)};
+        fft<n, -1>(in, out);
+#pragma unroll
+        for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
+      }
+      __syncthreads();
+      // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int e = tid + NT * r;
+        if (e < ENT) {
+          const int ky = e / H, kx = e % H;
+          const int kyf = ky <= n / 2 ? ky : n - ky;
+          T g[NJ];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int d = Zt - z0 + j - (ZB - 1);
+            g[j] = gtab[(size_t(d < 0 ? -d : d) * H + kyf) * H + kx];
+          }
+          cplx<T> sv[ZB];
+#pragma unroll
+          for (int zb = 0; zb < ZB; ++zb) sv[zb] = slab[(size_t(zb) * n + ky) * H + kx];
+#pragma unroll
+          for (int zz = 0; zz < NG; ++zz) {
+            T re[ZB], im[ZB];
+#pragma unroll
+            for (int zb = 0; zb < ZB; ++zb) {
+              const T gv = g[zz - zb + ZB - 1];
+              re[zb] = gv * sv[zb].re;
+              im[zb] = gv * sv[zb].im;
+            }
+            pr[r][zz] += tree_sum<0, ZB>(re);
+            pi[r][zz] += tree_sum<0, ZB>(im);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // y^-1 of the N_g planes, ZB planes at a time through the slab buffer
+#pragma unroll
+    for (int c0 = 0; c0 < NG; c0 += ZB) {
+      constexpr int CZ = ZB < NG ? ZB : NG;
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int e = tid + NT * r;
+        if (e < ENT) {
+#pragma unroll
+          for (int zc = 0; zc < CZ; ++zc)
+            if (c0 + zc < NG) slab[size_t(zc) * ENT + e] = {pr[r][c0 + zc], pi[r][c0 + zc]};
+        }
+      }
+      __syncthreads();
+      for (int w = tid; w < CZ * H; w += NT) {
+        const int kx = w % H, zc = w / H;
+        if (c0 + zc < NG) {
+          const cplx<T>* col = slab + size_t(zc) * ENT + kx;
+          cplx<T> in[n], out[n];
+#pragma unroll
+          for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
+          fft<n, +1>(in, out);
+#pragma unroll
+          for (int yy = 0; yy < NG; ++yy)
+            red[(size_t(c0 + zc) * NG + yy) * H + kx] = t.cy ? out[3 * NG + yy] : out[2 * NG + yy];
+        }
+      }
+      __syncthreads();
+    }
+
+    // x^-1: rows (Z, Y), two Hermitian half spectra per complex line, N_g target x values kept
+    for (int w = tid; w < (NG * NG + 1) / 2; w += NT) {
+      const int r0 = 2 * w, r1 = 2 * w + 1;
+      const bool has1 = r1 < NG * NG;
+      const cplx<T>* A = red + size_t(r0) * H;
+      const cplx<T>* B = red + size_t(has1 ? r1 : r0) * H;
+      cplx<T> zf[n], zo[n];
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        cplx<T> av = A[k], bv = has1 ? B[k] : cplx<T>{T(0), T(0)};
+        if (k == 0 || k == n / 2) {
+          av.im = T(0);
+          bv.im = T(0);
+        }
+        zf[k] = {av.re - bv.im, av.im + bv.re};
+        if (k > 0 && k < n / 2) zf[n - k] = {av.re + bv.im, bv.re - av.im};
+      }
+      fft<n, +1>(zf, zo);
+      T* out0 = a.local + size_t(t.g) * M + r0 * NG;
+#pragma unroll
+      for (int xx = 0; xx < NG; ++xx) out0[xx] = t.cx ? zo[3 * NG + xx].re : zo[2 * NG + xx].re;
+      if (has1) {
+        T* out1 = a.local + size_t(t.g) * M + r1 * NG;
+#pragma unroll
+        for (int xx = 0; xx < NG; ++xx) out1[xx] = t.cx ? zo[3 * NG + xx].im : zo[2 * NG + xx].im;
+      }
+    }
+  }
+}
+
+// Which kernel serves (T, N_g): the whole stage in LDS when it fits; else the z-slab kernel in
+// FP32; else the full-grid kernel with a global stage slice per workgroup.
+template <typename T, int NG>
+constexpr int m2l_kind() {
+  if constexpr (M2LShape<T, NG>::lds) return 0;
+  else if constexpr (sizeof(T) == 4 && SlabShape<T, NG>::fits) return 1;
+  else return 2;
+}
+
+// resident workgroups of the z-slab kernel: one per CU (its LDS use allows no second)
+constexpr int kSlabGrid = 256;
+
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot) {
   size_t b = 0;
-  bool lds = true;
+  int kind = 0;
 #define HPM_SHAPE(TT, NN)                      \
   if (ng == NN) {                              \
     b = M2LShape<TT, NN>::bytes;               \
-    lds = M2LShape<TT, NN>::lds;               \
+    kind = m2l_kind<TT, NN>();                 \
   }
   if (prec == HPM_F32) {
     HPM_SHAPE(float, 2) HPM_SHAPE(float, 3) HPM_SHAPE(float, 4) HPM_SHAPE(float, 6) HPM_SHAPE(float, 8)
@@ -291,8 +491,15 @@ int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot) {
     HPM_SHAPE(double, 2) HPM_SHAPE(double, 3) HPM_SHAPE(double, 4) HPM_SHAPE(double, 6) HPM_SHAPE(double, 8)
   }
 #undef HPM_SHAPE
-  *bytes_per_slot = lds ? 0 : b;
-  if (lds) return 8 * 256;
+  if (kind == 0) {
+    *bytes_per_slot = 0;
+    return 8 * 256;
+  }
+  if (kind == 1) {
+    *bytes_per_slot = 0;
+    return kSlabGrid;
+  }
+  *bytes_per_slot = b;
   return b > (size_t(1) << 20) ? 1024 : 2048;
 }
 
@@ -311,24 +518,22 @@ static void m2l_t(Plan& p, hipStream_t s) {
   a.flags = p.cflags.as<int>();
   a.child8 = p.child8.as<int>();
   a.nbr27 = p.nbr27.as<int>();
-  a.pb = p.cpb.as<int>();
-  a.pe = p.cpe.as<int>();
-  a.keys = p.keys.as<uint32_t>();
-  a.xs = p.xs.as<T>();
-  a.ys = p.ys.as<T>();
-  a.zs = p.zs.as<T>();
-  a.ms = p.ms.as<T>();
+  a.vkeys = p.vkeys.as<uint32_t>();
+  a.nvirt = int(p.nvirt);
+  a.ncells = int(p.ncells);
   a.gridlet = p.gridlet.as<T>();
   a.local = p.local.as<T>();
   a.ghat = p.tab.ghat.as<T>();
+  a.gxy = p.tab.gxy.as<T>();
   a.work = p.m2l_work.as<cplx<T>>();
   a.lo0 = p.prob.box_lo[0];
   a.lo1 = p.prob.box_lo[1];
   a.lo2 = p.prob.box_lo[2];
   a.size = p.prob.box_size;
   int grid = ((a.ntargets + 7) / 8) * 8;
-  if (grid > p.m2l_slots) grid = p.m2l_slots;
-  k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
+  if (grid > p.m2l_slots) grid = p.m2l_slots;  // the global stage holds m2l_slots slices
+  if constexpr (m2l_kind<T, NG>() == 1) k_m2l_slab<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
+  else k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 

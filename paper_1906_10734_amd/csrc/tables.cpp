@@ -15,7 +15,10 @@
 //                g(r) = -G (r^2+eps^2)^{-1/2}; for eps = 0 the origin takes the value at unit
 //                offset. G is real and even along each axis, so its DFT is real, even and a
 //                product of cosine sums; only the octant k in [0, n/2]^3 is stored, divided by
-//                n^3 (the normalisation of the unnormalised inverse FFT).
+//                n^3 (the normalisation of the unnormalised inverse FFT). The same function
+//                transformed along x and y only, at the z offsets 0 .. 4 N_g - 1 that separate a
+//                target node from a source node, and divided by n^2, serves the variant of the
+//                source-to-target step that convolves along z in real space.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -115,6 +118,8 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
   const int n = 8 * ng, H = n / 2 + 1;
   const int nlev = std::max(0, max_levels - 2);
   std::vector<double> ghat(size_t(std::max(nlev, 1)) * H * H * H, 0.0);
+  const int D = 4 * ng;
+  std::vector<double> gxy(size_t(std::max(nlev, 1)) * D * H * H, 0.0);
   std::vector<double> cs(size_t(H) * n);
   for (int k = 0; k < H; ++k)
     for (int d = 0; d < n; ++d)
@@ -156,6 +161,9 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
           for (int y = 0; y < n; ++y) acc += a1[(size_t(z) * n + y) * H + kx] * cs[size_t(ky) * n + y];
           a2[(size_t(z) * H + ky) * H + kx] = acc;
         }
+    // x, y only: gxy[d][ky][kx] = a2[d][ky][kx] / n^2, d < 4 N_g
+    const double inv_n2 = 1.0 / (double(n) * n);
+    for (size_t e = 0; e < size_t(D) * H * H; ++e) gxy[size_t(li) * D * H * H + e] = a2[e] * inv_n2;
     // z: ghat[kz][ky][kx] / n^3
     const double inv_n3 = 1.0 / (double(n) * n * n);
     double* out = &ghat[size_t(li) * H * H * H];
@@ -172,10 +180,12 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
     upload<float>(p.tab.fitw, w, s);
     upload<float>(p.tab.m2m, t1, s);
     upload<float>(p.tab.ghat, ghat, s);
+    upload<float>(p.tab.gxy, gxy, s);
   } else {
     upload<double>(p.tab.fitw, w, s);
     upload<double>(p.tab.m2m, t1, s);
     upload<double>(p.tab.ghat, ghat, s);
+    upload<double>(p.tab.gxy, gxy, s);
   }
 }
 

@@ -16,6 +16,7 @@
 
 #include "dev_common.h"
 #include "hpm_internal.h"
+#include "zones.h"
 
 namespace hpm {
 
@@ -221,31 +222,41 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_scatter(const uint32_t* ki
   }
 }
 
-static void radix_sort_pairs(Plan& p, int nbits, hipStream_t s) {
-  const int n = int(p.n);
+// Sorts n (key, value) pairs held in (ka, va); (kb, vb) is scratch of the same size. The result
+// ends in (ka, va).
+static void radix_sort(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int nbits,
+                       DevBuf& hist_buf, DevBuf& scan_tmp, hipStream_t s) {
+  if (n <= 0) return;
   const int nblocks = (n + kRsTile - 1) / kRsTile;
-  p.hist.reserve(size_t(256) * nblocks * sizeof(int) * 2);
-  int* hist = p.hist.as<int>();
+  hist_buf.reserve(size_t(256) * nblocks * sizeof(int) * 2);
+  int* hist = hist_buf.as<int>();
   int* offs = hist + 256 * nblocks;
-  uint32_t* ka = p.tmp_keys.as<uint32_t>();
-  int* va = p.tmp_vals.as<int>();
-  uint32_t* kb = p.keys.as<uint32_t>();
-  int* vb = p.perm.as<int>();
   const int passes = (nbits + 7) / 8;
+  uint32_t* k0 = ka;
+  int* v0 = va;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
     k_radix_hist<<<nblocks, kRsThreads, 0, s>>>(ka, n, shift, hist, nblocks);
     HPM_LAUNCH_CHECK();
-    exclusive_scan_i32(hist, offs, 256 * nblocks, nullptr, p.scan_tmp, s);
+    exclusive_scan_i32(hist, offs, 256 * nblocks, nullptr, scan_tmp, s);
     k_radix_scatter<<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, offs, nblocks);
     HPM_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (ka != p.keys.as<uint32_t>()) {
-    HPM_HIP(hipMemcpyAsync(p.keys.p, ka, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
-    HPM_HIP(hipMemcpyAsync(p.perm.p, va, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  if (ka != k0) {
+    HPM_HIP(hipMemcpyAsync(k0, ka, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    HPM_HIP(hipMemcpyAsync(v0, va, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   }
+}
+
+// particle keys: sorted from (tmp_keys, tmp_vals) into (keys, perm)
+static void radix_sort_pairs(Plan& p, int nbits, hipStream_t s) {
+  const int n = int(p.n);
+  radix_sort(p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(), p.keys.as<uint32_t>(),
+             p.perm.as<int>(), n, nbits, p.hist, p.scan_tmp, s);
+  HPM_HIP(hipMemcpyAsync(p.keys.p, p.tmp_keys.p, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  HPM_HIP(hipMemcpyAsync(p.perm.p, p.tmp_vals.p, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
 }
 
 template <typename T>
@@ -518,6 +529,175 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   k_leaf_compact<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.childoff.as<int>(),
                                                p.leaves.as<int>());
   HPM_LAUNCH_CHECK();
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// Virtual cubes: interaction-zone cube positions that are not cells of the tree but hold
+// particles of a coarser leaf. Each is listed once (sorted by cube id) and appended to the cell
+// arrays at ids ncells + v with its coordinates and particle range, so that its effective
+// masses are fitted once per solve like a leaf's and the source-to-target kernels read them
+// like any gridlet.
+// ---------------------------------------------------------------------------------------------
+struct VirtArgs {
+  int first_target;
+  int depth;
+  int nlevels;
+  const int* level_off;
+  const int* coord;
+  const int* parent;
+  const int* flags;
+  const int* child8;
+  const int* nbr27;
+  const int* pb;
+  const int* pe;
+  const uint32_t* keys;  // sorted particle keys at depth D
+  int* counts;           // [targets] (count pass)
+  const int* offs;       // [targets] (emit pass)
+  uint32_t* ids;         // emitted cube ids (emit pass)
+};
+
+// one workgroup per target, one thread per block slot: the slot's cube id if it is a nonempty
+// virtual cube
+template <bool EMIT>
+__global__ __launch_bounds__(256) void k_virt_slots(VirtArgs a) {
+  __shared__ int s_off[kMaxLevels + 1];
+  __shared__ int s_flag[256];
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  __syncthreads();
+  const int g = a.first_target + blockIdx.x;
+  const int l = level_of(g, s_off, a.nlevels);
+  const int pc = a.coord[g];
+  uint32_t id = 0;
+  int flag = 0;
+  if (tid < 216) {
+    const IzSlot z = iz_slot(coord_x(pc), coord_y(pc), coord_z(pc), l, a.parent[g], tid, a.nbr27,
+                             a.flags, a.child8);
+    if (z.coarse >= 0) {
+      const int shift = 3 * (a.depth - l);
+      const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
+      const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
+      const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
+      if (ve > vb) {
+        flag = 1;
+        id = cube_id(l, z.key);
+      }
+    }
+  }
+  s_flag[tid] = flag;
+  __syncthreads();
+  // inclusive scan of the 256 flags (Hillis-Steele)
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = tid >= o ? s_flag[tid - o] : 0;
+    __syncthreads();
+    s_flag[tid] += v;
+    __syncthreads();
+  }
+  if (!EMIT) {
+    if (tid == 255) a.counts[blockIdx.x] = s_flag[255];
+  } else if (flag) {
+    a.ids[a.offs[blockIdx.x] + s_flag[tid] - 1] = id;
+  }
+}
+
+__global__ void k_unique_flags(int n, const uint32_t* ids, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = (i == 0 || ids[i] != ids[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_unique_emit(int n, const uint32_t* ids, const int* flags, const int* pos,
+                              uint32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flags[i]) out[pos[i]] = ids[i];
+}
+
+// coordinates, particle range and level of virtual cube v, stored at cell id ncells + v
+__global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, const uint32_t* keys,
+                             int ncells, int* coord, int* pb, int* pe, int* vlevel, int* vlist) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const uint32_t id = vids[v];
+  const int l = cube_id_level(id);
+  const uint32_t key = id ^ (1u << (3 * l));
+  int x = 0, y = 0, z = 0;
+  for (int b = 0; b < l; ++b) {
+    x |= int((key >> (3 * b)) & 1u) << b;
+    y |= int((key >> (3 * b + 1)) & 1u) << b;
+    z |= int((key >> (3 * b + 2)) & 1u) << b;
+  }
+  const int shift = 3 * (depth - l);
+  const int b0 = lower_bound_u32(keys, 0, n, key << shift);
+  const int e0 = lower_bound_u32(keys, b0, n, (key + 1u) << shift);
+  coord[ncells + v] = pack_coord(x, y, z);
+  pb[ncells + v] = b0;
+  pe[ncells + v] = e0;
+  vlevel[v] = l;
+  vlist[v] = ncells + v;
+}
+
+void build_virtual(Plan& p, hipStream_t s) {
+  p.nvirt = 0;
+  if (p.nlevels <= 2) return;
+  const int first = p.level_off[2];
+  const int nt = int(p.ncells) - first;
+  if (nt <= 0) return;
+  VirtArgs a;
+  a.first_target = first;
+  a.depth = p.depth;
+  a.nlevels = p.nlevels;
+  a.level_off = p.dlevel.as<int>();
+  a.coord = p.ccoord.as<int>();
+  a.parent = p.cparent.as<int>();
+  a.flags = p.cflags.as<int>();
+  a.child8 = p.child8.as<int>();
+  a.nbr27 = p.nbr27.as<int>();
+  a.pb = p.cpb.as<int>();
+  a.pe = p.cpe.as<int>();
+  a.keys = p.keys.as<uint32_t>();
+  p.nchild.reserve(size_t(nt) * 4);
+  p.childoff.reserve(size_t(nt) * 4);
+  a.counts = p.nchild.as<int>();
+  a.offs = p.childoff.as<int>();
+  a.ids = nullptr;
+  k_virt_slots<false><<<nt, 256, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+  int* d_total = p.err.as<int>() + 1;
+  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
+  int refs = 0;
+  HPM_HIP(hipMemcpyAsync(&refs, d_total, 4, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+  if (refs <= 0) return;
+  p.vids.reserve(size_t(refs) * 4);
+  p.vtmp.reserve(size_t(refs) * 4 * 4);  // sort scratch (keys, values, values) and flags/pos
+  a.ids = p.vids.as<uint32_t>();
+  k_virt_slots<true><<<nt, 256, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+  uint32_t* kb = p.vtmp.as<uint32_t>();
+  int* va = p.vtmp.as<int>() + refs;
+  int* vb = p.vtmp.as<int>() + 2 * size_t(refs);
+  HPM_HIP(hipMemsetAsync(va, 0, size_t(refs) * 4, s));
+  radix_sort(p.vids.as<uint32_t>(), va, kb, vb, refs, 31, p.hist, p.scan_tmp, s);
+  // unique ids: flags in va, positions in vb, compacted into kb
+  k_unique_flags<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va);
+  HPM_LAUNCH_CHECK();
+  exclusive_scan_i32(va, vb, refs, d_total, p.scan_tmp, s);
+  int nv = 0;
+  HPM_HIP(hipMemcpyAsync(&nv, d_total, 4, hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+  p.vkeys.reserve(size_t(std::max(nv, 1)) * 4);
+  k_unique_emit<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va, vb,
+                                                p.vkeys.as<uint32_t>());
+  HPM_LAUNCH_CHECK();
+  ensure_cells(p, p.ncells + nv, p.ncells, s);
+  p.vlevel.reserve(size_t(std::max(nv, 1)) * 4);
+  p.vlist.reserve(size_t(std::max(nv, 1)) * 4);
+  k_virt_cells<<<nblk(nv, 256), 256, 0, s>>>(nv, p.vkeys.as<uint32_t>(), p.depth, int(p.n),
+                                              p.keys.as<uint32_t>(), int(p.ncells),
+                                              p.ccoord.as<int>(), p.cpb.as<int>(), p.cpe.as<int>(),
+                                              p.vlevel.as<int>(), p.vlist.as<int>());
+  HPM_LAUNCH_CHECK();
+  p.nvirt = nv;
 }
 
 }  // namespace hpm

@@ -28,6 +28,7 @@ __global__ void k_gather_masses(int n, const int* perm, const T* m, T* ms) {
 template <typename T>
 struct P2MArgs {
   const int* leaves;
+  const int* row_level;  // level of each row, or null: taken from the cell id
   int first;  // index of the first level>=2 leaf in the leaf list
   int count;
   const int* level_off;
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
   __syncthreads();
   const int b = blockIdx.x;
   const int g = a.leaves[a.first + b];
-  const int l = level_of(g, s_off, a.nlevels);
+  const int l = a.row_level ? a.row_level[b] : level_of(g, s_off, a.nlevels);
   const double L = a.size / double(1 << l);
   const int pc = a.coord[g];
   const T cx = T(a.lo0 + (coord_x(pc) + 0.5) * L);
@@ -220,13 +221,15 @@ void launch_gather_masses(Plan& p, const void* m, hipStream_t s) {
   HPM_LAUNCH_CHECK();
 }
 
+// moments and fit of `rows` cells listed in list[first ..]; levels from row_level or the ids
 template <typename T, int NG>
-static void p2m_t(Plan& p, hipStream_t s) {
-  const int rows = int(p.nleaves - p.nleaves_lt2);
+static void p2m_rows(Plan& p, const int* list, int first, int rows, const int* row_level,
+                     hipStream_t s) {
   if (rows <= 0) return;
   P2MArgs<T> a;
-  a.leaves = p.leaves.as<int>();
-  a.first = int(p.nleaves_lt2);
+  a.leaves = list;
+  a.row_level = row_level;
+  a.first = first;
   a.count = rows;
   a.level_off = p.dlevel.as<int>();
   a.nlevels = p.nlevels;
@@ -246,10 +249,17 @@ static void p2m_t(Plan& p, hipStream_t s) {
   k_p2m_moments<T, NG><<<rows, 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
   dim3 grid(nblk(rows, 16), nblk(p.tab.mpad, 64));
-  k_fit_gemm<T><<<grid, 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(),
-                                     p.leaves.as<int>(), int(p.nleaves_lt2), rows, NG * NG * NG,
-                                     p.tab.kpad, p.tab.mpad);
+  k_fit_gemm<T><<<grid, 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(), list,
+                                     first, rows, NG * NG * NG, p.tab.kpad, p.tab.mpad);
   HPM_LAUNCH_CHECK();
+}
+
+// leaves at levels >= 2, then the virtual cubes (the moments buffer is reused in stream order)
+template <typename T, int NG>
+static void p2m_t(Plan& p, hipStream_t s) {
+  p2m_rows<T, NG>(p, p.leaves.as<int>(), int(p.nleaves_lt2), int(p.nleaves - p.nleaves_lt2),
+                  nullptr, s);
+  p2m_rows<T, NG>(p, p.vlist.as<int>(), 0, int(p.nvirt), p.vlevel.as<int>(), s);
 }
 
 template <typename T, int NG>
