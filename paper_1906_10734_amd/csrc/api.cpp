@@ -73,6 +73,7 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   const size_t rows = size_t(std::max<int64_t>({p.nleaves - p.nleaves_lt2, p.nvirt, 1}));
   p.moments.reserve(rows * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
+  p.m2l_mean.reserve(cells * sizeof(double));
   build_near_lists(p, s);
   if (p.timing) {
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));

@@ -34,11 +34,14 @@ __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
 // Completes the local potential of the cells of one level after source-to-target:
 //   v_q = dPhi^C_q (the source-to-target result) + sum_p dPhi^P_p l_p((a^C + x_q)/2)
 // (the parent's part, the transpose of the separable child-to-parent matrix; absent at level 2),
-// then dPhi^C = v - mean(v) and c^C = c^P + mean(v). One workgroup per cell.
+// then dPhi^C = v - mean(v) and c^C = c^P + mean(v) (+ the mean of the source-to-target result
+// when that kernel delivers it apart from a zero-mean gridlet; the constant is then summed in
+// double). One workgroup per cell.
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int* __restrict__ parent,
                                              const int* __restrict__ coord, const T* __restrict__ t1,
-                                             T* __restrict__ local, T* __restrict__ lofs) {
+                                             T* __restrict__ local, T* __restrict__ lofs,
+                                             const double* __restrict__ m2l_mean) {
   constexpr int M = NG * NG * NG;
   constexpr int PER = (M + 255) / 256;
   __shared__ T s_in[M], s_a[M], s_b[M];
@@ -100,7 +103,13 @@ __global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int*
     if (e < M) local[size_t(g) * M + e] = w[r] - mean;
   }
   if (tid == 0) {
-    if (has_parent) {
+    if (m2l_mean) {
+      double c = m2l_mean[g] + double(mean);
+      if (has_parent) c += double(lofs[2 * P]) + double(lofs[2 * P + 1]);
+      const T hi = T(c);
+      lofs[2 * g] = hi;
+      lofs[2 * g + 1] = T(c - double(hi));
+    } else if (has_parent) {
       T s, err;
       two_sum(lofs[2 * P], mean, s, err);
       lofs[2 * g] = s;
@@ -516,7 +525,8 @@ static void l2l_t(Plan& p, int level, hipStream_t s) {
   const int cnt = p.level_off[level + 1] - off;
   if (cnt <= 0) return;
   k_l2l<T, NG><<<cnt, 256, 0, s>>>(off, level >= 3 ? 1 : 0, p.cparent.as<int>(), p.ccoord.as<int>(),
-                                   p.tab.m2m.as<T>(), p.local.as<T>(), p.lofs.as<T>());
+                                   p.tab.m2m.as<T>(), p.local.as<T>(), p.lofs.as<T>(),
+                                   p.m2l_split ? p.m2l_mean.as<double>() : nullptr);
   HPM_LAUNCH_CHECK();
 }
 

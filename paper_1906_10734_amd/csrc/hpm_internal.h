@@ -109,6 +109,8 @@ struct Plan {
   // gridlets
   DevBuf gridlet, local, moments;
   DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
+  DevBuf m2l_mean;          // [cells] double: mean of the source-to-target result, when split
+  bool m2l_split = false;   // the source-to-target kernel writes (mean, zero-mean gridlet)
   // near-zone lists and the P2P work items (see downsweep.hip)
   DevBuf near_rb, near_re, item_cnt, item_off, items, partial, pairs;
   int64_t n_items = 0;

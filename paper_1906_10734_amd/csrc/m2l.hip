@@ -58,6 +58,7 @@ struct M2LArgs {
   int ncells;
   const T* gridlet;
   T* local;
+  double* m2l_mean;  // z-slab kernel: mean of each target's result (the gridlet part is zero-mean)
   const T* ghat;
   const T* gxy;
   cplx<T>* work;
@@ -300,7 +301,8 @@ struct SlabShape {
   static constexpr int NJ = NG + ZB - 1;    // distinct offsets Z - z within one slab
   static constexpr size_t slab_bytes = size_t(ZB) * n * H * sizeof(cplx<T>);
   static constexpr size_t green_bytes = size_t(D) * H * H * sizeof(T);
-  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<T>);
+  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<double>) + size_t(M) * 8 +
+                                      size_t(n) * sizeof(cplx<double>);
   static constexpr bool green_lds = slab_bytes + red_bytes + green_bytes <= 150 * 1024;
   static constexpr bool fits = slab_bytes + red_bytes <= 150 * 1024;
 };
@@ -314,11 +316,19 @@ __global__ __launch_bounds__(512) void k_m2l_slab(M2LArgs<T> a) {
   static_assert(W % ZB == 0 && W % 2 == 0, "slab shape");
   __shared__ int s_src[216];
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ cplx<T> slab[ZB * n * H];       // [zb][ky (y before the y pass)][kx]
-  __shared__ cplx<T> red[NG * NG * H];       // after y^-1: [Z][Y][kx]
+  __shared__ __align__(16) cplx<T> slab[ZB * n * H];  // [zb][ky (y before the y pass)][kx]
+  __shared__ cplx<double> red[NG * NG * H];            // after y^-1: [Z][Y][kx]
+  __shared__ double s_out[M];
+  __shared__ double s_red[NT / 64];
+  __shared__ cplx<double> s_tw[n];  // e^{+2 pi i m / n}
   __shared__ T s_green[S::green_lds ? D * H * H : 1];  // [d][ky folded][kx]
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  for (int m = tid; m < n; m += NT) {
+    double sv, cv;
+    sincospi(2.0 * m / n, &sv, &cv);
+    s_tw[m] = {cv, sv};
+  }
   int green_level = -1;
 
   const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, jb = blockIdx.x >> 3;
@@ -405,63 +415,72 @@ __global__ __launch_bounds__(512) void k_m2l_slab(M2LArgs<T> a) {
       __syncthreads();
     }
 
-    // y^-1 of the N_g planes, ZB planes at a time through the slab buffer
+    // The inverse transforms run in double precision on the accumulated FP32 planes: their
+    // rounding, relative to the large smooth potential of the interaction zone, would otherwise
+    // dominate the error of the potential's variation across the target. Only N_g outputs per
+    // axis are wanted, so both are direct sums (N_g of n terms per line) against a double
+    // twiddle table.
+    static_assert(ZB >= NG, "the slab buffer holds the N_g accumulated planes");
 #pragma unroll
-    for (int c0 = 0; c0 < NG; c0 += ZB) {
-      constexpr int CZ = ZB < NG ? ZB : NG;
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + NT * r;
+      if (e < ENT) {
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int e = tid + NT * r;
-        if (e < ENT) {
-#pragma unroll
-          for (int zc = 0; zc < CZ; ++zc)
-            if (c0 + zc < NG) slab[size_t(zc) * ENT + e] = {pr[r][c0 + zc], pi[r][c0 + zc]};
-        }
+        for (int zz = 0; zz < NG; ++zz) slab[size_t(zz) * ENT + e] = {pr[r][zz], pi[r][zz]};
       }
-      __syncthreads();
-      for (int w = tid; w < CZ * H; w += NT) {
-        const int kx = w % H, zc = w / H;
-        if (c0 + zc < NG) {
-          const cplx<T>* col = slab + size_t(zc) * ENT + kx;
-          cplx<T> in[n], out[n];
-#pragma unroll
-          for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
-          fft<n, +1>(in, out);
-#pragma unroll
-          for (int yy = 0; yy < NG; ++yy)
-            red[(size_t(c0 + zc) * NG + yy) * H + kx] = t.cy ? out[3 * NG + yy] : out[2 * NG + yy];
-        }
-      }
-      __syncthreads();
     }
-
-    // x^-1: rows (Z, Y), two Hermitian half spectra per complex line, N_g target x values kept
-    for (int w = tid; w < (NG * NG + 1) / 2; w += NT) {
-      const int r0 = 2 * w, r1 = 2 * w + 1;
-      const bool has1 = r1 < NG * NG;
-      const cplx<T>* A = red + size_t(r0) * H;
-      const cplx<T>* B = red + size_t(has1 ? r1 : r0) * H;
-      cplx<T> zf[n], zo[n];
-#pragma unroll
+    __syncthreads();
+    // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n}, Y = (2 + c_y) N_g + yy
+    const int Yt = (2 + t.cy) * NG;
+    for (int u = tid; u < NG * NG * H; u += NT) {
+      const int kx = u % H, yy = (u / H) % NG, zz = u / (H * NG);
+      const int Y = Yt + yy;
+      const cplx<T>* col = slab + size_t(zz) * ENT + kx;
+      double ar = 0.0, ai = 0.0;
+      int m = 0;
+      for (int ky = 0; ky < n; ++ky) {
+        const cplx<T> f = col[size_t(ky) * H];
+        const cplx<double> w = s_tw[m];
+        ar += double(f.re) * w.re - double(f.im) * w.im;
+        ai += double(f.re) * w.im + double(f.im) * w.re;
+        m += Y;
+        if (m >= n) m -= n;
+      }
+      red[(size_t(zz) * NG + yy) * H + kx] = {ar, ai};
+    }
+    __syncthreads();
+    // x^-1 (Hermitian half spectrum): out = sum_k w_k Re(F_k e^{+2 pi i k X / n}), w_k = 1 at
+    // k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g + xx
+    const int Xt = (2 + t.cx) * NG;
+    for (int q = tid; q < M; q += NT) {
+      const int xx = q % NG, row = q / NG;
+      const int X = Xt + xx;
+      const cplx<double>* F = red + size_t(row) * H;
+      double acc = 0.0;
+      int m = 0;
       for (int k = 0; k < H; ++k) {
-        cplx<T> av = A[k], bv = has1 ? B[k] : cplx<T>{T(0), T(0)};
-        if (k == 0 || k == n / 2) {
-          av.im = T(0);
-          bv.im = T(0);
-        }
-        zf[k] = {av.re - bv.im, av.im + bv.re};
-        if (k > 0 && k < n / 2) zf[n - k] = {av.re + bv.im, bv.re - av.im};
+        const cplx<double> f = F[k];
+        const cplx<double> w = s_tw[m];
+        const double v = f.re * w.re - f.im * w.im;
+        acc += (k == 0 || k == n / 2) ? v : 2.0 * v;
+        m += X;
+        if (m >= n) m -= n;
       }
-      fft<n, +1>(zf, zo);
-      T* out0 = a.local + size_t(t.g) * M + r0 * NG;
-#pragma unroll
-      for (int xx = 0; xx < NG; ++xx) out0[xx] = t.cx ? zo[3 * NG + xx].re : zo[2 * NG + xx].re;
-      if (has1) {
-        T* out1 = a.local + size_t(t.g) * M + r1 * NG;
-#pragma unroll
-        for (int xx = 0; xx < NG; ++xx) out1[xx] = t.cx ? zo[3 * NG + xx].im : zo[2 * NG + xx].im;
-      }
+      s_out[q] = acc;
     }
+    __syncthreads();
+    // result = mean (double, per target) + zero-mean gridlet (T)
+    double part = 0.0;
+    for (int e = tid; e < M; e += NT) part += s_out[e];
+    part = wave_sum(part);
+    if ((tid & 63) == 0) s_red[tid >> 6] = part;
+    __syncthreads();
+    double mean = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) mean += s_red[w];
+    mean *= 1.0 / M;
+    for (int e = tid; e < M; e += NT) a.local[size_t(t.g) * M + e] = T(s_out[e] - mean);
+    if (tid == 0) a.m2l_mean[t.g] = mean;
   }
 }
 
@@ -523,6 +542,7 @@ static void m2l_t(Plan& p, hipStream_t s) {
   a.ncells = int(p.ncells);
   a.gridlet = p.gridlet.as<T>();
   a.local = p.local.as<T>();
+  a.m2l_mean = p.m2l_mean.as<double>();
   a.ghat = p.tab.ghat.as<T>();
   a.gxy = p.tab.gxy.as<T>();
   a.work = p.m2l_work.as<cplx<T>>();
@@ -532,6 +552,7 @@ static void m2l_t(Plan& p, hipStream_t s) {
   a.size = p.prob.box_size;
   int grid = ((a.ntargets + 7) / 8) * 8;
   if (grid > p.m2l_slots) grid = p.m2l_slots;  // the global stage holds m2l_slots slices
+  p.m2l_split = m2l_kind<T, NG>() == 1;
   if constexpr (m2l_kind<T, NG>() == 1) k_m2l_slab<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
   else k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();

@@ -302,29 +302,39 @@ __global__ void k_root(int n, CellArrays c) {
   }
 }
 
-// Split decision and the 9 boundaries of the child ranges of each cell of level l.
+// Split decision and the 9 boundaries of the child ranges of each cell of level l: eight lanes
+// per cell, lane k finds the first particle of child octant k by binary search in the cell's
+// (key-sorted) range.
 __global__ void k_level_split(int l, int depth, int uniform, int cap, int off, int cnt,
                               const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  const int g = off + i;
-  const int pb = c.pb[g], pe = c.pe[g];
-  const bool split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
-  c.flags[g] = split ? 1 : 0;
-  if (!split) {
-    nchild[i] = 0;
-    return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t >> 3, k = t & 7;
+  const bool live = i < cnt;
+  int b = 0, nonempty = 0;
+  bool split = false;
+  int pe = 0;
+  if (live) {
+    const int g = off + i;
+    const int pb = c.pb[g];
+    pe = c.pe[g];
+    split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
+    if (k == 0) c.flags[g] = split ? 1 : 0;
+    if (split) {
+      const int shift = 3 * (depth - l - 1);
+      const uint32_t base = c.key[g] << 3;
+      b = (k == 0) ? pb : lower_bound_u32(keys, pb, pe, (base + uint32_t(k)) << shift);
+      bounds[i * 9 + k] = b;
+      if (k == 7) bounds[i * 9 + 8] = pe;
+    }
   }
-  const int shift = 3 * (depth - l - 1);
-  const uint32_t base = c.key[g] << 3;
-  int b[9];
-  b[0] = pb;
-  b[8] = pe;
-  for (int k = 1; k < 8; ++k) b[k] = lower_bound_u32(keys, b[k - 1], pe, (base + k) << shift);
-  int nc = 0;
-  for (int k = 0; k < 9; ++k) bounds[i * 9 + k] = b[k];
-  for (int k = 0; k < 8; ++k) nc += (b[k + 1] > b[k]);
-  nchild[i] = nc;
+  // child k is nonempty if the next boundary is past this one (lanes k+1 of the same cell)
+  const int next = __shfl_down(b, 1, 8);
+  if (live && split) nonempty = ((k == 7) ? pe : next) > b ? 1 : 0;
+  int nc = nonempty;
+  nc += __shfl_xor(nc, 1, 8);
+  nc += __shfl_xor(nc, 2, 8);
+  nc += __shfl_xor(nc, 4, 8);
+  if (live && k == 0) nchild[i] = split ? nc : 0;
 }
 
 __global__ void k_level_emit(int off, int cnt, int off_next, const int* bounds,
@@ -352,32 +362,31 @@ __global__ void k_level_emit(int off, int cnt, int off_next, const int* bounds,
   }
 }
 
-// 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood.
+// 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
+// thread per (cell, neighbour) entry.
 __global__ void k_level_nbr(int l, int off, int cnt, CellArrays c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / 27, j = t % 27;
   if (i >= cnt) return;
+  const int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
   const int g = off + i;
   const int pc = c.coord[g];
   const int x = coord_x(pc), y = coord_y(pc), z = coord_z(pc);
   const int par = c.parent[g];
   const int side = 1 << l;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int qx = x + dx, qy = y + dy, qz = z + dz;
-        int v = -1;
-        if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
-          const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
-          const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
-          if (e >= 0) {
-            if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
-            else v = -2 - e;
-          } else {
-            v = e;
-          }
-        }
-        c.nbr27[g * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] = v;
-      }
+  const int qx = x + dx, qy = y + dy, qz = z + dz;
+  int v = -1;
+  if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
+    const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
+    const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+    if (e >= 0) {
+      if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
+      else v = -2 - e;
+    } else {
+      v = e;
+    }
+  }
+  c.nbr27[g * 27 + j] = v;
 }
 
 __global__ void k_leaf_flags(int ncells, const int* flags, int* isleaf) {
@@ -484,7 +493,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     p.bounds.reserve(size_t(cnt) * 9 * 4);
     p.nchild.reserve(size_t(cnt) * 4);
     p.childoff.reserve(size_t(cnt) * 4);
-    k_level_split<<<nblk(cnt, 128), 128, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, off,
+    k_level_split<<<nblk(int64_t(cnt) * 8, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, off,
                                                  cnt, p.keys.as<uint32_t>(), cells_of(p),
                                                  p.bounds.as<int>(), p.nchild.as<int>());
     HPM_LAUNCH_CHECK();
@@ -502,7 +511,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     p.nlevels = l + 2;
     off = off_next;
     cnt = total;
-    k_level_nbr<<<nblk(cnt, 128), 128, 0, s>>>(l + 1, off, cnt, cells_of(p));
+    k_level_nbr<<<nblk(int64_t(cnt) * 27, 256), 256, 0, s>>>(l + 1, off, cnt, cells_of(p));
     HPM_LAUNCH_CHECK();
   }
   p.ncells = off + cnt;

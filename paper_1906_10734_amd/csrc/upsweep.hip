@@ -114,10 +114,11 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
 // Operand layout of v_mfma_*_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. The
 // output rows differ by dtype (measured on gfx950): accumulator register v of lane l holds
 // D[4*(l/16)+v][l%16] for the f32 instruction and D[4*v+l/16][l%16] for the f64 one.
-template <typename T>
+template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const T* __restrict__ W,
                                                   T* __restrict__ gridlet, const int* __restrict__ leaves,
-                                                  int first, int rows, int M, int kpad, int mpad) {
+                                                  int first, int rows) {
+  constexpr int M = NG * NG * NG, kpad = (M + 3) / 4 * 4, mpad = (M + 15) / 16 * 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row0 = blockIdx.x * 16;
   const int col0 = (blockIdx.y * 4 + wave) * 16;
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
   const bool arow_ok = arow < rows;
   if constexpr (sizeof(T) == 4) {
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
     for (int k0 = 0; k0 < kpad; k0 += 4) {
       const float av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : 0.f;
       const float bv = W[size_t(k0 + kk) * mpad + col0 + i];
@@ -139,6 +141,7 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
     }
   } else {
     doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
     for (int k0 = 0; k0 < kpad; k0 += 4) {
       const double av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : 0.0;
       const double bv = W[size_t(k0 + kk) * mpad + col0 + i];
@@ -249,8 +252,8 @@ static void p2m_rows(Plan& p, const int* list, int first, int rows, const int* r
   k_p2m_moments<T, NG><<<rows, 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
   dim3 grid(nblk(rows, 16), nblk(p.tab.mpad, 64));
-  k_fit_gemm<T><<<grid, 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(), list,
-                                     first, rows, NG * NG * NG, p.tab.kpad, p.tab.mpad);
+  k_fit_gemm<T, NG><<<grid, 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(),
+                                         list, first, rows);
   HPM_LAUNCH_CHECK();
 }
 
