@@ -95,6 +95,9 @@ static void create_plan(const hpm_problem* pr, int64_t n, const void* x, const v
   p.ng = pr->ng;
   p.M = pr->ng * pr->ng * pr->ng;
   p.elem = (p.prec == HPM_F32) ? 4 : 8;
+  HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  HPM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&p.dbox), p.hbox, 0));
   const int depth = pr->uniform_depth > 0 ? pr->uniform_depth : pr->max_depth;
   build_tables(p, depth + 1, s);
   size_t slot_bytes = 0;
@@ -140,6 +143,7 @@ static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, 
 }
 
 Plan::~Plan() {
+  if (hbox) (void)hipHostFree(hbox);
   if (events_created) {
     for (auto& set : ev)
       for (auto& e : set)
@@ -272,7 +276,12 @@ hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info) {
     info->n_targets = p.nlevels > 2 ? p.ncells - p.level_off[2] : 0;
     for (int l = 0; l < kMaxLevelsHost; ++l)
       info->cells_per_level[l] = (l < p.nlevels) ? p.level_off[l + 1] - p.level_off[l] : 0;
-    info->p2p_pairs = p.p2p_pairs;
+    long long pairs = 0;
+    if (p.pairs.p) {  // counted on the device by the near-list build
+      HPM_HIP(hipDeviceSynchronize());
+      HPM_HIP(hipMemcpy(&pairs, p.pairs.p, sizeof(pairs), hipMemcpyDeviceToHost));
+    }
+    info->p2p_pairs = pairs;
   });
 }
 

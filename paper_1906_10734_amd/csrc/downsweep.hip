@@ -223,15 +223,12 @@ void build_near_lists(Plan& p, hipStream_t s) {
   HPM_LAUNCH_CHECK();
   k_near_items<<<nblk(nl, 256), 256, 0, s>>>(a, p.pairs.as<long long>());
   HPM_LAUNCH_CHECK();
-  int* d_total = p.err.as<int>() + 2;
-  exclusive_scan_i32(p.item_cnt.as<int>(), p.item_off.as<int>(), nl, d_total, p.scan_tmp, s);
-  int total = 0;
-  long long pairs = 0;
-  HPM_HIP(hipMemcpyAsync(&total, d_total, 4, hipMemcpyDeviceToHost, s));
-  HPM_HIP(hipMemcpyAsync(&pairs, p.pairs.p, 8, hipMemcpyDeviceToHost, s));
+  exclusive_scan_i32(p.item_cnt.as<int>(), p.item_off.as<int>(), nl, p.dbox + Plan::kBoxTotal,
+                     p.scan_tmp, s);
   HPM_HIP(hipStreamSynchronize(s));
+  const int total = p.hbox[Plan::kBoxTotal];
   p.n_items = total;
-  p.p2p_pairs = pairs;
+  p.p2p_pairs = -1;  // read from the device on request
   p.items.reserve(size_t(std::max(total, 1)) * sizeof(int4));
   p.partial.reserve(size_t(std::max(total, 1)) * 64 * 5 * p.elem);
   k_fill_items<<<nblk(nl, 256), 256, 0, s>>>(nl, p.item_off.as<int>(), p.cpb.as<int>(),

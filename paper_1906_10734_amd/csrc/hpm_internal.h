@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hpm.h"
@@ -65,6 +66,10 @@ struct DevBuf {
   }
   template <typename U>
   U* as() const { return static_cast<U*>(p); }
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
 };
 
 // Constant tables of one (precision, N_g, softening, box, levels) combination, in device memory.
@@ -119,7 +124,13 @@ struct Plan {
   int m2l_slots = 0;
   Tables tab;
   // scratch for the tree build
-  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff, err;
+  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff;
+  // pinned, device-mapped words that kernels write and the host reads after a stream
+  // synchronisation (counts that size the next step of the build, input error flags)
+  static constexpr int kBoxWords = 16;
+  static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
+  int* hbox = nullptr;
+  int* dbox = nullptr;
 
   // stage timing with HIP events (off unless enabled): a ring of pending executions
   static constexpr int kStages = 5;   // P2M, M2M, M2L, L2L, leaves

@@ -290,11 +290,16 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
 // multiply and the inverse z transform of the full-grid kernel are replaced by N_g x 6 N_g
 // real multiply-adds per (ky, kx) entry.
 // ---------------------------------------------------------------------------------------------
+constexpr int kSlabThreads = 256;      // threads per workgroup
+constexpr int kSlabLayers = 1;         // block layers (N_g source z rows each) per slab
+constexpr bool kSlabGreenLds = false;  // Green table of the level in LDS (else read through L2)
+constexpr int kSlabPerCU = 2;          // resident workgroups per CU
+
 template <typename T, int NG>
 struct SlabShape {
   static constexpr int n = 8 * NG, H = n / 2 + 1, W = 6 * NG, M = NG * NG * NG;
-  static constexpr int NT = 512;            // threads per workgroup
-  static constexpr int ZB = NG;             // source z rows per slab (one block layer)
+  static constexpr int NT = kSlabThreads;
+  static constexpr int ZB = kSlabLayers * NG;  // source z rows per slab
   static constexpr int D = 4 * NG;          // z offsets |Z - z| < 4 N_g
   static constexpr int ENT = n * H;         // (ky, kx) entries of a plane
   static constexpr int PER = (ENT + NT - 1) / NT;
@@ -303,12 +308,13 @@ struct SlabShape {
   static constexpr size_t green_bytes = size_t(D) * H * H * sizeof(T);
   static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<double>) + size_t(M) * 8 +
                                       size_t(n) * sizeof(cplx<double>);
-  static constexpr bool green_lds = slab_bytes + red_bytes + green_bytes <= 150 * 1024;
+  static constexpr bool green_lds =
+      kSlabGreenLds && slab_bytes + red_bytes + green_bytes <= 150 * 1024;
   static constexpr bool fits = slab_bytes + red_bytes <= 150 * 1024;
 };
 
 template <typename T, int NG>
-__global__ __launch_bounds__(512) void k_m2l_slab(M2LArgs<T> a) {
+__global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   using S = SlabShape<T, NG>;
   constexpr int n = S::n, H = S::H, W = S::W, M = S::M, NT = S::NT, ZB = S::ZB, D = S::D,
                 PER = S::PER, NJ = S::NJ, ENT = S::ENT;
@@ -493,8 +499,8 @@ constexpr int m2l_kind() {
   else return 2;
 }
 
-// resident workgroups of the z-slab kernel: one per CU (its LDS use allows no second)
-constexpr int kSlabGrid = 256;
+// resident workgroups of the z-slab kernel on 256 CUs
+constexpr int kSlabGrid = 256 * kSlabPerCU;
 
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot) {
   size_t b = 0;

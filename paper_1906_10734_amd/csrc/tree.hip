@@ -81,6 +81,53 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* 
   if (total_out && threadIdx.x == 0) *total_out = (block_off ? block_off[blockIdx.x] : 0) + total;
 }
 
+// One workgroup scans up to kScanSingleMax values in chunks of 1024 x 8 with a running offset
+// (one launch instead of three for the medium sizes of the tree build).
+constexpr int kScanSingleThreads = 1024;
+constexpr int kScanSingleMax = kScanSingleThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* in, int* out, int n,
+                                                                    int* total_out) {
+  __shared__ int s_wave[kScanSingleThreads / 64];
+  __shared__ int s_run;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_run = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += kScanSingleThreads * kScanItems) {
+    const int base = c0 + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = (base + k < n) ? in[base + k] : 0;
+      sum += v[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int pre = s_run, all = 0;
+    for (int w = 0; w < kScanSingleThreads / 64; ++w) {
+      if (w < wave) pre += s_wave[w];
+      all += s_wave[w];
+    }
+    int run = pre + x - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    __syncthreads();  // every thread has read s_run and s_wave
+    if (threadIdx.x == 0) s_run += all;
+    __syncthreads();
+  }
+  if (total_out && threadIdx.x == 0) *total_out = s_run;
+}
+
 static size_t scan_tmp_ints(int n) {
   size_t t = 0;
   while (n > kScanTile) {
@@ -94,6 +141,11 @@ static void scan_rec(const int* in, int* out, int n, int* total, int* tmp, hipSt
   const int nb = (n + kScanTile - 1) / kScanTile;
   if (nb <= 1) {
     k_scan_tile<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total);
+    HPM_LAUNCH_CHECK();
+    return;
+  }
+  if (n <= kScanSingleMax) {
+    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, n, total);
     HPM_LAUNCH_CHECK();
     return;
   }
@@ -121,7 +173,7 @@ void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp,
 template <typename T>
 __global__ void k_keys(int n, const T* x, const T* y, const T* z, double lo0, double lo1,
                        double lo2, double hi0, double hi1, double hi2, double scale, int depth,
-                       uint32_t* keys, int* vals, int* err) {
+                       uint32_t* keys, int* vals, int* box) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double px = double(x[i]), py = double(y[i]), pz = double(z[i]);
@@ -130,7 +182,7 @@ __global__ void k_keys(int n, const T* x, const T* y, const T* z, double lo0, do
   if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad = 2;
   else if (!(px >= lo0 && px <= hi0 && py >= lo1 && py <= hi1 && pz >= lo2 && pz <= hi2)) bad = 1;
   if (bad) {
-    atomicOr(err, bad);
+    box[bad == 2 ? Plan::kBoxNonfinite : Plan::kBoxOutOfBox] = 1;
     keys[i] = 0;
     vals[i] = i;
     return;
@@ -250,13 +302,14 @@ static void radix_sort(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int 
   }
 }
 
-// particle keys: sorted from (tmp_keys, tmp_vals) into (keys, perm)
+// particle keys: sorted from (tmp_keys, tmp_vals) into (keys, perm); the sorted buffers are
+// swapped in rather than copied
 static void radix_sort_pairs(Plan& p, int nbits, hipStream_t s) {
   const int n = int(p.n);
   radix_sort(p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(), p.keys.as<uint32_t>(),
              p.perm.as<int>(), n, nbits, p.hist, p.scan_tmp, s);
-  HPM_HIP(hipMemcpyAsync(p.keys.p, p.tmp_keys.p, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
-  HPM_HIP(hipMemcpyAsync(p.perm.p, p.tmp_vals.p, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  p.keys.swap(p.tmp_keys);
+  p.perm.swap(p.tmp_vals);
 }
 
 template <typename T>
@@ -394,8 +447,11 @@ __global__ void k_leaf_flags(int ncells, const int* flags, int* isleaf) {
   if (i < ncells) isleaf[i] = (flags[i] & 1) ? 0 : 1;
 }
 
-__global__ void k_leaf_compact(int ncells, const int* flags, const int* pos, int* leaves) {
+// leaf list; the cell with id first2 (the first of level 2) reports how many leaves precede it
+__global__ void k_leaf_compact(int ncells, const int* flags, const int* pos, int* leaves,
+                               int first2, int* lt2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncells && i == first2) *lt2 = pos[i];
   if (i < ncells && !(flags[i] & 1)) leaves[pos[i]] = i;
 }
 
@@ -426,8 +482,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   p.perm.reserve(size_t(n) * 4);
   p.tmp_keys.reserve(size_t(n) * 4);
   p.tmp_vals.reserve(size_t(n) * 4);
-  p.err.reserve(16);
-  HPM_HIP(hipMemsetAsync(p.err.p, 0, 4, s));
+  p.hbox[Plan::kBoxOutOfBox] = 0;
+  p.hbox[Plan::kBoxNonfinite] = 0;
 
   const double scale = double(1 << D) / pr.box_size;
   const double hi0 = pr.box_lo[0] + pr.box_size, hi1 = pr.box_lo[1] + pr.box_size,
@@ -437,20 +493,18 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
                                                (const float*)z, pr.box_lo[0], pr.box_lo[1],
                                                pr.box_lo[2], hi0, hi1, hi2, scale, D,
                                                p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
-                                               p.err.as<int>());
+                                               p.dbox);
   } else {
     k_keys<double><<<nblk(n, 256), 256, 0, s>>>(n, (const double*)x, (const double*)y,
                                                 (const double*)z, pr.box_lo[0], pr.box_lo[1],
                                                 pr.box_lo[2], hi0, hi1, hi2, scale, D,
                                                 p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
-                                                p.err.as<int>());
+                                                p.dbox);
   }
   HPM_LAUNCH_CHECK();
-  int herr = 0;
-  HPM_HIP(hipMemcpyAsync(&herr, p.err.p, 4, hipMemcpyDeviceToHost, s));
   HPM_HIP(hipStreamSynchronize(s));
-  if (herr & 2) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
-  if (herr & 1) fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
+  if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
+  if (p.hbox[Plan::kBoxOutOfBox]) fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
 
   radix_sort_pairs(p, 3 * D, s);
 
@@ -488,7 +542,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   int off = 0, cnt = 1;
   p.level_off[0] = 0;
   p.nlevels = 1;
-  int* d_total = p.err.as<int>() + 1;
+  int* d_total = p.dbox + Plan::kBoxTotal;
   for (int l = 0; l <= D; ++l) {
     p.bounds.reserve(size_t(cnt) * 9 * 4);
     p.nchild.reserve(size_t(cnt) * 4);
@@ -498,9 +552,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
                                                  p.bounds.as<int>(), p.nchild.as<int>());
     HPM_LAUNCH_CHECK();
     exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), cnt, d_total, p.scan_tmp, s);
-    int total = 0;
-    HPM_HIP(hipMemcpyAsync(&total, d_total, 4, hipMemcpyDeviceToHost, s));
     HPM_HIP(hipStreamSynchronize(s));
+    const int total = p.hbox[Plan::kBoxTotal];
     const int off_next = off + cnt;
     ensure_cells(p, int64_t(off_next) + total, off_next, s);
     k_level_emit<<<nblk(cnt, 128), 128, 0, s>>>(off, cnt, off_next, p.bounds.as<int>(),
@@ -526,18 +579,16 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   k_leaf_flags<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.nchild.as<int>());
   HPM_LAUNCH_CHECK();
   exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nc, d_total, p.scan_tmp, s);
-  int nleaves = 0, lt2 = 0;
-  HPM_HIP(hipMemcpyAsync(&nleaves, d_total, 4, hipMemcpyDeviceToHost, s));
-  if (p.nlevels > 2)
-    HPM_HIP(hipMemcpyAsync(&lt2, p.childoff.as<int>() + p.level_off[2], 4, hipMemcpyDeviceToHost, s));
-  HPM_HIP(hipStreamSynchronize(s));
-  if (p.nlevels <= 2) lt2 = nleaves;
-  p.nleaves = nleaves;
-  p.nleaves_lt2 = lt2;
-  p.leaves.reserve(size_t(std::max(nleaves, 1)) * 4);
+  p.leaves.reserve(size_t(nc) * 4);  // at most one leaf per cell
+  const int first2 = p.nlevels > 2 ? p.level_off[2] : -1;
   k_leaf_compact<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.childoff.as<int>(),
-                                               p.leaves.as<int>());
+                                               p.leaves.as<int>(), first2,
+                                               p.dbox + Plan::kBoxLeavesLt2);
   HPM_LAUNCH_CHECK();
+  HPM_HIP(hipStreamSynchronize(s));
+  const int nleaves = p.hbox[Plan::kBoxTotal];
+  p.nleaves = nleaves;
+  p.nleaves_lt2 = (p.nlevels > 2) ? p.hbox[Plan::kBoxLeavesLt2] : nleaves;
 }
 
 
@@ -566,8 +617,10 @@ struct VirtArgs {
   uint32_t* ids;         // emitted cube ids (emit pass)
 };
 
-// one workgroup per target, one thread per block slot: the slot's cube id if it is a nonempty
-// virtual cube
+// One workgroup per cell of levels 1 .. L-2 (the possible parents of targets), one thread per
+// slot of its 6^3 block: the cube id if the slot is a nonempty virtual cube that lies in the
+// interaction zone of some child (every block cube except the 8 children's own positions). The
+// 8 siblings share the block, so each parent lists it once.
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_virt_slots(VirtArgs a) {
   __shared__ int s_off[kMaxLevels + 1];
@@ -575,14 +628,16 @@ __global__ __launch_bounds__(256) void k_virt_slots(VirtArgs a) {
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
   __syncthreads();
-  const int g = a.first_target + blockIdx.x;
-  const int l = level_of(g, s_off, a.nlevels);
-  const int pc = a.coord[g];
+  const int par = a.first_target + blockIdx.x;
+  const int l = level_of(par, s_off, a.nlevels) + 1;  // level of the block's cubes
   uint32_t id = 0;
   int flag = 0;
-  if (tid < 216) {
-    const IzSlot z = iz_slot(coord_x(pc), coord_y(pc), coord_z(pc), l, a.parent[g], tid, a.nbr27,
-                             a.flags, a.child8);
+  const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
+  const bool centre = bx >= 2 && bx <= 3 && by >= 2 && by <= 3 && bz >= 2 && bz <= 3;
+  if (tid < 216 && !centre && (a.flags[par] & 1)) {
+    const int pc = a.coord[par];
+    const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27,
+                                a.flags, a.child8);
     if (z.coarse >= 0) {
       const int shift = 3 * (a.depth - l);
       const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
@@ -648,8 +703,9 @@ __global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, con
 void build_virtual(Plan& p, hipStream_t s) {
   p.nvirt = 0;
   if (p.nlevels <= 2) return;
-  const int first = p.level_off[2];
-  const int nt = int(p.ncells) - first;
+  // parents of targets: cells of levels 1 .. nlevels-2
+  const int first = p.level_off[1];
+  const int nt = p.level_off[p.nlevels - 1] - first;
   if (nt <= 0) return;
   VirtArgs a;
   a.first_target = first;
@@ -671,11 +727,10 @@ void build_virtual(Plan& p, hipStream_t s) {
   a.ids = nullptr;
   k_virt_slots<false><<<nt, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
-  int* d_total = p.err.as<int>() + 1;
+  int* d_total = p.dbox + Plan::kBoxTotal;
   exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
-  int refs = 0;
-  HPM_HIP(hipMemcpyAsync(&refs, d_total, 4, hipMemcpyDeviceToHost, s));
   HPM_HIP(hipStreamSynchronize(s));
+  const int refs = p.hbox[Plan::kBoxTotal];
   if (refs <= 0) return;
   p.vids.reserve(size_t(refs) * 4);
   p.vtmp.reserve(size_t(refs) * 4 * 4);  // sort scratch (keys, values, values) and flags/pos
@@ -685,15 +740,13 @@ void build_virtual(Plan& p, hipStream_t s) {
   uint32_t* kb = p.vtmp.as<uint32_t>();
   int* va = p.vtmp.as<int>() + refs;
   int* vb = p.vtmp.as<int>() + 2 * size_t(refs);
-  HPM_HIP(hipMemsetAsync(va, 0, size_t(refs) * 4, s));
   radix_sort(p.vids.as<uint32_t>(), va, kb, vb, refs, 31, p.hist, p.scan_tmp, s);
   // unique ids: flags in va, positions in vb, compacted into kb
   k_unique_flags<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va);
   HPM_LAUNCH_CHECK();
   exclusive_scan_i32(va, vb, refs, d_total, p.scan_tmp, s);
-  int nv = 0;
-  HPM_HIP(hipMemcpyAsync(&nv, d_total, 4, hipMemcpyDeviceToHost, s));
   HPM_HIP(hipStreamSynchronize(s));
+  const int nv = p.hbox[Plan::kBoxTotal];
   p.vkeys.reserve(size_t(std::max(nv, 1)) * 4);
   k_unique_emit<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va, vb,
                                                 p.vkeys.as<uint32_t>());

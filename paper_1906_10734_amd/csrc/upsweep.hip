@@ -9,6 +9,8 @@
 // workgroup per parent, three LDS passes per child.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dev_common.h"
 #include "hpm_internal.h"
 
@@ -110,7 +112,9 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
   for (int nidx = lane + 64 * PER; nidx < a.kpad; nidx += 64) a.moments[size_t(b) * a.kpad + nidx] = T(0);
 }
 
-// gridlet[leaf][p] = sum_n Q[row][n] W[n][p]; each wave one 16x16 output tile, K in steps of 4.
+// gridlet[leaf][p] = sum_n Q[row][n] W[n][p] on the matrix cores, K in steps of 4. A workgroup
+// takes 32 rows; each wave one 16-row tile and half of the 16-column tiles, so the A fragment it
+// loads per K step feeds several independent accumulators.
 // Operand layout of v_mfma_*_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. The
 // output rows differ by dtype (measured on gfx950): accumulator register v of lane l holds
 // D[4*(l/16)+v][l%16] for the f32 instruction and D[4*v+l/16][l%16] for the f64 one.
@@ -119,43 +123,44 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
                                                   T* __restrict__ gridlet, const int* __restrict__ leaves,
                                                   int first, int rows) {
   constexpr int M = NG * NG * NG, kpad = (M + 3) / 4 * 4, mpad = (M + 15) / 16 * 16;
+  constexpr int CT = mpad / 16;       // column tiles
+  constexpr int CH = (CT + 1) / 2;    // column tiles per wave
+  using V4 = typename std::conditional<sizeof(T) == 4, floatx4, doublex4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row0 = blockIdx.x * 16;
-  const int col0 = (blockIdx.y * 4 + wave) * 16;
-  if (col0 >= mpad) return;
+  const int row0 = blockIdx.x * 32 + (wave & 1) * 16;
+  const int c0 = (wave >> 1) * CH;
   const int i = lane & 15, kk = lane >> 4;
   const int arow = row0 + i;
   const bool arow_ok = arow < rows;
-  if constexpr (sizeof(T) == 4) {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-    for (int k0 = 0; k0 < kpad; k0 += 4) {
-      const float av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : 0.f;
-      const float bv = W[size_t(k0 + kk) * mpad + col0 + i];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-    }
+  V4 acc[CH];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * kk + v, c = col0 + i;
-      if (r < rows && c < M) gridlet[size_t(leaves[first + r]) * M + c] = acc[v];
-    }
-  } else {
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int k0 = 0; k0 < kpad; k0 += 4) {
-      const double av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : 0.0;
-      const double bv = W[size_t(k0 + kk) * mpad + col0 + i];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
+  for (int t = 0; t < CH; ++t) acc[t] = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll 2
+  for (int k0 = 0; k0 < kpad; k0 += 4) {
+    const T av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : T(0);
+    const T* wrow = W + size_t(k0 + kk) * mpad + i;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * v + kk, c = col0 + i;
-      if (r < rows && c < M) gridlet[size_t(leaves[first + r]) * M + c] = acc[v];
+    for (int t = 0; t < CH; ++t) {
+      if (c0 + t < CT) {
+        const T bv = wrow[(c0 + t) * 16];
+        if constexpr (sizeof(T) == 4) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < CH; ++t) {
+    const int c = (c0 + t) * 16 + i;
+    if (c0 + t < CT && c < M) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + (sizeof(T) == 4 ? 4 * kk + v : 4 * v + kk);
+        if (r < rows) gridlet[size_t(leaves[first + r]) * M + c] = acc[t][v];
+      }
     }
   }
 }
 
-// M^P = sum over present children C of T^C M^C (Sec. 2.3), separable.
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_m2m(int off, const int* __restrict__ flags,
                                              const int* __restrict__ child8, const T* __restrict__ t1,
@@ -251,8 +256,7 @@ static void p2m_rows(Plan& p, const int* list, int first, int rows, const int* r
   a.size = p.prob.box_size;
   k_p2m_moments<T, NG><<<rows, 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
-  dim3 grid(nblk(rows, 16), nblk(p.tab.mpad, 64));
-  k_fit_gemm<T, NG><<<grid, 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(),
+  k_fit_gemm<T, NG><<<nblk(rows, 32), 256, 0, s>>>(p.moments.as<T>(), p.tab.fitw.as<T>(), p.gridlet.as<T>(),
                                          list, first, rows);
   HPM_LAUNCH_CHECK();
 }

@@ -22,16 +22,14 @@ struct IzSlot {
   uint32_t key;  // Morton key of the cube at level l (valid when coarse >= 0)
 };
 
-// Slot "slot" (< 216, x fastest) of the block of target (tx, ty, tz) at level l with parent par.
-// nbr27[par] encodes the 27 level-(l-1) positions around the parent: >= 0 a real cell, -1 empty,
-// <= -2 inside the coarser leaf -2 - e. flags bit 0 marks a cell with children.
-__device__ __forceinline__ IzSlot iz_slot(int tx, int ty, int tz, int l, int par, int slot,
-                                          const int* nbr27, const int* flags, const int* child8) {
+// Cube "slot" (< 216, x fastest) of the 6^3 block around parent P = (px, py, pz) at level l - 1
+// (cell id par): the level-l position 2 (P - 1) + b. nbr27[par] encodes the 27 level-(l-1)
+// positions around the parent: >= 0 a real cell, -1 empty, <= -2 inside the coarser leaf
+// -2 - e. flags bit 0 marks a cell with children.
+__device__ __forceinline__ IzSlot block_cube(int px, int py, int pz, int l, int par, int slot,
+                                             const int* nbr27, const int* flags, const int* child8) {
   IzSlot r{-1, -1, 0u};
   const int bx = slot % 6, by = (slot / 6) % 6, bz = slot / 36;
-  const int cx = tx & 1, cy = ty & 1, cz = tz & 1;
-  const bool near = abs(bx - 2 - cx) <= 1 && abs(by - 2 - cy) <= 1 && abs(bz - 2 - cz) <= 1;
-  if (near) return r;
   const int e = nbr27[par * 27 + (bx >> 1) + 3 * (by >> 1) + 9 * (bz >> 1)];
   const int oct = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
   int coarse = -1;
@@ -42,12 +40,22 @@ __device__ __forceinline__ IzSlot iz_slot(int tx, int ty, int tz, int l, int par
     coarse = -2 - e;
   }
   if (coarse >= 0) {
-    const int qx = 2 * ((tx >> 1) - 1) + bx, qy = 2 * ((ty >> 1) - 1) + by,
-              qz = 2 * ((tz >> 1) - 1) + bz;
+    const int qx = 2 * (px - 1) + bx, qy = 2 * (py - 1) + by, qz = 2 * (pz - 1) + bz;
     r.coarse = coarse;
     r.key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
   }
   return r;
+}
+
+// Interaction-zone slot of target (tx, ty, tz) at level l with parent par: its parent's block
+// cube, unless the cube is one of the 27 around the target.
+__device__ __forceinline__ IzSlot iz_slot(int tx, int ty, int tz, int l, int par, int slot,
+                                          const int* nbr27, const int* flags, const int* child8) {
+  const int bx = slot % 6, by = (slot / 6) % 6, bz = slot / 36;
+  const int cx = tx & 1, cy = ty & 1, cz = tz & 1;
+  const bool near = abs(bx - 2 - cx) <= 1 && abs(by - 2 - cy) <= 1 && abs(bz - 2 - cz) <= 1;
+  if (near) return IzSlot{-1, -1, 0u};
+  return block_cube(tx >> 1, ty >> 1, tz >> 1, l, par, slot, nbr27, flags, child8);
 }
 
 // A cube's identifier across levels: its level-l Morton key below a leading 1 bit at 3 l
