@@ -263,13 +263,19 @@ __device__ __forceinline__ T inv_sqrt(T x) {
   else return 1.0 / sqrt(x);
 }
 
+template <typename T>
+struct alignas(4 * sizeof(T)) SrcP {
+  T x, y, z, m;
+};
+
 // Lanes split as (target tl < kp, source group grp < 64/kp) when the chunk has fewer than 64
-// targets; sources are staged 64 at a time in LDS and the groups are combined with shuffles.
+// targets; sources are staged 64 at a time in LDS (position and mass in one 4-vector) and the
+// groups are combined with shuffles. The self pair is recognised by its place in the source
+// sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
-  __shared__ T s_x[64], s_y[64], s_z[64], s_m[64];
-  __shared__ int s_id[64];
+  __shared__ SrcP<T> s_src[64];
   const int lane = threadIdx.x;
   const int4 it = a.items[blockIdx.x];
   const int li = it.x, t0 = it.y, s0 = it.z, S = it.w;
@@ -294,6 +300,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   const int tl = lane % kp, grp = lane / kp;
   const int i = pb + t0 + tl;
   const bool valid = tl < K;
+  const int self = s_pre[13] + (i - s_rb[13]);  // the target's own place in the source sequence
   T xi = T(0), yi = T(0), zi = T(0);
   if (valid) {
     xi = a.xs[i];
@@ -313,20 +320,17 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         else hi = mid;
       }
       const int j = s_rb[lo] + (sidx - s_pre[lo]);
-      s_x[lane] = a.xs[j];
-      s_y[lane] = a.ys[j];
-      s_z[lane] = a.zs[j];
-      s_m[lane] = a.ms[j];
-      s_id[lane] = j;
+      s_src[lane] = SrcP<T>{a.xs[j], a.ys[j], a.zs[j], a.ms[j]};
     }
     __syncthreads();
     const int cnt = min(64, s_end - tile);
     if (valid) {
       for (int e = grp; e < cnt; e += G) {
-        const T dx = xi - s_x[e], dy = yi - s_y[e], dz = zi - s_z[e];
+        const SrcP<T> q = s_src[e];
+        const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
-        const T inv = (s_id[e] == i) ? T(0) : inv_sqrt(r2);
-        const T mi = s_m[e] * inv;
+        const T inv = (tile + e == self) ? T(0) : inv_sqrt(r2);
+        const T mi = q.m * inv;
         const T mi3 = mi * inv * inv;
         const T yv = -mi - phc;  // Kahan: ph += -m/r
         const T tv = ph + yv;

@@ -112,9 +112,11 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
   for (int nidx = lane + 64 * PER; nidx < a.kpad; nidx += 64) a.moments[size_t(b) * a.kpad + nidx] = T(0);
 }
 
-// gridlet[leaf][p] = sum_n Q[row][n] W[n][p] on the matrix cores, K in steps of 4. A workgroup
-// takes 32 rows; each wave one 16-row tile and half of the 16-column tiles, so the A fragment it
-// loads per K step feeds several independent accumulators.
+// gridlet[leaf][p] = sum_n Q[row][n] W[n][p] on the matrix cores. A workgroup takes 32 rows;
+// each wave one 16-row tile and half of the 16-column tiles, so every A fragment feeds several
+// independent accumulators. W passes through LDS in chunks of KC rows loaded by the whole
+// workgroup at once (its loads are all in flight together), the A fragments of a chunk are
+// loaded into registers ahead of the chunk's MFMAs.
 // Operand layout of v_mfma_*_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]. The
 // output rows differ by dtype (measured on gfx950): accumulator register v of lane l holds
 // D[4*(l/16)+v][l%16] for the f32 instruction and D[4*v+l/16][l%16] for the f64 one.
@@ -125,7 +127,11 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
   constexpr int M = NG * NG * NG, kpad = (M + 3) / 4 * 4, mpad = (M + 15) / 16 * 16;
   constexpr int CT = mpad / 16;       // column tiles
   constexpr int CH = (CT + 1) / 2;    // column tiles per wave
+  constexpr int KC = kpad < 24 ? kpad : 24;  // K rows per LDS chunk (a multiple of 4)
+  constexpr int KS = KC / 4;
+  constexpr int MP2 = 2 * CH * 16;    // LDS row: both waves' tiles, zero past mpad
   using V4 = typename std::conditional<sizeof(T) == 4, floatx4, doublex4>::type;
+  __shared__ T sW[KC * MP2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row0 = blockIdx.x * 32 + (wave & 1) * 16;
   const int c0 = (wave >> 1) * CH;
@@ -135,16 +141,41 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
   V4 acc[CH];
 #pragma unroll
   for (int t = 0; t < CH; ++t) acc[t] = V4{T(0), T(0), T(0), T(0)};
-#pragma unroll 2
-  for (int k0 = 0; k0 < kpad; k0 += 4) {
-    const T av = arow_ok ? Q[size_t(arow) * kpad + k0 + kk] : T(0);
-    const T* wrow = W + size_t(k0 + kk) * mpad + i;
+  // W chunk rows k0 .. k0+KC into registers (all loads in flight together)
+  constexpr int NF = (KC * MP2 + 255) / 256;
+  T wreg[NF];
+  auto load_w = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < CH; ++t) {
-      if (c0 + t < CT) {
-        const T bv = wrow[(c0 + t) * 16];
-        if constexpr (sizeof(T) == 4) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
-        else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+    for (int f = 0; f < NF; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      const int k = k0 + e / MP2, c = e % MP2;
+      wreg[f] = (e < KC * MP2 && k < kpad && c < mpad) ? W[size_t(k) * mpad + c] : T(0);
+    }
+  };
+  load_w(0);
+  for (int k0 = 0; k0 < kpad; k0 += KC) {
+    T av[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int k = k0 + 4 * q + kk;
+      av[q] = (arow_ok && k < kpad) ? Q[size_t(arow) * kpad + k] : T(0);
+    }
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      if (e < KC * MP2) sW[e] = wreg[f];
+    }
+    __syncthreads();
+    if (k0 + KC < kpad) load_w(k0 + KC);  // next chunk in flight during this one's MFMAs
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const T* wrow = sW + (4 * q + kk) * MP2 + c0 * 16 + i;
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const T bv = wrow[t * 16];
+        if constexpr (sizeof(T) == 4) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv, acc[t], 0, 0, 0);
+        else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv, acc[t], 0, 0, 0);
       }
     }
   }
