@@ -110,6 +110,10 @@ struct Plan {
   DevBuf vlevel;  // [nvirt] level
   DevBuf vlist;   // [nvirt] cell id ncells + v
   DevBuf vids, vtmp;  // enumeration scratch
+  // source gridlet ids of the 216 block slots of each parent of targets (cells of levels
+  // 1 .. L-2, from id blocks_first on)
+  DevBuf blocks;
+  int blocks_first = 0;
   DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
   // gridlets
   DevBuf gridlet, local, moments;
@@ -153,7 +157,8 @@ void build_tables(Plan& p, int max_levels, hipStream_t s);
 // ---- tree.hip -----------------------------------------------------------------------------------
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
 void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
-// lists the virtual cubes of the current tree and appends them to the cell arrays
+// lists the virtual cubes of the current tree, appends them to the cell arrays and builds the
+// per-parent table of block sources
 void build_virtual(Plan& p, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------

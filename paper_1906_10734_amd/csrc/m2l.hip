@@ -26,7 +26,6 @@
 #include "dev_common.h"
 #include "fft.h"
 #include "hpm_internal.h"
-#include "zones.h"
 
 namespace hpm {
 
@@ -50,12 +49,8 @@ struct M2LArgs {
   const int* level_off;
   const int* coord;
   const int* parent;
-  const int* flags;
-  const int* child8;
-  const int* nbr27;
-  const uint32_t* vkeys;  // sorted ids of the virtual cubes, whose gridlets follow the cells'
-  int nvirt;
-  int ncells;
+  const int* blocks;  // [parent][216] source gridlet ids of each parent's block (or -1)
+  int first_parent;   // cell id of the table's first row
   const T* gridlet;
   T* local;
   double* m2l_mean;  // z-slab kernel: mean of each target's result (the gridlet part is zero-mean)
@@ -89,27 +84,13 @@ __device__ __forceinline__ TargetGeom target_geom(int g, const int* s_off, int n
   return t;
 }
 
-// Source of block cube "slot" (< 216) of target t: the gridlet id of a real cell (>= 0) or of a
-// virtual cube (ncells + v), or -1 (near zone, empty, outside the box).
+// Source of block cube "slot" (< 216) of target t: its gridlet id (a real cell, or ncells + v
+// for a virtual cube), or -1 for the 27 cubes around the target and for empty positions.
 template <typename T>
 __device__ __forceinline__ int resolve_slot(const M2LArgs<T>& a, const TargetGeom& t, int slot) {
-  const IzSlot z = iz_slot(t.tx, t.ty, t.tz, t.l, t.par, slot, a.nbr27, a.flags, a.child8);
-  if (z.coarse < 0) return z.real;
-  const uint32_t id = cube_id(t.l, z.key);
-  int lo = 0, hi = a.nvirt;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a.vkeys[mid] < id) lo = mid + 1;
-    else hi = mid;
-  }
-  return (lo < a.nvirt && a.vkeys[lo] == id) ? a.ncells + lo : -1;
-}
-
-// Sum of v[B .. B+N) as a balanced binary tree of compile-time shape.
-template <int B, int N, typename T, int L>
-__device__ __forceinline__ T tree_sum(const T (&v)[L]) {
-  if constexpr (N == 1) return v[B];
-  else return tree_sum<B, N / 2>(v) + tree_sum<B + N / 2, N - N / 2>(v);
+  const int bx = slot % 6, by = (slot / 6) % 6, bz = slot / 36;
+  const bool near = abs(bx - 2 - t.cx) <= 1 && abs(by - 2 - t.cy) <= 1 && abs(bz - 2 - t.cz) <= 1;
+  return near ? -1 : a.blocks[size_t(t.par - a.first_parent) * 216 + slot];
 }
 
 // x pass of the two source rows (y0, zr) and (y0 + 1, zr) of the block grid (y0 even): the
@@ -388,7 +369,8 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
         for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
       }
       __syncthreads();
-      // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab
+      // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab, the slab's
+      // terms chained with FMAs before they join the running sum
 #pragma unroll
       for (int r = 0; r < PER; ++r) {
         const int e = tid + NT * r;
@@ -406,15 +388,15 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
           for (int zb = 0; zb < ZB; ++zb) sv[zb] = slab[(size_t(zb) * n + ky) * H + kx];
 #pragma unroll
           for (int zz = 0; zz < NG; ++zz) {
-            T re[ZB], im[ZB];
+            T ar = g[zz + ZB - 1] * sv[0].re, ai = g[zz + ZB - 1] * sv[0].im;
 #pragma unroll
-            for (int zb = 0; zb < ZB; ++zb) {
+            for (int zb = 1; zb < ZB; ++zb) {
               const T gv = g[zz - zb + ZB - 1];
-              re[zb] = gv * sv[zb].re;
-              im[zb] = gv * sv[zb].im;
+              ar = fma(gv, sv[zb].re, ar);
+              ai = fma(gv, sv[zb].im, ai);
             }
-            pr[r][zz] += tree_sum<0, ZB>(re);
-            pi[r][zz] += tree_sum<0, ZB>(im);
+            pr[r][zz] += ar;
+            pi[r][zz] += ai;
           }
         }
       }
@@ -540,12 +522,8 @@ static void m2l_t(Plan& p, hipStream_t s) {
   a.level_off = p.dlevel.as<int>();
   a.coord = p.ccoord.as<int>();
   a.parent = p.cparent.as<int>();
-  a.flags = p.cflags.as<int>();
-  a.child8 = p.child8.as<int>();
-  a.nbr27 = p.nbr27.as<int>();
-  a.vkeys = p.vkeys.as<uint32_t>();
-  a.nvirt = int(p.nvirt);
-  a.ncells = int(p.ncells);
+  a.blocks = p.blocks.as<int>();
+  a.first_parent = p.blocks_first;
   a.gridlet = p.gridlet.as<T>();
   a.local = p.local.as<T>();
   a.m2l_mean = p.m2l_mean.as<double>();

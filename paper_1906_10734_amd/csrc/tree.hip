@@ -700,6 +700,41 @@ __global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, con
   vlist[v] = ncells + v;
 }
 
+// Source gridlet id of every slot of the 6^3 block of each parent of targets: a real cell id,
+// ncells + v for virtual cube v, or -1 (empty position, outside the box, or not a parent).
+__global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, const uint32_t* vkeys,
+                                                     int nvirt, int* table) {
+  __shared__ int s_off[kMaxLevels + 1];
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  __syncthreads();
+  if (tid >= 216) return;
+  const int par = a.first_target + blockIdx.x;
+  int src = -1;
+  if (a.flags[par] & 1) {
+    const int l = level_of(par, s_off, a.nlevels) + 1;
+    const int pc = a.coord[par];
+    const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27,
+                                a.flags, a.child8);
+    if (z.coarse < 0) {
+      src = z.real;
+    } else {
+      const uint32_t id = cube_id(l, z.key);
+      const int v = lower_bound_u32(vkeys, 0, nvirt, id);
+      src = (v < nvirt && vkeys[v] == id) ? ncells + v : -1;
+    }
+  }
+  table[size_t(blockIdx.x) * 216 + tid] = src;
+}
+
+static void build_block_table(Plan& p, const VirtArgs& a, int nt, hipStream_t s) {
+  p.blocks.reserve(size_t(nt) * 216 * 4);
+  p.blocks_first = a.first_target;
+  k_block_table<<<nt, 256, 0, s>>>(a, int(p.ncells), p.vkeys.as<uint32_t>(), int(p.nvirt),
+                                   p.blocks.as<int>());
+  HPM_LAUNCH_CHECK();
+}
+
 void build_virtual(Plan& p, hipStream_t s) {
   p.nvirt = 0;
   if (p.nlevels <= 2) return;
@@ -731,7 +766,10 @@ void build_virtual(Plan& p, hipStream_t s) {
   exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
   HPM_HIP(hipStreamSynchronize(s));
   const int refs = p.hbox[Plan::kBoxTotal];
-  if (refs <= 0) return;
+  if (refs <= 0) {
+    build_block_table(p, a, nt, s);
+    return;
+  }
   p.vids.reserve(size_t(refs) * 4);
   p.vtmp.reserve(size_t(refs) * 4 * 4);  // sort scratch (keys, values, values) and flags/pos
   a.ids = p.vids.as<uint32_t>();
@@ -760,6 +798,11 @@ void build_virtual(Plan& p, hipStream_t s) {
                                               p.vlevel.as<int>(), p.vlist.as<int>());
   HPM_LAUNCH_CHECK();
   p.nvirt = nv;
+  a.coord = p.ccoord.as<int>();  // the cell arrays may have moved when they grew
+  a.flags = p.cflags.as<int>();
+  a.child8 = p.child8.as<int>();
+  a.nbr27 = p.nbr27.as<int>();
+  build_block_table(p, a, nt, s);
 }
 
 }  // namespace hpm
