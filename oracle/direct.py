@@ -1,5 +1,7 @@
-"""O(N^2) softened direct sum, the force-error reference (test infrastructure only).
+"""O(N^2) direct sum, the force-error reference (test infrastructure only).
 
+phi_i = sum_{j != i} m_j g(r_ij) and a_i = -sum_{j != i} m_j c(r_ij) (r_i - r_j) with the kernel's
+potential g and force coefficient c (green.py); for the default kernel
 phi_i = -G sum_{j != i} m_j (r_ij^2 + eps^2)^{-1/2},
 a_i   = -G sum_{j != i} m_j (r_i - r_j) (r_ij^2 + eps^2)^{-3/2}.
 """
@@ -7,9 +9,12 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import green
+
 
 def direct_sum(x, y, z, m, gconst: float = 1.0, softening: float = 0.0,
-               targets: np.ndarray | None = None, chunk_pairs: int = 1 << 22):
+               targets: np.ndarray | None = None, chunk_pairs: int = 1 << 22,
+               kernel: str = "newton", screening: float = 0.0):
     """Potential and acceleration at ``targets`` (input indices; all particles if None)."""
     pos = np.stack([np.asarray(x, np.float64), np.asarray(y, np.float64),
                     np.asarray(z, np.float64)], axis=1)
@@ -19,16 +24,17 @@ def direct_sum(x, y, z, m, gconst: float = 1.0, softening: float = 0.0,
     phi = np.zeros(tgt.size)
     acc = np.zeros((tgt.size, 3))
     step = max(1, chunk_pairs // max(n, 1))
-    eps2 = softening * softening
+    green.check(kernel, screening)
     for s in range(0, tgt.size, step):
         t = tgt[s:s + step]
         d = pos[t][:, None, :] - pos[None, :, :]
-        r2 = np.einsum("tsk,tsk->ts", d, d) + eps2
+        r2 = np.einsum("tsk,tsk->ts", d, d)
         self_mask = t[:, None] == np.arange(n)[None, :]
-        inv = np.where(self_mask, 0.0, 1.0 / np.sqrt(np.where(self_mask, 1.0, r2)))
-        w = m[None, :] * inv
-        phi[s:s + step] = -gconst * w.sum(axis=1)
-        acc[s:s + step] = -gconst * np.einsum("ts,tsk->tk", w * inv * inv, d)
+        r2 = np.where(self_mask, 1.0, r2)
+        g = np.where(self_mask, 0.0, green.potential(r2, gconst, softening, kernel, screening))
+        c = np.where(self_mask, 0.0, green.force_coefficient(r2, gconst, softening, kernel, screening))
+        phi[s:s + step] = (m[None, :] * g).sum(axis=1)
+        acc[s:s + step] = -np.einsum("ts,tsk->tk", m[None, :] * c, d)
     return phi, acc
 
 

@@ -27,7 +27,7 @@ from functools import lru_cache
 import numpy as np
 import scipy.fft as sfft
 
-from . import tables
+from . import green, tables
 from .tree import Tree
 
 
@@ -41,6 +41,8 @@ class Problem:
     uniform_depth: int = 0
     leaf_capacity: int = 64
     max_depth: int = 10
+    kernel: str = "newton"   # point-mass kernel (green.py); "yukawa" needs a screening length
+    screening: float = 0.0
 
 
 # ---------------------------------------------------------------------------------------------
@@ -123,15 +125,17 @@ def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float):
 
 
 def pair_sum(tpos: np.ndarray, tids: np.ndarray, spos: np.ndarray, sm: np.ndarray,
-             sids: np.ndarray, gconst: float, eps: float):
-    """Softened direct sum of sources on targets, skipping equal particle ids (no self force)."""
+             sids: np.ndarray, gconst: float, eps: float, kernel: str = "newton",
+             screening: float = 0.0):
+    """Direct sum of the kernel over sources on targets, skipping equal particle ids."""
     d = tpos[:, None, :] - spos[None, :, :]
-    r2 = np.einsum("tsk,tsk->ts", d, d) + eps * eps
+    r2 = np.einsum("tsk,tsk->ts", d, d)
     same = tids[:, None] == sids[None, :]
-    inv = np.where(same, 0.0, 1.0 / np.sqrt(np.where(same, 1.0, r2)))
-    w = sm[None, :] * inv
-    pot = -gconst * w.sum(axis=1)
-    acc = -gconst * np.einsum("ts,tsk->tk", w * inv * inv, d)
+    r2 = np.where(same, 1.0, r2)
+    g = np.where(same, 0.0, green.potential(r2, gconst, eps, kernel, screening))
+    c = np.where(same, 0.0, green.force_coefficient(r2, gconst, eps, kernel, screening))
+    pot = (sm[None, :] * g).sum(axis=1)
+    acc = -np.einsum("ts,tsk->tk", sm[None, :] * c, d)
     return pot, acc
 
 
@@ -143,6 +147,7 @@ class HPM:
     """One HPM evaluation. ``mode`` selects the M2L route: "fft" (the method) or "direct"."""
 
     def __init__(self, x, y, z, m, prob: Problem, mode: str = "fft"):
+        green.check(prob.kernel, prob.screening)
         self.prob = prob
         self.mode = mode
         pos = np.stack([np.asarray(x, np.float64), np.asarray(y, np.float64),
@@ -198,7 +203,8 @@ class HPM:
     def _ghat_level(self, l: int) -> np.ndarray:
         if l not in self._ghat:
             h = self.tree.cube_size(l) / self.ng
-            glat = tables.green_lattice(self.ng, h, self.prob.gconst, self.prob.softening)
+            glat = tables.green_lattice(self.ng, h, self.prob.gconst, self.prob.softening,
+                                        self.prob.kernel, self.prob.screening)
             self._ghat[l] = sfft.rfftn(glat)
         return self._ghat[l]
 
@@ -226,7 +232,8 @@ class HPM:
             snodes = t.cube_centre(l, q) + L * xp
             d = tnodes[:, None, :] - snodes[None, :, :]
             r2 = np.einsum("tsk,tsk->ts", d, d)
-            out += tables.green_physical(r2, self.prob.gconst, self.prob.softening) @ g
+            out += tables.green_physical(r2, self.prob.gconst, self.prob.softening,
+                                         self.prob.kernel, self.prob.screening) @ g
         return out
 
     def _m2l_fft(self, l, coord, sources):
@@ -270,7 +277,7 @@ class HPM:
         srcs = [t.cube_range(l, q) for q in t.near_positions(lev.coords[i], l)]
         sidx = np.concatenate([np.arange(sb, se) for sb, se in srcs if se > sb])
         pn, an = pair_sum(self.pos[sel], sel, self.pos[sidx], self.m[sidx], sidx, p.gconst,
-                          p.softening)
+                          p.softening, p.kernel, p.screening)
         return pf, af, pn, an
 
     def evaluate(self, sample: np.ndarray | None = None):

@@ -24,6 +24,8 @@ from math import comb, factorial
 
 import numpy as np
 
+from . import green
+
 
 def node_fractions(ng: int) -> list:
     """Gridlet node coordinates (i + 1/2)/N_g - 1/2 as exact rationals (Sec. 2.2)."""
@@ -170,16 +172,18 @@ def periodic_distance(n: int) -> np.ndarray:
     return np.where(i <= n // 2, i, n - i).astype(np.float64)
 
 
-def green_physical(r2: np.ndarray, gconst: float, softening: float) -> np.ndarray:
-    """Softened point-mass potential kernel g(r) = -G (r^2 + eps^2)^{-1/2}.
+def green_physical(r2: np.ndarray, gconst: float, softening: float, kernel: str = "newton",
+                   screening: float = 0.0) -> np.ndarray:
+    """Point-mass potential kernel g(r) (see green.py).
 
     The paper's Eq. (1) is the 1/(4 pi r) kernel in grid units; the method is kernel independent
-    (Sec. 4), and this build's kernel is gravity with Plummer softening eps (eps = 0 gives 1/r).
+    (Sec. 4). The default is gravity with Plummer softening eps (eps = 0 gives 1/r).
     """
-    return -gconst / np.sqrt(r2 + softening * softening)
+    return green.potential(r2, gconst, softening, kernel, screening)
 
 
-def green_lattice(ng: int, h: float, gconst: float, softening: float) -> np.ndarray:
+def green_lattice(ng: int, h: float, gconst: float, softening: float, kernel: str = "newton",
+                  screening: float = 0.0) -> np.ndarray:
     """Exact lattice Green function on the (8 N_g)^3 FFT grid, indexed [z, y, x] (Eq. 1).
 
     G[k, j, i] = g(h * sqrt(|i|_p^2 + |j|_p^2 + |k|_p^2)) with node spacing h. The grid edge is
@@ -192,4 +196,4 @@ def green_lattice(ng: int, h: float, gconst: float, softening: float) -> np.ndar
     r2 = (dx * dx + dy * dy + dz * dz) * (h * h)
     if softening == 0.0:
         r2[0, 0, 0] = h * h
-    return green_physical(r2, gconst, softening)
+    return green_physical(r2, gconst, softening, kernel, screening)
