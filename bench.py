@@ -68,12 +68,14 @@ def traffic_from_profile(ng: int, prec: str):
     return rec.get("bytes_per_launch")
 
 
-def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int):
+def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, kernel="newton",
+             screening=0.0):
     """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
     p = parts.astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
     x, y, z, m = (torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
-    prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3)
+    prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3,
+                       kernel=kernel, screening=screening)
     plan = hpm.Plan(prob, x, y, z)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(warmup):
@@ -198,6 +200,24 @@ def main():
         return float(e.pow(2).mean().sqrt()), float(e.max())
 
     f32_rms, f32_max = ferr(out32)
+
+    # the screened kernel (kernel independence, Sec. 4) on the same workload, FP32, with its
+    # own direct-sum reference
+    lam = 0.05
+    ry, outy, devy = run_path(hpm, torch, parts, "f32", ng, args.steps, 1, "yukawa", lam)
+    _, yax, yay, yaz = hpm.direct_sum(x64, y64, z64, m64, sub, 1.0, 1e-3, kernel="yukawa",
+                                      screening=lam)
+    yref = torch.stack([yax, yay, yaz], 1)
+    ya = torch.stack([o[sub].double() for o in outy[1:]], 1)
+    ye = (ya - yref).norm(dim=1) / yref.norm(dim=1)
+    ry64, outy64, _ = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1, "yukawa", lam)
+    ye64 = (torch.stack([o[sub] for o in outy64[1:]], 1) - yref).norm(dim=1) / yref.norm(dim=1)
+    yukawa = {"screening": lam, "value": round(args.n / (ry["ms_per_step"] * 1e-3), 1),
+              "unit": "particles/s", "ms_per_step": round(ry["ms_per_step"], 4),
+              "force_err_rms": float(ye.pow(2).mean().sqrt()), "force_err_max": float(ye.max()),
+              "fp64": {"value": round(args.n / (ry64["ms_per_step"] * 1e-3), 1),
+                       "ms_per_step": round(ry64["ms_per_step"], 4),
+                       "force_err_rms": float(ye64.pow(2).mean().sqrt())}}
     f64_rms, f64_max = ferr(out64)
     phi_f32_vs_f64 = float(((out32[0].double() - out64[0]).norm() / out64[0].norm()))
 
@@ -243,6 +263,7 @@ def main():
         "stage_ms_per_step": {k: round(v / max(r32["stages"]["n_exec"], 1), 4)
                               for k, v in r32["stages"].items() if k not in ("n_exec", "n_build")},
         "roofline": roofline,
+        "kernels": {"yukawa_f32": yukawa},
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
     if not args.no_cpu_baseline:

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 1
+#define HPM_ABI_VERSION 2
 
 typedef enum {
   HPM_OK = 0,
@@ -50,6 +50,17 @@ typedef enum {
 } hpm_status;
 
 typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
+
+/*
+ * Interaction kernel: the potential g of a unit point mass at distance r, with the softened
+ * distance s = (r^2 + eps^2)^{1/2}. The method is kernel independent (Abstract; Sec. 4): the
+ * kernel enters the lattice Green function of the source-to-target step (Eq. 1 with g in place
+ * of 1/r) and the near-zone pair sum; the gridlet fit, the translations and the interpolation
+ * do not depend on it.
+ *   HPM_KERNEL_NEWTON   g = -G / s                    (eps = 0: the bare 1/r kernel)
+ *   HPM_KERNEL_YUKAWA   g = -G exp(-s / lam) / s      (screened; lam = screening > 0)
+ */
+typedef enum { HPM_KERNEL_NEWTON = 0, HPM_KERNEL_YUKAWA = 1 } hpm_kernel;
 
 /*
  * Problem description.
@@ -66,6 +77,8 @@ typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
  *   softening      Plummer softening eps >= 0 of g(r) (eps = 0: the bare 1/r kernel).
  *   gconst         G > 0.
  *   box_lo, box_size  the cubic root cell (level 0), box_size > 0 (Sec. 1).
+ *   kernel         an hpm_kernel value.
+ *   screening      lam > 0 of HPM_KERNEL_YUKAWA (ignored for HPM_KERNEL_NEWTON).
  */
 typedef struct {
   int32_t abi;
@@ -78,6 +91,9 @@ typedef struct {
   double gconst;
   double box_lo[3];
   double box_size;
+  int32_t kernel;
+  int32_t reserved;   /* must be 0 */
+  double screening;
 } hpm_problem;
 
 /* Per-solve statistics filled by hpm_plan_info (host struct owned by the caller). */
@@ -187,17 +203,19 @@ hpm_status hpm_plan_copy_locals(const hpm_plan* plan, int32_t level, void* host)
 hpm_status hpm_plan_copy_local_offsets(const hpm_plan* plan, int32_t level, double* host);
 
 /*
- * Softened direct sum (the force-error reference of Sec. 3.2's accuracy measure), on the
+ * Direct sum of the kernel (the force-error reference of Sec. 3.2's accuracy measure), on the
  * device in double precision regardless of "precision" of the inputs:
- *   phi_t = -G sum_{j != i_t} m_j (r^2+eps^2)^{-1/2},  a_t = -G sum_{j != i_t} m_j r_ij (r^2+eps^2)^{-3/2}
+ *   phi_t = sum_{j != i_t} m_j g(r_tj),  a_t = -grad phi_t
+ * (for HPM_KERNEL_NEWTON: phi_t = -G sum m_j (r^2+eps^2)^{-1/2}, a_t = -G sum m_j r_tj (r^2+eps^2)^{-3/2})
  * for n_targets input indices "targets" (device int32) against all n sources.
  *   precision   dtype of x, y, z, m (HPM_F32 or HPM_F64);
+ *   kernel, screening  as in hpm_problem;
  *   phi, ax, ay, az  device double arrays of n_targets elements (outputs).
  */
 hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const void* y,
                           const void* z, const void* m, int64_t n_targets, const int32_t* targets,
-                          double gconst, double softening, double* phi, double* ax, double* ay,
-                          double* az, void* stream);
+                          double gconst, double softening, int32_t kernel, double screening,
+                          double* phi, double* ax, double* ay, double* az, void* stream);
 
 #ifdef __cplusplus
 }

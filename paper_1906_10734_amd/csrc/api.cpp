@@ -19,6 +19,13 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 void fail(hpm_status s, const std::string& msg) { throw HpmError{s, msg}; }
 
+static void check_kernel(int32_t kernel, double screening) {
+  if (kernel != HPM_KERNEL_NEWTON && kernel != HPM_KERNEL_YUKAWA)
+    fail(HPM_ERR_INVALID_ARG, "kernel must be HPM_KERNEL_NEWTON or HPM_KERNEL_YUKAWA");
+  if (kernel == HPM_KERNEL_YUKAWA && !(std::isfinite(screening) && screening > 0.0))
+    fail(HPM_ERR_INVALID_ARG, "the Yukawa kernel needs screening > 0");
+}
+
 static void check_problem(const hpm_problem* pr) {
   if (!pr) fail(HPM_ERR_INVALID_ARG, "problem is NULL");
   if (pr->abi != HPM_ABI_VERSION) fail(HPM_ERR_INVALID_ARG, "problem.abi != HPM_ABI_VERSION");
@@ -36,6 +43,8 @@ static void check_problem(const hpm_problem* pr) {
     if (!std::isfinite(pr->box_lo[k])) fail(HPM_ERR_INVALID_ARG, "box_lo must be finite");
   if (!(std::isfinite(pr->softening) && pr->softening >= 0.0)) fail(HPM_ERR_INVALID_ARG, "softening must be >= 0");
   if (!(std::isfinite(pr->gconst) && pr->gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "gconst must be > 0");
+  check_kernel(pr->kernel, pr->screening);
+  if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
   if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
   if (pr->uniform_depth == 0) {
     if (pr->leaf_capacity < 1) fail(HPM_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
@@ -373,8 +382,8 @@ hpm_status hpm_plan_copy_local_offsets(const hpm_plan* plan, int32_t level, doub
 
 hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const void* y,
                           const void* z, const void* m, int64_t n_targets, const int32_t* targets,
-                          double gconst, double softening, double* phi, double* ax, double* ay,
-                          double* az, void* stream) {
+                          double gconst, double softening, int32_t kernel, double screening,
+                          double* phi, double* ax, double* ay, double* az, void* stream) {
   return guarded([&] {
     if (precision != HPM_F32 && precision != HPM_F64) fail(HPM_ERR_INVALID_ARG, "bad precision");
     if (n < 1 || n > (int64_t(1) << 30) || n_targets < 0 || n_targets > n)
@@ -382,8 +391,9 @@ hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const voi
     if (!x || !y || !z || !m || (n_targets > 0 && (!targets || !phi || !ax || !ay || !az)))
       fail(HPM_ERR_INVALID_ARG, "NULL pointer");
     if (!(softening >= 0.0) || !(gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "bad constants");
-    launch_direct_sum(precision, n, x, y, z, m, n_targets, targets, gconst, softening, phi, ax, ay,
-                      az, (hipStream_t)stream);
+    check_kernel(kernel, screening);
+    launch_direct_sum(precision, n, x, y, z, m, n_targets, targets, gconst, softening,
+                      PairKernel{kernel, screening}, phi, ax, ay, az, (hipStream_t)stream);
   });
 }
 

@@ -255,12 +255,30 @@ struct P2PArgs {
   const T* ms;
   T* partial;  // [item][64][5]: phi, phi compensation, ax, ay, az (without G)
   T eps2;
+  T inv_lam;  // 1 / screening length (screened kernel)
 };
 
 template <typename T>
 __device__ __forceinline__ T inv_sqrt(T x) {
   if constexpr (sizeof(T) == 4) return rsqrtf(x);
   else return 1.0 / sqrt(x);
+}
+
+// Pair terms of the interaction kernel (without G) from inv = 1/s, s the softened distance:
+// the potential of a unit source is -w and its acceleration -c (r_i - r_j).
+//   HPM_KERNEL_NEWTON  w = 1/s,                c = 1/s^3
+//   HPM_KERNEL_YUKAWA  w = exp(-s/lam)/s,      c = exp(-s/lam) (1/(lam s^2) + 1/s^3)
+// inv = 0 (the self pair) gives w = c = 0 for both.
+template <int KER, typename T>
+__device__ __forceinline__ void pair_terms(T s2, T inv, T inv_lam, T& w, T& c) {
+  if constexpr (KER == HPM_KERNEL_NEWTON) {
+    w = inv;
+    c = inv * inv * inv;
+  } else {
+    const T e = exp(-(s2 * inv) * inv_lam);
+    w = e * inv;
+    c = w * (inv * inv + inv * inv_lam);
+  }
 }
 
 template <typename T>
@@ -272,7 +290,7 @@ struct alignas(4 * sizeof(T)) SrcP {
 // targets; sources are staged 64 at a time in LDS (position and mass in one 4-vector) and the
 // groups are combined with shuffles. The self pair is recognised by its place in the source
 // sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
-template <typename T>
+template <typename T, int KER>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
   __shared__ SrcP<T> s_src[64];
@@ -330,9 +348,11 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
         const T inv = (tile + e == self) ? T(0) : inv_sqrt(r2);
-        const T mi = q.m * inv;
-        const T mi3 = mi * inv * inv;
-        const T yv = -mi - phc;  // Kahan: ph += -m/r
+        T w, c;
+        pair_terms<KER>(r2, inv, a.inv_lam, w, c);
+        const T mi = q.m * w;
+        const T mi3 = q.m * c;
+        const T yv = -mi - phc;  // Kahan: ph += -m w
         const T tv = ph + yv;
         phc = (tv - ph) - yv;
         ph = tv;
@@ -473,10 +493,11 @@ __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
   }
 }
 
-template <typename T>
+template <typename T, int KER>
 __global__ __launch_bounds__(256) void k_direct(int n, const T* x, const T* y, const T* z, const T* m,
-                                                const int* targets, double G, double eps2, double* phi,
-                                                double* ax, double* ay, double* az) {
+                                                const int* targets, double G, double eps2,
+                                                double inv_lam, double* phi, double* ax, double* ay,
+                                                double* az) {
   __shared__ double s_red[4][4];
   const int t = targets[blockIdx.x];
   if (t < 0 || t >= n) {  // invalid target index: NaN result, no out-of-range read
@@ -490,8 +511,10 @@ __global__ __launch_bounds__(256) void k_direct(int n, const T* x, const T* y, c
     const double dx = xi - double(x[j]), dy = yi - double(y[j]), dz = zi - double(z[j]);
     const double r2 = dx * dx + dy * dy + dz * dz + eps2;
     const double inv = 1.0 / sqrt(r2);
-    const double mi = double(m[j]) * inv;
-    const double mi3 = mi * inv * inv;
+    double w, c;
+    pair_terms<KER>(r2, inv, inv_lam, w, c);
+    const double mi = double(m[j]) * w;
+    const double mi3 = double(m[j]) * c;
     p -= mi;
     fx -= mi3 * dx;
     fy -= mi3 * dy;
@@ -547,7 +570,9 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   b.ms = p.ms.as<T>();
   b.partial = p.partial.as<T>();
   b.eps2 = T(p.prob.softening * p.prob.softening);
-  k_p2p<T><<<int(p.n_items), 64, 0, s>>>(b);
+  b.inv_lam = (p.prob.kernel == HPM_KERNEL_YUKAWA) ? T(1.0 / p.prob.screening) : T(0);
+  if (p.prob.kernel == HPM_KERNEL_YUKAWA) k_p2p<T, HPM_KERNEL_YUKAWA><<<int(p.n_items), 64, 0, s>>>(b);
+  else k_p2p<T, HPM_KERNEL_NEWTON><<<int(p.n_items), 64, 0, s>>>(b);
   HPM_LAUNCH_CHECK();
   LeafArgs<T> a;
   a.n = int(p.n);
@@ -605,19 +630,29 @@ void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s
   HPM_DISPATCH_NG(leaf_t, p, phi, ax, ay, az, s);
 }
 
+template <typename T>
+static void direct_t(int64_t n, const void* x, const void* y, const void* z, const void* m,
+                     int64_t nt, const int32_t* targets, double G, double eps, PairKernel ker,
+                     double* phi, double* ax, double* ay, double* az, hipStream_t s) {
+  const double inv_lam = (ker.kind == HPM_KERNEL_YUKAWA) ? 1.0 / ker.screening : 0.0;
+  if (ker.kind == HPM_KERNEL_YUKAWA)
+    k_direct<T, HPM_KERNEL_YUKAWA><<<int(nt), 256, 0, s>>>(int(n), (const T*)x, (const T*)y,
+                                                           (const T*)z, (const T*)m, targets, G,
+                                                           eps * eps, inv_lam, phi, ax, ay, az);
+  else
+    k_direct<T, HPM_KERNEL_NEWTON><<<int(nt), 256, 0, s>>>(int(n), (const T*)x, (const T*)y,
+                                                           (const T*)z, (const T*)m, targets, G,
+                                                           eps * eps, inv_lam, phi, ax, ay, az);
+  HPM_LAUNCH_CHECK();
+}
+
 void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const void* z,
                        const void* m, int64_t nt, const int32_t* targets, double G, double eps,
-                       double* phi, double* ax, double* ay, double* az, hipStream_t s) {
+                       PairKernel ker, double* phi, double* ax, double* ay, double* az,
+                       hipStream_t s) {
   if (nt <= 0) return;
-  if (prec == HPM_F32)
-    k_direct<float><<<int(nt), 256, 0, s>>>(int(n), (const float*)x, (const float*)y,
-                                            (const float*)z, (const float*)m, targets, G, eps * eps,
-                                            phi, ax, ay, az);
-  else
-    k_direct<double><<<int(nt), 256, 0, s>>>(int(n), (const double*)x, (const double*)y,
-                                             (const double*)z, (const double*)m, targets, G,
-                                             eps * eps, phi, ax, ay, az);
-  HPM_LAUNCH_CHECK();
+  if (prec == HPM_F32) direct_t<float>(n, x, y, z, m, nt, targets, G, eps, ker, phi, ax, ay, az, s);
+  else direct_t<double>(n, x, y, z, m, nt, targets, G, eps, ker, phi, ax, ay, az, s);
 }
 
 }  // namespace hpm

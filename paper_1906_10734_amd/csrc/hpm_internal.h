@@ -72,6 +72,12 @@ struct DevBuf {
   }
 };
 
+// The interaction kernel of a problem (hpm_kernel and its screening length).
+struct PairKernel {
+  int32_t kind = HPM_KERNEL_NEWTON;
+  double screening = 0.0;
+};
+
 // Constant tables of one (precision, N_g, softening, box, levels) combination, in device memory.
 struct Tables {
   DevBuf m2m;    // [2][NG][NG]: T1^a[p][q] = l_p((a + xi_q)/2), a = -1/2 (index 0), +1/2 (1)
@@ -176,6 +182,7 @@ void launch_l2l(Plan& p, int level, hipStream_t s);
 void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s);
 void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const void* z,
                        const void* m, int64_t nt, const int32_t* targets, double G, double eps,
-                       double* phi, double* ax, double* ay, double* az, hipStream_t s);
+                       PairKernel ker, double* phi, double* ax, double* ay, double* az,
+                       hipStream_t s);
 
 }  // namespace hpm

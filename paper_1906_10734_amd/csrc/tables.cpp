@@ -11,8 +11,9 @@
 //                a = -1/2 or +1/2, the Lagrange basis l_p on the gridlet nodes (the matrix of
 //                the paper's double sum, in closed form). Parent-to-child uses the transpose.
 //   Green transform  per level l >= 2: the exact lattice Green function G(d) = g(h_l |d|_p) of
-//                Eq. (1) on the (8 N_g)^3 grid, h_l = size / (2^l N_g), with the softened kernel
-//                g(r) = -G (r^2+eps^2)^{-1/2}; for eps = 0 the origin takes the value at unit
+//                Eq. (1) on the (8 N_g)^3 grid, h_l = size / (2^l N_g), with the problem's
+//                kernel g (softened Newtonian -G (r^2+eps^2)^{-1/2}, or the screened one;
+//                any kernel works, Sec. 4); for eps = 0 the origin takes the value at unit
 //                offset. G is real and even along each axis, so its DFT is real, even and a
 //                product of cosine sums; only the octant k in [0, n/2]^3 is stored, divided by
 //                n^3 (the normalisation of the unnormalised inverse FFT). The same function
@@ -142,7 +143,13 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
           // zero keeps the largest (near-origin) kernel values out of the transform, where they
           // would only add rounding error.
           const bool unreachable = std::max(pd[x], std::max(pd[y], pd[z])) <= ng;
-          g[(size_t(z) * n + y) * n + x] = unreachable ? 0.0 : -G / std::sqrt(r2 + eps * eps);
+          double gv = 0.0;
+          if (!unreachable) {
+            const double sd = std::sqrt(r2 + eps * eps);
+            gv = (p.prob.kernel == HPM_KERNEL_YUKAWA) ? -G * std::exp(-sd / p.prob.screening) / sd
+                                                      : -G / sd;
+          }
+          g[(size_t(z) * n + y) * n + x] = gv;
         }
     // x: a1[z][y][kx]
     for (int z = 0; z < n; ++z)

@@ -16,8 +16,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpm.so")
 
-HPM_ABI_VERSION = 1
+HPM_ABI_VERSION = 2
 HPM_F64, HPM_F32 = 0, 1
+HPM_KERNELS = {"newton": 0, "yukawa": 1}
 STATUS = {0: "HPM_OK", 1: "HPM_ERR_INVALID_ARG", 2: "HPM_ERR_OUT_OF_BOX", 3: "HPM_ERR_NONFINITE",
           4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED"}
 
@@ -30,7 +31,8 @@ class HpmProblem(ctypes.Structure):
                 ("uniform_depth", ctypes.c_int32), ("leaf_capacity", ctypes.c_int32),
                 ("max_depth", ctypes.c_int32), ("softening", ctypes.c_double),
                 ("gconst", ctypes.c_double), ("box_lo", ctypes.c_double * 3),
-                ("box_size", ctypes.c_double)]
+                ("box_size", ctypes.c_double), ("kernel", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("screening", ctypes.c_double)]
 
 
 class HpmPlanInfo(ctypes.Structure):
@@ -59,8 +61,8 @@ SIGNATURES = {
     "hpm_plan_copy_gridlets": (_i32, [_vp, _i32, _vp]),
     "hpm_plan_copy_locals": (_i32, [_vp, _i32, _vp]),
     "hpm_plan_copy_local_offsets": (_i32, [_vp, _i32, _vp]),
-    "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _vp, _vp, _vp,
-                              _vp, _vp]),
+    "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _i32, _d, _vp,
+                              _vp, _vp, _vp, _vp]),
 }
 
 
@@ -103,6 +105,8 @@ class Problem:
     gconst: float = 1.0
     box_lo: tuple = (0.0, 0.0, 0.0)
     box_size: float = 1.0
+    kernel: str = "newton"          # "newton" or "yukawa" (screened, needs screening > 0)
+    screening: float = 0.0
 
     @property
     def dtype(self) -> torch.dtype:
@@ -121,6 +125,9 @@ class Problem:
         for k in range(3):
             p.box_lo[k] = self.box_lo[k]
         p.box_size = self.box_size
+        p.kernel = HPM_KERNELS[self.kernel]
+        p.reserved = 0
+        p.screening = self.screening
         return p
 
 
@@ -247,8 +254,9 @@ def solve(problem: Problem, x, y, z, m, stream=None):
     return tuple(out)
 
 
-def direct_sum(x, y, z, m, targets, gconst: float = 1.0, softening: float = 0.0, stream=None):
-    """Brute-force softened sum on the device in FP64 at the given input indices."""
+def direct_sum(x, y, z, m, targets, gconst: float = 1.0, softening: float = 0.0, stream=None,
+               kernel: str = "newton", screening: float = 0.0):
+    """Brute-force sum of the kernel on the device in FP64 at the given input indices."""
     n = int(x.numel())
     dt = x.dtype
     prec = HPM_F32 if dt == torch.float32 else HPM_F64
@@ -256,6 +264,7 @@ def direct_sum(x, y, z, m, targets, gconst: float = 1.0, softening: float = 0.0,
     out = [torch.empty(tg.numel(), dtype=torch.float64, device=x.device) for _ in range(4)]
     _check(_lib.hpm_direct_sum(prec, n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
                                _dev(z, dt, n, "z"), _dev(m, dt, n, "m"), tg.numel(),
-                               tg.data_ptr(), gconst, softening, *(o.data_ptr() for o in out),
+                               tg.data_ptr(), gconst, softening, HPM_KERNELS[kernel], screening,
+                               *(o.data_ptr() for o in out),
                                _stream(stream)), "hpm_direct_sum")
     return tuple(out)

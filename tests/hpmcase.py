@@ -35,10 +35,11 @@ def particles(name: str, prec: str):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle(name: str, prec: str, ng: int, eps: float = 1e-3):
+def oracle(name: str, prec: str, ng: int, eps: float = 1e-3, kernel: str = "newton",
+           screening: float = 0.0):
     """Oracle HPM on the same (rounded) inputs: (hpm object, phi, acc) in input order."""
     p, kw = particles(name, prec)
-    prob = ohpm.Problem(ng=ng, softening=eps, **kw)
+    prob = ohpm.Problem(ng=ng, softening=eps, kernel=kernel, screening=screening, **kw)
     phi, acc, h = ohpm.solve(p.x, p.y, p.z, p.m, prob, mode="fft")
     return h, phi, acc
 
@@ -48,9 +49,10 @@ def device(p, torch):
     return [torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m)]
 
 
-def gpu_problem(ng: int, prec: str, kw: dict, eps: float = 1e-3):
+def gpu_problem(ng: int, prec: str, kw: dict, eps: float = 1e-3, kernel: str = "newton",
+                screening: float = 0.0):
     from paper_1906_10734_amd import hpm
-    return hpm.Problem(ng=ng, precision=prec, softening=eps,
+    return hpm.Problem(ng=ng, precision=prec, softening=eps, kernel=kernel, screening=screening,
                        uniform_depth=kw.get("uniform_depth", 0),
                        leaf_capacity=kw.get("leaf_capacity", 64),
                        max_depth=kw.get("max_depth", 10))

@@ -39,16 +39,23 @@ def test_binding_covers_the_header():
 
 def _problem(**kw):
     from paper_1906_10734_amd import hpm
-    p = hpm.Problem(**{k: v for k, v in kw.items() if k != "abi"}).c()
+    raw = ("abi", "kernel_id", "reserved")
+    p = hpm.Problem(**{k: v for k, v in kw.items() if k not in raw}).c()
     if "abi" in kw:
         p.abi = kw["abi"]
+    if "kernel_id" in kw:
+        p.kernel = kw["kernel_id"]
+    if "reserved" in kw:
+        p.reserved = kw["reserved"]
     return p
 
 
 @pytest.mark.parametrize("kw,status", [
     (dict(ng=5), 6), (dict(ng=0), 1), (dict(ng=7), 6), (dict(ng=8), 6), (dict(box_size=0.0), 1),
     (dict(softening=-1.0), 1), (dict(gconst=0.0), 1), (dict(uniform_depth=11), 1),
-    (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=2), 1),
+    (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=1), 1), (dict(abi=99), 1),
+    (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
+    (dict(kernel="yukawa", screening=float("nan")), 1), (dict(reserved=1), 1),
 ])
 def test_bad_problem_rejected_on_host(kw, status):
     from paper_1906_10734_amd import hpm
@@ -72,7 +79,12 @@ def test_null_and_size_checks():
     assert lib.hpm_plan_create(ctypes.byref(p), 16, None, dummy, dummy, None, ctypes.byref(out)) == 1
     assert lib.hpm_plan_create(None, 16, dummy, dummy, dummy, None, ctypes.byref(out)) == 1
     assert lib.hpm_plan_execute(None, dummy, dummy, dummy, dummy, dummy, None) == 1
-    assert lib.hpm_direct_sum(7, 16, dummy, dummy, dummy, dummy, 1, dummy, 1.0, 0.0, dummy, dummy,
-                              dummy, dummy, None) == 1
+    assert lib.hpm_direct_sum(7, 16, dummy, dummy, dummy, dummy, 1, dummy, 1.0, 0.0, 0, 0.0, dummy,
+                              dummy, dummy, dummy, None) == 1
+    # unknown kernel, and the screened kernel without a screening length
+    assert lib.hpm_direct_sum(0, 16, dummy, dummy, dummy, dummy, 1, dummy, 1.0, 0.0, 5, 0.0, dummy,
+                              dummy, dummy, dummy, None) == 1
+    assert lib.hpm_direct_sum(0, 16, dummy, dummy, dummy, dummy, 1, dummy, 1.0, 0.0, 1, 0.0, dummy,
+                              dummy, dummy, dummy, None) == 1
     assert lib.hpm_status_string(2) == b"HPM_ERR_OUT_OF_BOX"
     lib.hpm_plan_destroy(None)
