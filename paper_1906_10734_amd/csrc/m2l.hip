@@ -131,6 +131,44 @@ __device__ __forceinline__ void xpass_rows(const M2LArgs<T>& a, int y0, int zr, 
   }
 }
 
+// x pass of one source row (y, zr) of the block grid: the gridlet rows of the six cubes along x
+// (6 N_g values, zero beyond) as a real line of length n = 8 N_g, whose half spectrum
+// X[0..n/2] comes from one n/2-point complex FFT of the packed even/odd samples:
+//   Z = FFT(x[2j] + i x[2j+1]),  E_k = (Z_k + conj Z_{n/2-k}) / 2,  O_k = (Z_k - conj Z_{n/2-k}) / 2i,
+//   X_k = E_k + e^{-2 pi i k / n} O_k.
+template <typename T, int NG>
+__device__ __forceinline__ void xpass_row(const M2LArgs<T>& a, int yr, int zr, const int* s_src,
+                                          cplx<T> (&X)[4 * NG + 1]) {
+  constexpr int n = 8 * NG, h = n / 2, M = NG * NG * NG;
+  cplx<T> z[h];
+#pragma unroll
+  for (int j = 0; j < h; ++j) z[j] = {T(0), T(0)};
+  const int bz = zr / NG, kz = zr % NG, by = yr / NG, jy = yr % NG;
+#pragma unroll
+  for (int bx = 0; bx < 6; ++bx) {
+    const int src = s_src[bx + 6 * (by + 6 * bz)];
+    if (src >= 0) {
+      const T* gsrc = a.gridlet + size_t(src) * M + (kz * NG + jy) * NG;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        const int xx = bx * NG + i;  // compile-time: even samples real, odd imaginary
+        if (xx % 2 == 0) z[xx / 2].re = gsrc[i];
+        else z[xx / 2].im = gsrc[i];
+      }
+    }
+  }
+  cplx<T> Z[h];
+  fft<h, -1>(z, Z);
+  static_for<0, h + 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const cplx<T> zk = Z[k % h], zc = Z[(h - k) % h];
+    const cplx<T> e = {T(0.5) * (zk.re + zc.re), T(0.5) * (zk.im - zc.im)};
+    const cplx<T> o = {T(0.5) * (zk.im + zc.im), T(0.5) * (zc.re - zk.re)};
+    const cplx<T> wo = twiddle<k, n, -1>(o);
+    X[k] = {e.re + wo.re, e.im + wo.im};
+  });
+}
+
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
   using S = M2LShape<T, NG>;
@@ -344,17 +382,14 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
       for (int zz = 0; zz < NG; ++zz) pr[r][zz] = pi[r][zz] = T(0);
 
     for (int z0 = 0; z0 < W; z0 += ZB) {
-      // x: rows (zb, y) of the slab, y fastest, two rows per line
-      for (int w = tid; w < ZB * W / 2; w += NT) {
-        const int r0 = 2 * w, zb = r0 / W, y0 = r0 % W;
-        cplx<T> A[H], B[H];
-        xpass_rows<T, NG>(a, y0, z0 + zb, s_src, A, B);
-        cplx<T>* row = slab + (size_t(zb) * n + y0) * H;
+      // x: rows (zb, y) of the slab, y fastest, one real row per thread
+      for (int w = tid; w < ZB * W; w += NT) {
+        const int zb = w / W, yr = w % W;
+        cplx<T> X[H];
+        xpass_row<T, NG>(a, yr, z0 + zb, s_src, X);
+        cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
 #pragma unroll
-        for (int k = 0; k < H; ++k) {
-          row[k] = A[k];
-          row[H + k] = B[k];
-        }
+        for (int k = 0; k < H; ++k) row[k] = X[k];
       }
       __syncthreads();
       // y: columns (zb, kx); rows y >= 6 N_g are zero
