@@ -254,6 +254,29 @@ def main():
                "fp64": {"value": round(args.n / (r4d["ms_per_step"] * 1e-3), 1),
                         "ms_per_step": round(r4d["ms_per_step"], 4), "force_err_rms": e4d[0]}}
 
+    # latency of the small uniform problem (4096 particles, uniform depth 3, N_g = 4, FP64)
+    from synth import uniform_cube
+    pu = uniform_cube(4096, 1000)
+    xu, yu, zu, mu = (torch.tensor(a_, dtype=torch.float64, device="cuda")
+                      for a_ in (pu.x, pu.y, pu.z, pu.m))
+    planu = hpm.Plan(hpm.Problem(ng=4, precision="f64", uniform_depth=3, softening=1e-3),
+                     xu, yu, zu)
+    outu = [torch.empty(pu.n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    lat_u = []
+    for k in range(220):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        planu.rebuild(xu, yu, zu)
+        planu.execute(mu, *outu)
+        e1.record()
+        e1.synchronize()
+        if k >= 20:
+            lat_u.append(e0.elapsed_time(e1))
+    planu.close()
+    small = {"workload": "uniform cube N=4096, uniform depth 3, N_g=4, eps=1e-3, FP64",
+             "solves": len(lat_u), "latency_ms": {"p50": round(float(np.percentile(lat_u, 50)), 4),
+                                                  "p99": round(float(np.percentile(lat_u, 99)), 4)}}
+
     rec = {
         "metric": "HPM particles/s (FP32 vs FP64 GPU) at 1e-4 force err; solve p50/p99 latency",
         "value": round(value, 1), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -277,6 +300,7 @@ def main():
         "roofline": roofline,
         "kernels": {"yukawa_f32": yukawa},
         "other_orders": {"ng4": ng4},
+        "small_solve": small,
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
     if not args.no_cpu_baseline:

@@ -1,5 +1,5 @@
-// Interaction-zone slots of a target cell (Sec. 2.1), shared by the source-to-target kernels and
-// by the enumeration of cubes that lie inside coarser leaves.
+// The 6^3 block of level-l cube positions around a parent of targets (Sec. 2.1), used by the
+// enumeration of cubes that lie inside coarser leaves and by the per-parent source tables.
 //
 // A target T at level l >= 2 with parent P sees the 6^3 block of level-l cubes around P: block
 // cube b = (bx, by, bz) in [0, 6)^3 sits at integer position 2 (P - 1) + b. The 27 cubes within
@@ -45,17 +45,6 @@ __device__ __forceinline__ IzSlot block_cube(int px, int py, int pz, int l, int 
     r.key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
   }
   return r;
-}
-
-// Interaction-zone slot of target (tx, ty, tz) at level l with parent par: its parent's block
-// cube, unless the cube is one of the 27 around the target.
-__device__ __forceinline__ IzSlot iz_slot(int tx, int ty, int tz, int l, int par, int slot,
-                                          const int* nbr27, const int* flags, const int* child8) {
-  const int bx = slot % 6, by = (slot / 6) % 6, bz = slot / 36;
-  const int cx = tx & 1, cy = ty & 1, cz = tz & 1;
-  const bool near = abs(bx - 2 - cx) <= 1 && abs(by - 2 - cy) <= 1 && abs(bz - 2 - cz) <= 1;
-  if (near) return IzSlot{-1, -1, 0u};
-  return block_cube(tx >> 1, ty >> 1, tz >> 1, l, par, slot, nbr27, flags, child8);
 }
 
 // A cube's identifier across levels: its level-l Morton key below a leading 1 bit at 3 l
