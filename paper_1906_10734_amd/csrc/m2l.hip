@@ -438,11 +438,10 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
       __syncthreads();
     }
 
-    // The inverse transforms run in double precision on the accumulated FP32 planes: their
-    // rounding, relative to the large smooth potential of the interaction zone, would otherwise
-    // dominate the error of the potential's variation across the target. Only N_g outputs per
-    // axis are wanted, so both are direct sums (N_g of n terms per line) against a double
-    // twiddle table.
+    // The inverse y transform runs in FP32 (the N_g target values of each column kept) and the
+    // inverse x transform in double precision as direct sums against a double twiddle table:
+    // the last rounding then happens at the magnitude of the potential's variation across the
+    // target, not at that of the interaction zone's large smooth potential.
     static_assert(ZB >= NG, "the slab buffer holds the N_g accumulated planes");
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -454,22 +453,18 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     }
     __syncthreads();
     // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n}, Y = (2 + c_y) N_g + yy
-    const int Yt = (2 + t.cy) * NG;
-    for (int u = tid; u < NG * NG * H; u += NT) {
-      const int kx = u % H, yy = (u / H) % NG, zz = u / (H * NG);
-      const int Y = Yt + yy;
+    for (int w = tid; w < NG * H; w += NT) {
+      const int kx = w % H, zz = w / H;
       const cplx<T>* col = slab + size_t(zz) * ENT + kx;
-      double ar = 0.0, ai = 0.0;
-      int m = 0;
-      for (int ky = 0; ky < n; ++ky) {
-        const cplx<T> f = col[size_t(ky) * H];
-        const cplx<double> w = s_tw[m];
-        ar += double(f.re) * w.re - double(f.im) * w.im;
-        ai += double(f.re) * w.im + double(f.im) * w.re;
-        m += Y;
-        if (m >= n) m -= n;
+      cplx<T> in[n], out[n];
+#pragma unroll
+      for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
+      fft<n, +1>(in, out);
+#pragma unroll
+      for (int yy = 0; yy < NG; ++yy) {
+        const cplx<T> o = t.cy ? out[3 * NG + yy] : out[2 * NG + yy];
+        red[(size_t(zz) * NG + yy) * H + kx] = {double(o.re), double(o.im)};
       }
-      red[(size_t(zz) * NG + yy) * H + kx] = {ar, ai};
     }
     __syncthreads();
     // x^-1 (Hermitian half spectrum): out = sum_k w_k Re(F_k e^{+2 pi i k X / n}), w_k = 1 at
