@@ -5,10 +5,14 @@ TEST INFRASTRUCTURE ONLY (parity oracle); the product never imports this module.
 Steps (Sec. 1, enumerated list, and Sec. 2):
   P2M  leaf effective masses from Cartesian multipoles: Eq. (2) then Eq. (5).
   M2M  child-to-parent translation with the matrices T^C (Sec. 2.3).
-  M2L  source-to-target over the 189-cube interaction zone (Sec. 2.1). Two modes:
+  M2L  source-to-target over the 189-cube interaction zone (Sec. 2.1). Three modes:
          "direct": the definition, sum_Q sum_q g(r_p - r_q) M_q over every IZ gridlet node;
          "fft":    the method, one zero-padded (8 N_g)^3 FFT of the IZ effective masses times the
-                   transform of the exact lattice Green function (Eq. 1), target gridlet read out.
+                   transform of the exact lattice Green function (Eq. 1), target gridlet read out;
+         "cells":  the cell-by-cell alternative the paper compares against (Sec. 2.5): for each
+                   source cube a zero-padded (2 N_g)^3 transform times the transform of the
+                   Green function at that cube's offset, the products summed and transformed
+                   back once.
   L2L  parent-to-child: potential multipoles Eq. (6), polynomial Eq. (7) at the child nodes.
   L2P  Eq. (7) at each particle, its gradient for the acceleration.
   P2P  near zone (27 cubes) by direct summation (Sec. 1, item 1).
@@ -144,7 +148,8 @@ def pair_sum(tpos: np.ndarray, tids: np.ndarray, spos: np.ndarray, sm: np.ndarra
 # ---------------------------------------------------------------------------------------------
 
 class HPM:
-    """One HPM evaluation. ``mode`` selects the M2L route: "fft" (the method) or "direct"."""
+    """One HPM evaluation. ``mode`` selects the M2L route: "fft" (the method), "direct" (the
+    definition) or "cells" (cell-by-cell transforms)."""
 
     def __init__(self, x, y, z, m, prob: Problem, mode: str = "fft"):
         green.check(prob.kernel, prob.screening)
@@ -220,7 +225,42 @@ class HPM:
             return np.zeros(self.M)
         if self.mode == "direct":
             return self._m2l_direct(l, coord, sources)
+        if self.mode == "cells":
+            return self._m2l_cells(l, coord, sources)
         return self._m2l_fft(l, coord, sources)
+
+    def _green_offset(self, l: int, d: tuple) -> np.ndarray:
+        """Transform of the (2 N_g)^3 cyclic Green array for source cube offset d (cube units):
+        entry u holds g(h |d N_g + u_c|) with u_c = u for u < N_g and u - 2 N_g otherwise, so that
+        every target-minus-source node offset of that cube pair, d N_g + (p - q) with
+        |p - q| < N_g, is stored once (no wrap-around)."""
+        key = ("cells", l, d)
+        if key not in self._ghat:
+            ng = self.ng
+            h = self.tree.cube_size(l) / ng
+            u = np.arange(2 * ng)
+            uc = np.where(u < ng, u, u - 2 * ng).astype(np.float64)
+            oz, oy, ox = np.meshgrid(d[2] * ng - uc, d[1] * ng - uc, d[0] * ng - uc, indexing="ij")
+            r2 = (ox * ox + oy * oy + oz * oz) * h * h
+            g = tables.green_physical(r2, self.prob.gconst, self.prob.softening, self.prob.kernel,
+                                      self.prob.screening)
+            self._ghat[key] = sfft.rfftn(g)
+        return self._ghat[key]
+
+    def _m2l_cells(self, l, coord, sources):
+        """Cell-by-cell: sum over sources of rfft(source padded to (2 N_g)^3) * Ghat_d, one
+        inverse transform, the N_g^3 corner read out (target node p, source node q: the cyclic
+        index of p - q is the stored offset d N_g - (p - q) read as (q - p) mod 2 N_g)."""
+        ng = self.ng
+        acc = None
+        for q, g in sources:
+            d = tuple(int(v) for v in (np.asarray(q) - coord))
+            pad = np.zeros((2 * ng, 2 * ng, 2 * ng))
+            pad[:ng, :ng, :ng] = g.reshape(ng, ng, ng)
+            term = sfft.rfftn(pad) * self._green_offset(l, d)
+            acc = term if acc is None else acc + term
+        out = sfft.irfftn(acc, s=(2 * ng, 2 * ng, 2 * ng))
+        return out[:ng, :ng, :ng].ravel().copy()
 
     def _m2l_direct(self, l, coord, sources):
         t, ng = self.tree, self.ng

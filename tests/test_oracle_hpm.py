@@ -100,3 +100,16 @@ def test_uniform_sphere_closed_form():
     r = np.linalg.norm(pos - 0.5, axis=1)
     want = -(3 * R * R - r * r) / (2 * R ** 3)
     assert potential_error(phi, want) < 3.0 / np.sqrt(n)
+
+
+@pytest.mark.parametrize("kernel,screening", [("newton", 0.0), ("yukawa", 0.2)])
+def test_cell_by_cell_transforms_equal_direct_mode(kernel, screening):
+    # Sec. 2.5's alternative (a padded (2 N_g)^3 transform per source cube, products summed and
+    # transformed back once) computes the same source-to-target sums as the definition.
+    p = plummer_sphere(1500, 21, a=0.1)
+    prob = hpm.Problem(ng=4, softening=1e-3, leaf_capacity=16, max_depth=7, kernel=kernel,
+                       screening=screening)
+    phi_c, acc_c, _ = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="cells")
+    phi_d, acc_d, _ = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="direct")
+    assert potential_error(phi_c, phi_d) < 1e-13
+    assert force_error(acc_c, acc_d)[0] < 1e-11
