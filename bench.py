@@ -69,13 +69,13 @@ def traffic_from_profile(ng: int, prec: str):
 
 
 def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, kernel="newton",
-             screening=0.0):
+             screening=0.0, m2l="grid"):
     """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
     p = parts.astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
     x, y, z, m = (torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
     prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3,
-                       kernel=kernel, screening=screening)
+                       kernel=kernel, screening=screening, m2l=m2l)
     plan = hpm.Plan(prob, x, y, z)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(warmup):
@@ -165,6 +165,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--profile", action="store_true",
                     help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--m2l", choices=("grid", "cells"), default="grid",
+                    help="source-to-target route of the --profile run")
+    ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
+                    help="precision of the --profile run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -176,16 +180,19 @@ def main():
 
     parts = plummer_sphere(args.n, 1001)
     ng = args.ng
-    r32, out32, dev32 = run_path(hpm, torch, parts, "f32", ng, args.steps, args.warmup)
     if args.profile:
+        r32, _, _ = run_path(hpm, torch, parts, args.precision, ng, args.steps, args.warmup,
+                             m2l=args.m2l)
         src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "ms_per_step": r32["ms_per_step"],
-                          "stages": r32["stages"], "copy_bytes": 2 * src.numel() * 4}))
+        print(json.dumps({"profile_run": True, "m2l": args.m2l, "precision": args.precision,
+                          "ms_per_step": r32["ms_per_step"], "stages": r32["stages"],
+                          "copy_bytes": 2 * src.numel() * 4}))
         return
+    r32, out32, dev32 = run_path(hpm, torch, parts, "f32", ng, args.steps, args.warmup)
     r64, out64, dev64 = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1)
 
     # accuracy: FP64 direct sum on a 4096-particle subset of the FP64 positions
@@ -254,6 +261,22 @@ def main():
                "fp64": {"value": round(args.n / (r4d["ms_per_step"] * 1e-3), 1),
                         "ms_per_step": round(r4d["ms_per_step"], 4), "force_err_rms": e4d[0]}}
 
+    # the cell-by-cell source-to-target route (Sec. 2.5) on the same workload: whole-solve rate,
+    # its source-to-target stage time beside the padded grid's, and the force error
+    def stage(r, k):
+        return r["stages"][k] / max(r["stages"]["n_exec"], 1)
+    rc, oc, _ = run_path(hpm, torch, parts, "f32", ng, args.steps, 1, m2l="cells")
+    rcd, ocd, _ = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1, m2l="cells")
+    pg = float(np.log2(ng))
+    routes = {"cells_f32": {"value": round(args.n / (rc["ms_per_step"] * 1e-3), 1),
+                            "ms_per_step": round(rc["ms_per_step"], 4),
+                            "m2l_ms": round(stage(rc, "m2l"), 4), "force_err_rms": ferr(oc)[0]},
+              "cells_f64": {"value": round(args.n / (rcd["ms_per_step"] * 1e-3), 1),
+                            "ms_per_step": round(rcd["ms_per_step"], 4),
+                            "m2l_ms": round(stage(rcd, "m2l"), 4), "force_err_rms": ferr(ocd)[0]},
+              "grid_m2l_ms": {"f32": round(stage(r32, "m2l"), 4), "f64": round(stage(r64, "m2l"), 4)},
+              "paper_count_ratio_grid_over_cells": round(0.34 * (pg + 3) / (pg + 1), 3)}
+
     # latency of the small uniform problem (4096 particles, uniform depth 3, N_g = 4, FP64)
     from synth import uniform_cube
     pu = uniform_cube(4096, 1000)
@@ -300,6 +323,7 @@ def main():
         "roofline": roofline,
         "kernels": {"yukawa_f32": yukawa},
         "other_orders": {"ng4": ng4},
+        "m2l_routes": routes,
         "small_solve": small,
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)

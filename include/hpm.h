@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 2
+#define HPM_ABI_VERSION 3
 
 typedef enum {
   HPM_OK = 0,
@@ -63,6 +63,18 @@ typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
 typedef enum { HPM_KERNEL_NEWTON = 0, HPM_KERNEL_YUKAWA = 1 } hpm_kernel;
 
 /*
+ * Route of the source-to-target step (both compute the same sums, Sec. 2.1 and Sec. 2.5):
+ *   HPM_M2L_GRID   one zero-padded (8 N_g)^3 convolution per target over its whole interaction
+ *                  zone (the method);
+ *   HPM_M2L_CELLS  cell-by-cell: each source cube's gridlet zero-padded to (2 N_g)^3 and
+ *                  transformed once per solve, multiplied per (target, source) pair by the
+ *                  transform of the Green function at that pair's cube offset, the products
+ *                  summed and transformed back once per target (the alternative the paper
+ *                  weighs in Sec. 2.5; kept for comparison).
+ */
+typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1 } hpm_m2l_mode;
+
+/*
  * Problem description.
  *   ng             gridlet points per axis (Sec. 2): 2, 3, 4 or 6 (the FFT edge 8 N_g must
  *                  factor into 2s and 3s). N_g = 8 is built but currently returns
@@ -78,6 +90,7 @@ typedef enum { HPM_KERNEL_NEWTON = 0, HPM_KERNEL_YUKAWA = 1 } hpm_kernel;
  *   gconst         G > 0.
  *   box_lo, box_size  the cubic root cell (level 0), box_size > 0 (Sec. 1).
  *   kernel         an hpm_kernel value.
+ *   m2l_mode       an hpm_m2l_mode value.
  *   screening      lam > 0 of HPM_KERNEL_YUKAWA (ignored for HPM_KERNEL_NEWTON).
  */
 typedef struct {
@@ -92,7 +105,7 @@ typedef struct {
   double box_lo[3];
   double box_size;
   int32_t kernel;
-  int32_t reserved;   /* must be 0 */
+  int32_t m2l_mode;
   double screening;
 } hpm_problem;
 

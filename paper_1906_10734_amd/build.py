@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhpm.so")
-SOURCES = ["api.cpp", "tables.cpp", "tree.hip", "upsweep.hip", "m2l.hip", "downsweep.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "tree.hip", "upsweep.hip", "m2l.hip", "m2l_cells.hip", "downsweep.hip"]
 ARCH = os.environ.get("HPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -44,7 +44,8 @@ static void check_problem(const hpm_problem* pr) {
   if (!(std::isfinite(pr->softening) && pr->softening >= 0.0)) fail(HPM_ERR_INVALID_ARG, "softening must be >= 0");
   if (!(std::isfinite(pr->gconst) && pr->gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "gconst must be > 0");
   check_kernel(pr->kernel, pr->screening);
-  if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
+  if (pr->m2l_mode != HPM_M2L_GRID && pr->m2l_mode != HPM_M2L_CELLS)
+    fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID or HPM_M2L_CELLS");
   if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
   if (pr->uniform_depth == 0) {
     if (pr->leaf_capacity < 1) fail(HPM_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
@@ -83,6 +84,13 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   p.moments.reserve(rows * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
   p.m2l_mean.reserve(cells * sizeof(double));
+  if (p.prob.m2l_mode == HPM_M2L_CELLS && p.nlevels > 2) {
+    const size_t spec = cell_modes(p.ng) * 2 * p.elem;
+    const size_t ntg = cells - size_t(p.level_off[2]);
+    p.cell_src.reserve((ntg + size_t(p.nvirt) + 1) * spec);  // + a zero row
+    p.cell_tgt.reserve(ntg * spec);
+    build_cell_parents(p, s);
+  }
   build_near_lists(p, s);
   if (p.timing) {
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));
@@ -143,7 +151,8 @@ static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, 
   if (ev) HPM_HIP(hipEventRecord(ev[1], s));
   for (int l = p.nlevels - 2; l >= 2; --l) launch_m2m(p, l, s);
   if (ev) HPM_HIP(hipEventRecord(ev[2], s));
-  launch_m2l(p, s);
+  if (p.prob.m2l_mode == HPM_M2L_CELLS) launch_m2l_cells(p, s);
+  else launch_m2l(p, s);
   if (ev) HPM_HIP(hipEventRecord(ev[3], s));
   for (int l = 2; l < p.nlevels; ++l) launch_l2l(p, l, s);  // level 2: re-centring only
   if (ev) HPM_HIP(hipEventRecord(ev[4], s));

@@ -85,8 +85,11 @@ struct Tables {
   DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
   DevBuf gxy;    // [levels 2..L][4 N_g][n/2+1][n/2+1]: Green function transformed along x and y
                  // only, at z offsets d < 4 N_g, [d][ky][kx], / n^2
+  DevBuf gcell;  // cell-by-cell route only: [levels 2..L][343 offsets][(2N_g)^2 (N_g+1)] complex,
+                 // transform of the cyclic Green array of each source cube offset, / (2 N_g)^3
   int kpad = 0, mpad = 0;
   int ghat_levels = 0;
+  int gcell_levels = 0;
 };
 
 struct Plan {
@@ -132,6 +135,13 @@ struct Plan {
   int64_t p2p_pairs = 0;
   DevBuf m2l_work;
   int m2l_slots = 0;
+  // cell-by-cell route: source spectra [cells of levels >= 2, then virtual cubes][modes] and the
+  // accumulated target spectra [cells of levels >= 2][modes]
+  DevBuf cell_src, cell_tgt;
+  // the split parents (cells of levels 1 .. L-2 with children) in id order, and where each
+  // parent level starts in that list (cell_pbeg[L-1] is its length)
+  DevBuf cell_plist, cell_pflag, cell_ppos;
+  int cell_pbeg[kMaxLevelsHost + 1] = {0};
   Tables tab;
   // scratch for the tree build
   DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff;
@@ -139,6 +149,7 @@ struct Plan {
   // synchronisation (counts that size the next step of the build, input error flags)
   static constexpr int kBoxWords = 16;
   static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
+  static constexpr int kBoxCellLevels = 4;  // words 5 .. 4 + L-1: split-parent list bounds
   int* hbox = nullptr;
   int* dbox = nullptr;
 
@@ -175,6 +186,13 @@ void launch_m2m(Plan& p, int level, hipStream_t s);
 // ---- m2l.hip -------------------------------------------------------------------------------------
 void launch_m2l(Plan& p, hipStream_t s);
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
+
+// ---- m2l_cells.hip -------------------------------------------------------------------------------
+// modes of one cell spectrum, (2 N_g)^2 (N_g + 1)
+size_t cell_modes(int ng);
+// the list of split parents that the cell-by-cell route visits (with the tree build)
+void build_cell_parents(Plan& p, hipStream_t s);
+void launch_m2l_cells(Plan& p, hipStream_t s);
 
 // ---- downsweep.hip -------------------------------------------------------------------------------
 void build_near_lists(Plan& p, hipStream_t s);

@@ -1,0 +1,411 @@
+// Source-to-target (M2L) cell by cell: the alternative to the single padded grid that the paper
+// weighs and sets aside (Sec. 2.5). It computes the same sums as the (8 N_g)^3 route: every
+// target node receives G(target node - source node) times each effective mass of its 189
+// interaction-zone cubes (Sec. 2.1, Eq. 1).
+//
+// Each source cube's gridlet, zero padded to C^3 with C = 2 N_g, is transformed once per solve.
+// For a target and one of its sources at cube offset d = source - target (|d|_inf in 2..3), the
+// C^3 cyclic array whose entry u holds g(h |d N_g - u_c|), where u_c = u for u < N_g and
+// u - C otherwise, convolved cyclically with the padded source gives the potential at the
+// target's N_g^3 nodes in the corner [0, N_g)^3: every node offset d N_g + (p - q) of the pair,
+// |p - q| < N_g per axis, lands on a distinct entry, so nothing wraps. The transforms of these
+// arrays (one per offset and level, divided by C^3) are constant tables. The sum over sources is
+// taken in frequency space, then one pruned inverse transform per target keeps the corner.
+//
+// The paper's operation count charges one padded transform per (target, source) pair; here a
+// source's transform is shared by every target that sees it (up to 27 parents' blocks), so what
+// remains per pair is the pointwise product, C^2 (N_g + 1) complex multiply-adds.
+//
+// Kernels:
+//   k_cells_forward   one workgroup per source gridlet (cells of levels >= 2 and virtual cubes):
+//                     half spectrum [kz < C][ky < C][kx <= N_g] by separable direct sums.
+//   k_cells_accum     one thread per (parent, mode), one launch per parent level. The Green table
+//                     of the level is shared by every parent, so a workgroup stages its chunk of
+//                     modes in LDS and runs several parents side by side; the 8 children of a
+//                     parent share the 6^3 block of sources, so for each source plane bz a
+//                     thread keeps that plane's 36 spectra in registers and applies each Green
+//                     entry to every child and slot it joins (up to 4 of them). Only the split
+//                     parents are visited, from a list built with the tree.
+//   k_cells_inverse   one workgroup per target: pruned inverse (z, then y, then the Hermitian x
+//                     sum), the N_g^3 corner written as the target's gridlet potentials. The
+//                     inverse runs in double whatever the plan's precision (it is a small part of
+//                     the work); in FP32 plans the result is stored as its mean (double) plus the
+//                     zero-mean gridlet, so that the large common value of a target's potentials
+//                     does not cost the precision of their differences.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "fft.h"
+#include "hpm_internal.h"
+
+#include <algorithm>
+
+namespace hpm {
+
+template <int NG>
+struct CellShape {
+  static constexpr int C = 2 * NG;
+  static constexpr int HC = NG + 1;
+  static constexpr int K = C * C * HC;  // modes, [kz][ky][kx]
+  static constexpr int M = NG * NG * NG;
+  static constexpr int OFFS = 343;      // d in [-3, 3]^3, index (dx+3) + 7 (dy+3) + 49 (dz+3)
+};
+
+// e^{sign 2 pi i j / C} for j < C, in LDS (double sincospi, rounded once to T)
+template <typename T, int C>
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw, double sign) {
+  const int j = threadIdx.x;
+  if (j < C) {
+    double s, c;
+    sincospi(2.0 * j / C, &s, &c);
+    tw[j] = {T(c), T(sign * s)};
+  }
+}
+
+template <typename T>
+struct CellArgs {
+  int first_cell;    // id of the first cell of level 2: sources and targets are indexed from it
+  int nsources;      // cells of levels >= 2, then the virtual cubes (row nsources of the
+                     // source spectra is zero)
+  int first_parent;  // first row of the block table (cells of level 1)
+  int nparents;
+  int nlevels;
+  const int* level_off;
+  const int* child8;
+  const int* blocks;
+  const T* gridlet;
+  T* local;
+  const cplx<T>* gcell;  // [level - 2][343][K]
+  cplx<T>* sspec;        // [source - first_cell][K]
+  cplx<T>* tspec;        // [target - first_cell][K]
+  double* m2l_mean;      // [cells]: mean of each target's result, FP32 plans
+};
+
+template <typename T, int NG>
+__global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
+  using S = CellShape<NG>;
+  constexpr int C = S::C, HC = S::HC, K = S::K, M = S::M;
+  __shared__ cplx<T> tw[C];
+  __shared__ T s_g[M];
+  __shared__ cplx<T> s_a1[NG * NG * HC];  // [z][y][kx]
+  __shared__ cplx<T> s_a2[NG * C * HC];   // [z][ky][kx]
+  const int src = blockIdx.x, tid = threadIdx.x;
+  if (src == a.nsources) {  // the zero row that empty block slots read
+    for (int e = tid; e < K; e += 256) a.sspec[size_t(src) * K + e] = {T(0), T(0)};
+    return;
+  }
+  load_twiddles<T, C>(tw, -1.0);
+  const T* g = a.gridlet + size_t(a.first_cell + src) * M;
+  for (int e = tid; e < M; e += 256) s_g[e] = g[e];
+  __syncthreads();
+  for (int e = tid; e < NG * NG * HC; e += 256) {
+    const int kx = e % HC, row = e / HC;  // row = z * NG + y
+    cplx<T> acc = {T(0), T(0)};
+    int m = 0;
+#pragma unroll
+    for (int x = 0; x < NG; ++x) {
+      const T v = s_g[row * NG + x];
+      acc.re += v * tw[m].re;
+      acc.im += v * tw[m].im;
+      m += kx;
+      if (m >= C) m -= C;
+    }
+    s_a1[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < NG * C * HC; e += 256) {
+    const int kx = e % HC, ky = (e / HC) % C, z = e / (HC * C);
+    cplx<T> acc = {T(0), T(0)};
+    int m = 0;
+#pragma unroll
+    for (int y = 0; y < NG; ++y) {
+      acc = cadd(acc, cmul(s_a1[(z * NG + y) * HC + kx], tw[m]));
+      m += ky;
+      if (m >= C) m -= C;
+    }
+    s_a2[e] = acc;
+  }
+  __syncthreads();
+  cplx<T>* out = a.sspec + size_t(src) * K;
+  for (int e = tid; e < K; e += 256) {
+    const int col = e % (C * HC), kz = e / (C * HC);  // col = ky * HC + kx
+    cplx<T> acc = {T(0), T(0)};
+    int m = 0;
+#pragma unroll
+    for (int z = 0; z < NG; ++z) {
+      acc = cadd(acc, cmul(s_a2[z * C * HC + col], tw[m]));
+      m += kz;
+      if (m >= C) m -= C;
+    }
+    out[e] = acc;
+  }
+}
+
+// Mode chunk of one workgroup of k_cells_accum and the parents it runs side by side: a chunk of
+// the Green table of a level (343 offsets x KM modes) is 44 KB of LDS in either precision.
+template <typename T>
+struct AccumShape {
+  static constexpr int KM = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int PP = 256 / KM;
+};
+
+// One launch per parent level; workgroup (chunk, group): modes [chunk KM, chunk KM + KM) of the
+// split parents plist[pbeg + group PP ...], one (parent, mode) per thread.
+template <typename T, int NG>
+__global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, const int* plist,
+                                                     int pbeg, int pend) {
+  using S = CellShape<NG>;
+  using A = AccumShape<T>;
+  constexpr int K = S::K, KM = A::KM, PP = A::PP;
+  static_assert(K % KM == 0, "mode chunks tile the spectrum");
+  __shared__ cplx<T> s_g[S::OFFS * KM];  // [offset][mode]
+  __shared__ int s_src[PP * 216];         // source spectrum rows of the group's blocks
+  const int tid = threadIdx.x, m = tid % KM, pp = tid / KM;
+  const int k0 = blockIdx.x * KM, k = k0 + m;
+  const cplx<T>* G = a.gcell + size_t(tlevel - 2) * S::OFFS * K + k0;
+  for (int e = tid; e < S::OFFS * KM; e += 256) s_g[e] = G[size_t(e / KM) * K + e % KM];
+  // every group iteration runs in all threads of the workgroup (uniform trip count)
+  for (int grp = blockIdx.y; pbeg + grp * PP < pend; grp += gridDim.y) {
+    __syncthreads();  // the previous group's slot rows are consumed
+    for (int e = tid; e < PP * 216; e += 256) {
+      const int q = pbeg + grp * PP + e / 216;
+      int v = a.nsources;  // the zero row
+      if (q < pend) {
+        const int src = a.blocks[size_t(plist[q] - a.first_parent) * 216 + e % 216];
+        if (src >= 0) v = src - a.first_cell;
+      }
+      s_src[e] = v;
+    }
+    __syncthreads();
+    const int idx = pbeg + grp * PP + pp;
+    if (idx >= pend) continue;
+    const int par = plist[idx];
+    const int* row = s_src + pp * 216;
+    cplx<T> acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = {T(0), T(0)};
+    for (int bz = 0; bz < 6; ++bz) {
+      cplx<T> sp[36];
+#pragma unroll
+      for (int j = 0; j < 36; ++j) sp[j] = a.sspec[size_t(row[bz * 36 + j]) * K + k];
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const int dz = bz - 2 - cz;  // in [-3, 3]
+        const bool zfar = dz < -1 || dz > 1;
+        const cplx<T>* gz = s_g + (49 * (dz + 3)) * KM + m;
+#pragma unroll
+        for (int dy = -3; dy <= 3; ++dy) {
+#pragma unroll
+          for (int dx = -3; dx <= 3; ++dx) {
+            const bool far_xy = dx < -1 || dx > 1 || dy < -1 || dy > 1;
+            if (!far_xy && !zfar) continue;  // the 27 offsets of the near zone
+            const cplx<T> gv = gz[((dx + 3) + 7 * (dy + 3)) * KM];
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+#pragma unroll
+              for (int cx = 0; cx < 2; ++cx) {
+                const int by = dy + 2 + cy, bx = dx + 2 + cx;
+                if (by < 0 || by > 5 || bx < 0 || bx > 5) continue;
+                cplx<T>& o = acc[cx | (cy << 1) | (cz << 2)];
+                const cplx<T> sv = sp[by * 6 + bx];
+                o.re = fma(gv.re, sv.re, o.re);
+                o.re = fma(-gv.im, sv.im, o.re);
+                o.im = fma(gv.re, sv.im, o.im);
+                o.im = fma(gv.im, sv.re, o.im);
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int t = a.child8[size_t(par) * 8 + c];
+      if (t >= 0) a.tspec[size_t(t - a.first_cell) * K + k] = acc[c];
+    }
+  }
+}
+
+template <typename T, int NG>
+__global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
+  using S = CellShape<NG>;
+  constexpr int C = S::C, HC = S::HC, K = S::K, M = S::M;
+  constexpr bool split = sizeof(T) == 4;
+  __shared__ cplx<double> tw[C];
+  __shared__ cplx<double> s_f[K];              // [kz][ky][kx]
+  __shared__ cplx<double> s_b1[NG * C * HC];   // [z][ky][kx], z < N_g
+  __shared__ cplx<double> s_b2[NG * NG * HC];  // [z][y][kx]
+  __shared__ double s_out[M];
+  __shared__ double s_red[4];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  load_twiddles<double, C>(tw, 1.0);
+  const cplx<T>* f = a.tspec + size_t(t) * K;
+  for (int e = tid; e < K; e += 256) s_f[e] = {double(f[e].re), double(f[e].im)};
+  __syncthreads();
+  for (int e = tid; e < NG * C * HC; e += 256) {
+    const int col = e % (C * HC), z = e / (C * HC);
+    cplx<double> acc = {0.0, 0.0};
+    int m = 0;
+#pragma unroll
+    for (int kz = 0; kz < C; ++kz) {
+      acc = cadd(acc, cmul(s_f[kz * C * HC + col], tw[m]));
+      m += z;
+      if (m >= C) m -= C;
+    }
+    s_b1[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < NG * NG * HC; e += 256) {
+    const int kx = e % HC, y = (e / HC) % NG, z = e / (HC * NG);
+    cplx<double> acc = {0.0, 0.0};
+    int m = 0;
+#pragma unroll
+    for (int ky = 0; ky < C; ++ky) {
+      acc = cadd(acc, cmul(s_b1[(z * C + ky) * HC + kx], tw[m]));
+      m += y;
+      if (m >= C) m -= C;
+    }
+    s_b2[e] = acc;
+  }
+  __syncthreads();
+  const int g = a.first_cell + t;
+  T* out = a.local + size_t(g) * M;
+  double part = 0.0;
+  for (int e = tid; e < M; e += 256) {
+    const int x = e % NG, zy = e / NG;  // zy = z * N_g + y
+    // real part of the Hermitian sum over kx in (-N_g, N_g]: the kx = 0 and kx = N_g (Nyquist)
+    // terms once, the others twice
+    double acc = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int kx = 0; kx < HC; ++kx) {
+      const cplx<double> v = s_b2[zy * HC + kx];
+      const double re = v.re * tw[m].re - v.im * tw[m].im;
+      acc += (kx == 0 || kx == NG) ? re : 2.0 * re;
+      m += x;
+      if (m >= C) m -= C;
+    }
+    if constexpr (split) {
+      s_out[e] = acc;
+      part += acc;
+    } else {
+      out[e] = T(acc);
+    }
+  }
+  if constexpr (split) {
+    part = wave_sum(part);
+    if ((tid & 63) == 0) s_red[tid >> 6] = part;
+    __syncthreads();
+    const double mean = (s_red[0] + s_red[1] + s_red[2] + s_red[3]) * (1.0 / M);
+    for (int e = tid; e < M; e += 256) out[e] = T(s_out[e] - mean);
+    if (tid == 0) a.m2l_mean[g] = mean;
+  }
+}
+
+template <typename T, int NG>
+static void cells_t(Plan& p, hipStream_t s) {
+  using S = CellShape<NG>;
+  p.m2l_split = sizeof(T) == 4;
+  if (p.nlevels <= 2) return;
+  CellArgs<T> a;
+  a.first_cell = p.level_off[2];
+  const int ntargets = int(p.ncells) - a.first_cell;
+  if (ntargets <= 0) return;
+  a.nsources = ntargets + int(p.nvirt);
+  a.first_parent = p.blocks_first;
+  a.nparents = p.level_off[p.nlevels - 1] - p.blocks_first;
+  a.nlevels = p.nlevels;
+  a.level_off = p.dlevel.as<int>();
+  a.child8 = p.child8.as<int>();
+  a.blocks = p.blocks.as<int>();
+  a.gridlet = p.gridlet.as<T>();
+  a.local = p.local.as<T>();
+  a.gcell = p.tab.gcell.as<cplx<T>>();
+  a.sspec = p.cell_src.as<cplx<T>>();
+  a.tspec = p.cell_tgt.as<cplx<T>>();
+  a.m2l_mean = p.m2l_mean.as<double>();
+  if (p.tab.gcell_levels < p.nlevels - 2) fail(HPM_ERR_DEVICE, "cell Green tables missing");
+  if (p.cell_src.bytes < size_t(a.nsources + 1) * S::K * sizeof(cplx<T>) ||
+      p.cell_tgt.bytes < size_t(ntargets) * S::K * sizeof(cplx<T>))
+    fail(HPM_ERR_DEVICE, "cell spectra buffers too small");
+  k_cells_forward<T, NG><<<a.nsources + 1, 256, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+  using A = AccumShape<T>;
+  for (int lp = 1; lp + 1 < p.nlevels; ++lp) {
+    const int pbeg = p.cell_pbeg[lp], pend = p.cell_pbeg[lp + 1];
+    if (pend <= pbeg) continue;
+    const int groups = std::min((pend - pbeg + A::PP - 1) / A::PP, 65535);
+    k_cells_accum<T, NG><<<dim3(S::K / A::KM, groups), 256, 0, s>>>(a, lp + 1,
+                                                                       p.cell_plist.as<int>(),
+                                                                       pbeg, pend);
+    HPM_LAUNCH_CHECK();
+  }
+  k_cells_inverse<T, NG><<<ntargets, 256, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+}
+
+size_t cell_modes(int ng) { return size_t(2 * ng) * (2 * ng) * (ng + 1); }
+
+// ---- list of split parents (cells of levels 1 .. L-2 with children), by level ----------------
+__global__ void k_split_flags(int first, int n, const int* cflags, int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = cflags[first + i] & 1;
+}
+
+__global__ void k_split_emit(int first, int n, const int* flag, const int* pos, int* list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) list[pos[i]] = first + i;
+}
+
+// start of each parent level in the list (levels 1 .. L-2), and its end, into the mailbox
+__global__ void k_split_bounds(int nlevels, const int* level_off, int first, int n,
+                               const int* flag, const int* pos, int* box) {
+  const int l = threadIdx.x;
+  if (l < 1 || l > nlevels - 1) return;
+  const int i = level_off[l] - first;  // first cell of level l, relative to the list's range
+  box[Plan::kBoxCellLevels + l] = i < n ? pos[i] : pos[n - 1] + flag[n - 1];
+}
+
+void build_cell_parents(Plan& p, hipStream_t s) {
+  for (int l = 0; l <= kMaxLevelsHost; ++l) p.cell_pbeg[l] = 0;
+  if (p.nlevels <= 2) return;
+  const int first = p.level_off[1], n = p.level_off[p.nlevels - 1] - first;
+  if (n <= 0) return;
+  p.cell_pflag.reserve(size_t(n) * 4);
+  p.cell_ppos.reserve(size_t(n) * 4);
+  p.cell_plist.reserve(size_t(n) * 4);
+  const int nb = (n + 255) / 256;
+  k_split_flags<<<nb, 256, 0, s>>>(first, n, p.cflags.as<int>(), p.cell_pflag.as<int>());
+  HPM_LAUNCH_CHECK();
+  exclusive_scan_i32(p.cell_pflag.as<int>(), p.cell_ppos.as<int>(), n, nullptr, p.scan_tmp, s);
+  k_split_emit<<<nb, 256, 0, s>>>(first, n, p.cell_pflag.as<int>(), p.cell_ppos.as<int>(),
+                                  p.cell_plist.as<int>());
+  HPM_LAUNCH_CHECK();
+  k_split_bounds<<<1, 64, 0, s>>>(p.nlevels, p.dlevel.as<int>(), first, n, p.cell_pflag.as<int>(),
+                                  p.cell_ppos.as<int>(), p.dbox);
+  HPM_LAUNCH_CHECK();
+  HPM_HIP(hipStreamSynchronize(s));
+  for (int l = 1; l <= p.nlevels - 1; ++l) p.cell_pbeg[l] = p.hbox[Plan::kBoxCellLevels + l];
+}
+
+void launch_m2l_cells(Plan& p, hipStream_t s) {
+  if (p.prec == HPM_F32) {
+    switch (p.ng) {
+      case 2: cells_t<float, 2>(p, s); break;
+      case 3: cells_t<float, 3>(p, s); break;
+      case 4: cells_t<float, 4>(p, s); break;
+      case 6: cells_t<float, 6>(p, s); break;
+      case 8: cells_t<float, 8>(p, s); break;
+    }
+  } else {
+    switch (p.ng) {
+      case 2: cells_t<double, 2>(p, s); break;
+      case 3: cells_t<double, 3>(p, s); break;
+      case 4: cells_t<double, 4>(p, s); break;
+      case 6: cells_t<double, 6>(p, s); break;
+      case 8: cells_t<double, 8>(p, s); break;
+    }
+  }
+}
+
+}  // namespace hpm

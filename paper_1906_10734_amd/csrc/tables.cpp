@@ -20,6 +20,11 @@
 //                transformed along x and y only, at the z offsets 0 .. 4 N_g - 1 that separate a
 //                target node from a source node, and divided by n^2, serves the variant of the
 //                source-to-target step that convolves along z in real space.
+//   cell-by-cell Green transforms  (only for the cell-by-cell route, Sec. 2.5) per level and
+//                source cube offset d in [-3, 3]^3: the (2 N_g)^3 cyclic array whose entry u holds
+//                g(h_l |d N_g - u_c|), u_c = u for u < N_g and u - 2 N_g otherwise, so that each
+//                node offset between the two cubes sits on its own entry; its half spectrum
+//                [kz][ky][kx <= N_g] by separable direct sums, divided by (2 N_g)^3.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -77,6 +82,84 @@ static std::vector<double> invert(std::vector<double> a, int n) {
     }
   }
   return inv;
+}
+
+// Transforms of the cyclic Green arrays of the cell-by-cell route, all levels and offsets.
+static std::vector<double> cell_green(const Plan& p, int nlev) {
+  const int ng = p.ng, C = 2 * ng, HC = ng + 1, K = C * C * HC;
+  std::vector<double> out(size_t(std::max(nlev, 1)) * 343 * K * 2, 0.0);
+  std::vector<double> cs(size_t(C) * C), sn(size_t(C) * C);
+  for (int k = 0; k < C; ++k)
+    for (int j = 0; j < C; ++j) {
+      const double ang = 2.0 * M_PI * double((k * j) % C) / double(C);
+      cs[size_t(k) * C + j] = std::cos(ang);
+      sn[size_t(k) * C + j] = -std::sin(ang);
+    }
+  const double G = p.prob.gconst, eps = p.prob.softening, inv = 1.0 / (double(C) * C * C);
+  std::vector<double> g(size_t(C) * C * C);
+  std::vector<double> a1r(size_t(C) * C * HC), a1i(a1r.size()), a2r(size_t(C) * C * HC),
+      a2i(a2r.size());
+  for (int li = 0; li < nlev; ++li) {
+    const double h = p.prob.box_size / (double(1 << (li + 2)) * ng);
+    for (int od = 0; od < 343; ++od) {
+      const int d[3] = {od % 7 - 3, (od / 7) % 7 - 3, od / 49 - 3};
+      if (std::abs(d[0]) <= 1 && std::abs(d[1]) <= 1 && std::abs(d[2]) <= 1) continue;  // near
+      for (int z = 0; z < C; ++z)
+        for (int y = 0; y < C; ++y)
+          for (int x = 0; x < C; ++x) {
+            const int u[3] = {x, y, z};
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+              const double o = double(d[a] * ng - (u[a] < ng ? u[a] : u[a] - C));
+              r2 += o * o;
+            }
+            const double sd = std::sqrt(r2 * h * h + eps * eps);
+            g[(size_t(z) * C + y) * C + x] = (p.prob.kernel == HPM_KERNEL_YUKAWA)
+                                                 ? -G * std::exp(-sd / p.prob.screening) / sd
+                                                 : -G / sd;
+          }
+      // x (real input): a1[z][y][kx]
+      for (int zy = 0; zy < C * C; ++zy)
+        for (int kx = 0; kx < HC; ++kx) {
+          double re = 0.0, im = 0.0;
+          for (int x = 0; x < C; ++x) {
+            re += g[size_t(zy) * C + x] * cs[size_t(kx) * C + x];
+            im += g[size_t(zy) * C + x] * sn[size_t(kx) * C + x];
+          }
+          a1r[size_t(zy) * HC + kx] = re;
+          a1i[size_t(zy) * HC + kx] = im;
+        }
+      // y: a2[z][ky][kx]
+      for (int z = 0; z < C; ++z)
+        for (int ky = 0; ky < C; ++ky)
+          for (int kx = 0; kx < HC; ++kx) {
+            double re = 0.0, im = 0.0;
+            for (int y = 0; y < C; ++y) {
+              const size_t i = (size_t(z) * C + y) * HC + kx;
+              const double c = cs[size_t(ky) * C + y], sv = sn[size_t(ky) * C + y];
+              re += a1r[i] * c - a1i[i] * sv;
+              im += a1r[i] * sv + a1i[i] * c;
+            }
+            a2r[(size_t(z) * C + ky) * HC + kx] = re;
+            a2i[(size_t(z) * C + ky) * HC + kx] = im;
+          }
+      // z: [kz][ky][kx], interleaved (re, im), / C^3
+      double* o = &out[(size_t(li) * 343 + od) * K * 2];
+      for (int kz = 0; kz < C; ++kz)
+        for (int col = 0; col < C * HC; ++col) {
+          double re = 0.0, im = 0.0;
+          for (int z = 0; z < C; ++z) {
+            const size_t i = size_t(z) * C * HC + col;
+            const double c = cs[size_t(kz) * C + z], sv = sn[size_t(kz) * C + z];
+            re += a2r[i] * c - a2i[i] * sv;
+            im += a2r[i] * sv + a2i[i] * c;
+          }
+          o[(size_t(kz) * C * HC + col) * 2] = re * inv;
+          o[(size_t(kz) * C * HC + col) * 2 + 1] = im * inv;
+        }
+    }
+  }
+  return out;
 }
 
 template <typename T>
@@ -183,6 +266,12 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
         }
   }
   p.tab.ghat_levels = nlev;
+  if (p.prob.m2l_mode == HPM_M2L_CELLS) {
+    const std::vector<double> gc = cell_green(p, nlev);
+    if (p.prec == HPM_F32) upload<float>(p.tab.gcell, gc, s);
+    else upload<double>(p.tab.gcell, gc, s);
+    p.tab.gcell_levels = nlev;
+  }
   if (p.prec == HPM_F32) {
     upload<float>(p.tab.fitw, w, s);
     upload<float>(p.tab.m2m, t1, s);

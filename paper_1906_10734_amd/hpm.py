@@ -16,9 +16,10 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpm.so")
 
-HPM_ABI_VERSION = 2
+HPM_ABI_VERSION = 3
 HPM_F64, HPM_F32 = 0, 1
 HPM_KERNELS = {"newton": 0, "yukawa": 1}
+HPM_M2L_MODES = {"grid": 0, "cells": 1}
 STATUS = {0: "HPM_OK", 1: "HPM_ERR_INVALID_ARG", 2: "HPM_ERR_OUT_OF_BOX", 3: "HPM_ERR_NONFINITE",
           4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED"}
 
@@ -32,7 +33,7 @@ class HpmProblem(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("softening", ctypes.c_double),
                 ("gconst", ctypes.c_double), ("box_lo", ctypes.c_double * 3),
                 ("box_size", ctypes.c_double), ("kernel", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("screening", ctypes.c_double)]
+                ("m2l_mode", ctypes.c_int32), ("screening", ctypes.c_double)]
 
 
 class HpmPlanInfo(ctypes.Structure):
@@ -107,6 +108,7 @@ class Problem:
     box_size: float = 1.0
     kernel: str = "newton"          # "newton" or "yukawa" (screened, needs screening > 0)
     screening: float = 0.0
+    m2l: str = "grid"               # "grid" (the method) or "cells" (cell-by-cell comparison)
 
     @property
     def dtype(self) -> torch.dtype:
@@ -126,7 +128,7 @@ class Problem:
             p.box_lo[k] = self.box_lo[k]
         p.box_size = self.box_size
         p.kernel = HPM_KERNELS[self.kernel]
-        p.reserved = 0
+        p.m2l_mode = HPM_M2L_MODES[self.m2l]
         p.screening = self.screening
         return p
 

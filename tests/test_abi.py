@@ -39,14 +39,14 @@ def test_binding_covers_the_header():
 
 def _problem(**kw):
     from paper_1906_10734_amd import hpm
-    raw = ("abi", "kernel_id", "reserved")
+    raw = ("abi", "kernel_id", "m2l_mode")
     p = hpm.Problem(**{k: v for k, v in kw.items() if k not in raw}).c()
     if "abi" in kw:
         p.abi = kw["abi"]
     if "kernel_id" in kw:
         p.kernel = kw["kernel_id"]
-    if "reserved" in kw:
-        p.reserved = kw["reserved"]
+    if "m2l_mode" in kw:
+        p.m2l_mode = kw["m2l_mode"]
     return p
 
 
@@ -55,7 +55,7 @@ def _problem(**kw):
     (dict(softening=-1.0), 1), (dict(gconst=0.0), 1), (dict(uniform_depth=11), 1),
     (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=1), 1), (dict(abi=99), 1),
     (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
-    (dict(kernel="yukawa", screening=float("nan")), 1), (dict(reserved=1), 1),
+    (dict(kernel="yukawa", screening=float("nan")), 1), (dict(m2l_mode=2), 1), (dict(abi=2), 1),
 ])
 def test_bad_problem_rejected_on_host(kw, status):
     from paper_1906_10734_amd import hpm
