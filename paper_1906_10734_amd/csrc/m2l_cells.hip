@@ -184,6 +184,9 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
     cplx<T> acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = {T(0), T(0)};
+    // two planes at a time in FP32, so that one plane's loads overlap the other's arithmetic
+    // (FP64 has no registers to spare for it)
+#pragma unroll(sizeof(T) == 4 ? 2 : 1)
     for (int bz = 0; bz < 6; ++bz) {
       cplx<T> sp[36];
 #pragma unroll
