@@ -15,6 +15,11 @@ Steps (Sec. 1, enumerated list, and Sec. 2):
                    back once.
   L2L  parent-to-child: potential multipoles Eq. (6), polynomial Eq. (7) at the child nodes.
   L2P  Eq. (7) at each particle, its gradient for the acceleration.
+
+Extended gridlet (Sec. 2.5, Problem.extended): target gridlets (the M2L output and the locals of
+L2L and L2P) carry N_g + 2 nodes per axis, the gridlet widened by one node on every side at the
+same spacing; Eq. (6)-(7) then use that node set (polynomials of degree N_g + 1 per axis). The
+sources keep N_g^3 effective masses.
   P2P  near zone (27 cubes) by direct summation (Sec. 1, item 1).
 
 Readings (the paper is silent): the potential kernel is g(r) = -G (r^2+eps^2)^{-1/2}; expansions
@@ -47,6 +52,7 @@ class Problem:
     max_depth: int = 10
     kernel: str = "newton"   # point-mass kernel (green.py); "yukawa" needs a screening length
     screening: float = 0.0
+    extended: bool = False   # target gridlets widened by one node per side (Sec. 2.5)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -87,34 +93,35 @@ def m2m(children: dict, ng: int) -> np.ndarray:
     return out.astype(np.float64)
 
 
-def potential_multipoles(phi: np.ndarray, ng: int) -> np.ndarray:
-    """Eq. (6): V_n = sum_p B_pn Phi_p (extended precision)."""
-    return tables.inverse_3d(ng, LD).T @ np.asarray(phi, dtype=LD)
+def potential_multipoles(phi: np.ndarray, ng: int, ext: int = 0) -> np.ndarray:
+    """Eq. (6): V_n = sum_p B_pn Phi_p (extended precision), on the target gridlet's nodes."""
+    return tables.inverse_3d(ng, LD, ext).T @ np.asarray(phi, dtype=LD)
 
 
 @lru_cache(maxsize=None)
-def _child_node_monomials(ng: int, octant: int) -> np.ndarray:
+def _child_node_monomials(ng: int, octant: int, ext: int = 0) -> np.ndarray:
     """u^n at the child's nodes u = (a^C + x_p)/2 in parent units (geometry only, cached)."""
     a = np.asarray(tables.child_offset(octant), dtype=LD)
-    u = (a[None, :] + tables.node_positions(ng).astype(LD)) / LD(2)
-    return monomials(u, ng)
+    u = (a[None, :] + tables.node_positions(ng, ext).astype(LD)) / LD(2)
+    return monomials(u, ng + 2 * ext)
 
 
-def l2l(phi_parent: np.ndarray, octant: int, ng: int) -> np.ndarray:
+def l2l(phi_parent: np.ndarray, octant: int, ng: int, ext: int = 0) -> np.ndarray:
     """Parent contribution on a child gridlet: Phi^C_p = Phi^P((a^C + x_p)/2), Eq. (6)-(7)."""
-    v = potential_multipoles(phi_parent, ng)
-    return (_child_node_monomials(ng, octant) @ v).astype(np.float64)    # Eq. (7)
+    v = potential_multipoles(phi_parent, ng, ext)
+    return (_child_node_monomials(ng, octant, ext) @ v).astype(np.float64)    # Eq. (7)
 
 
-def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float):
+def l2p(phi: np.ndarray, rel: np.ndarray, ng: int, L: float, ext: int = 0):
     """Eq. (7) at particles (offsets ``rel`` from the cell centre) and minus its gradient.
 
     Returns (potential (k,), acceleration (k, 3)).
     """
-    v = potential_multipoles(phi, ng)
+    v = potential_multipoles(phi, ng, ext)
     x = np.asarray(rel, dtype=LD) / LD(L)
-    pot = monomials(x, ng) @ v
-    nidx = tables.multi_index(ng)
+    npt = ng + 2 * ext
+    pot = monomials(x, npt) @ v
+    nidx = tables.multi_index(npt)
     acc = np.zeros((x.shape[0], 3), dtype=LD)
     for ax in range(3):
         dm = np.ones((x.shape[0], nidx.shape[0]), dtype=LD)
@@ -164,6 +171,9 @@ class HPM:
         self.m = np.asarray(m, np.float64)[t.perm]
         self.ng = prob.ng
         self.M = prob.ng ** 3
+        self.ext = 1 if prob.extended else 0
+        self.ne = prob.ng + 2 * self.ext     # target gridlet nodes per axis
+        self.ML = self.ne ** 3
         self._virtual = {}
         self._ghat = {}
         self.gridlets = {}
@@ -222,7 +232,7 @@ class HPM:
             if g is not None:
                 sources.append((np.asarray(q), g))
         if not sources:
-            return np.zeros(self.M)
+            return np.zeros(self.ML)
         if self.mode == "direct":
             return self._m2l_direct(l, coord, sources)
         if self.mode == "cells":
@@ -230,16 +240,17 @@ class HPM:
         return self._m2l_fft(l, coord, sources)
 
     def _green_offset(self, l: int, d: tuple) -> np.ndarray:
-        """Transform of the (2 N_g)^3 cyclic Green array for source cube offset d (cube units):
-        entry u holds g(h |d N_g + u_c|) with u_c = u for u < N_g and u - 2 N_g otherwise, so that
-        every target-minus-source node offset of that cube pair, d N_g + (p - q) with
-        |p - q| < N_g, is stored once (no wrap-around)."""
+        """Transform of the C^3 cyclic Green array for source cube offset d (cube units), with
+        C = 2 N_g + 2 ext: entry u holds g(h |d N_g - u_c|) with u_c = u for u < N_g + ext and
+        u - C otherwise, so that every target-minus-source node offset of that cube pair,
+        d N_g + (p - q) with -N_g - ext < p - q < N_g + ext, is stored once (no wrap-around)."""
         key = ("cells", l, d)
         if key not in self._ghat:
-            ng = self.ng
+            ng, ext = self.ng, self.ext
+            C = 2 * ng + 2 * ext
             h = self.tree.cube_size(l) / ng
-            u = np.arange(2 * ng)
-            uc = np.where(u < ng, u, u - 2 * ng).astype(np.float64)
+            u = np.arange(C)
+            uc = np.where(u < ng + ext, u, u - C).astype(np.float64)
             oz, oy, ox = np.meshgrid(d[2] * ng - uc, d[1] * ng - uc, d[0] * ng - uc, indexing="ij")
             r2 = (ox * ox + oy * oy + oz * oz) * h * h
             g = tables.green_physical(r2, self.prob.gconst, self.prob.softening, self.prob.kernel,
@@ -248,26 +259,29 @@ class HPM:
         return self._ghat[key]
 
     def _m2l_cells(self, l, coord, sources):
-        """Cell-by-cell: sum over sources of rfft(source padded to (2 N_g)^3) * Ghat_d, one
-        inverse transform, the N_g^3 corner read out (target node p, source node q: the cyclic
-        index of p - q is the stored offset d N_g - (p - q) read as (q - p) mod 2 N_g)."""
-        ng = self.ng
+        """Cell-by-cell: sum over sources of rfft(source padded to C^3) * Ghat_d, one inverse
+        transform, the target gridlet read out (target node p = -ext .. N_g - 1 + ext sits at
+        cyclic index p mod C: the convolution pairs it with source node q through entry
+        (p - q) mod C, whose stored offset is d N_g - (p - q))."""
+        ng, ext = self.ng, self.ext
+        C = 2 * ng + 2 * ext
         acc = None
         for q, g in sources:
             d = tuple(int(v) for v in (np.asarray(q) - coord))
-            pad = np.zeros((2 * ng, 2 * ng, 2 * ng))
+            pad = np.zeros((C, C, C))
             pad[:ng, :ng, :ng] = g.reshape(ng, ng, ng)
             term = sfft.rfftn(pad) * self._green_offset(l, d)
             acc = term if acc is None else acc + term
-        out = sfft.irfftn(acc, s=(2 * ng, 2 * ng, 2 * ng))
-        return out[:ng, :ng, :ng].ravel().copy()
+        out = sfft.irfftn(acc, s=(C, C, C))
+        idx = np.arange(-ext, ng + ext) % C
+        return out[np.ix_(idx, idx, idx)].ravel().copy()
 
     def _m2l_direct(self, l, coord, sources):
         t, ng = self.tree, self.ng
         L = t.cube_size(l)
         xp = tables.node_positions(ng)
-        tnodes = t.cube_centre(l, coord) + L * xp
-        out = np.zeros(self.M)
+        tnodes = t.cube_centre(l, coord) + L * tables.node_positions(ng, self.ext)
+        out = np.zeros(self.ML)
         for q, g in sources:
             snodes = t.cube_centre(l, q) + L * xp
             d = tnodes[:, None, :] - snodes[None, :, :]
@@ -287,8 +301,9 @@ class HPM:
                  b[0] * ng:(b[0] + 1) * ng] = g.reshape(ng, ng, ng)
         pot = sfft.irfftn(sfft.rfftn(grid) * self._ghat_level(l), s=grid.shape)
         tb = coord - origin
-        return pot[tb[2] * ng:(tb[2] + 1) * ng, tb[1] * ng:(tb[1] + 1) * ng,
-                   tb[0] * ng:(tb[0] + 1) * ng].ravel().copy()
+        e = self.ext   # the extended gridlet reaches one node into the neighbouring cubes
+        return pot[tb[2] * ng - e:(tb[2] + 1) * ng + e, tb[1] * ng - e:(tb[1] + 1) * ng + e,
+                   tb[0] * ng - e:(tb[0] + 1) * ng + e].ravel().copy()
 
     # ---- step 4: parent-to-child, level by level ------------------------------------------------
     def local(self, l: int, i: int) -> np.ndarray:
@@ -299,7 +314,7 @@ class HPM:
             phi = self.m2l(l, lev.coords[i])
             if l > 2:
                 par = int(lev.parent[i])
-                phi = phi + l2l(self.local(l - 1, par), int(lev.keys[i] & 7), self.ng)
+                phi = phi + l2l(self.local(l - 1, par), int(lev.keys[i] & 7), self.ng, self.ext)
             store[i] = phi
         return store[i]
 
@@ -311,7 +326,7 @@ class HPM:
         lev = t.levels[l]
         if l >= 2:
             pf, af = l2p(self.local(l, i), self.pos[sel] - t.cube_centre(l, lev.coords[i]),
-                         self.ng, t.cube_size(l))
+                         self.ng, t.cube_size(l), self.ext)
         else:
             pf, af = np.zeros(sel.size), np.zeros((sel.size, 3))
         srcs = [t.cube_range(l, q) for q in t.near_positions(lev.coords[i], l)]
@@ -351,7 +366,7 @@ class HPM:
         out = {}
         for l in range(2, self.tree.max_level + 1):
             out[l] = np.stack([self.local(l, i) for i in range(len(self.tree.levels[l]))]) \
-                if len(self.tree.levels[l]) else np.zeros((0, self.M))
+                if len(self.tree.levels[l]) else np.zeros((0, self.ML))
         return out
 
 

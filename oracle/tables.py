@@ -15,6 +15,10 @@ the parent spans [-1, 1]). Its defining double sum over n and m factorises over 
 because every term is a product of per-axis factors.
 
 Eq. (1): the exact lattice Green function with periodic distance |i|_p.
+
+Sec. 2.5 (extended gridlet): a target gridlet widened by one node on every side, N_g + 2 nodes
+per axis at the same spacing, i.e. nodes (i + 1/2)/N_g - 1/2 for i = -1 .. N_g. The functions
+below take ``ext`` = 1 for that node set (0: the gridlet of Sec. 2.2); sources always use ext = 0.
 """
 from __future__ import annotations
 
@@ -27,19 +31,21 @@ import numpy as np
 from . import green
 
 
-def node_fractions(ng: int) -> list:
-    """Gridlet node coordinates (i + 1/2)/N_g - 1/2 as exact rationals (Sec. 2.2)."""
-    return [Fraction(2 * i + 1 - ng, 2 * ng) for i in range(ng)]
+def node_fractions(ng: int, ext: int = 0) -> list:
+    """Gridlet node coordinates (i + 1/2)/N_g - 1/2, i = -ext .. N_g - 1 + ext, as exact
+    rationals (Sec. 2.2; ext = 1 is the extended gridlet of Sec. 2.5)."""
+    return [Fraction(2 * i + 1 - ng, 2 * ng) for i in range(-ext, ng + ext)]
 
 
-def nodes(ng: int) -> np.ndarray:
-    return np.array([float(f) for f in node_fractions(ng)], dtype=np.float64)
+def nodes(ng: int, ext: int = 0) -> np.ndarray:
+    return np.array([float(f) for f in node_fractions(ng, ext)], dtype=np.float64)
 
 
-def _vandermonde_exact(ng: int) -> list:
-    """A1[n][p] = x_p^n with rational entries."""
-    xs = node_fractions(ng)
-    return [[xs[p] ** n for p in range(ng)] for n in range(ng)]
+def _vandermonde_exact(ng: int, ext: int = 0) -> list:
+    """A1[n][p] = x_p^n with rational entries (n, p < N_g + 2 ext)."""
+    xs = node_fractions(ng, ext)
+    k = len(xs)
+    return [[xs[p] ** n for p in range(k)] for n in range(k)]
 
 
 def _invert_exact(a: list) -> list:
@@ -76,14 +82,14 @@ def vandermonde_1d(ng: int, dtype=np.float64) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
-def _inverse_1d_exact(ng: int) -> list:
-    return _invert_exact(_vandermonde_exact(ng))
+def _inverse_1d_exact(ng: int, ext: int = 0) -> list:
+    return _invert_exact(_vandermonde_exact(ng, ext))
 
 
 @lru_cache(maxsize=None)
-def inverse_1d(ng: int, dtype=np.float64) -> np.ndarray:
+def inverse_1d(ng: int, dtype=np.float64, ext: int = 0) -> np.ndarray:
     """B1[p, n] = (A1^{-1})[p, n], exact rational inverse rounded once (Sec. 2.2)."""
-    return _to(_inverse_1d_exact(ng), dtype)
+    return _to(_inverse_1d_exact(ng, ext), dtype)
 
 
 def kron3(ax: np.ndarray, ay: np.ndarray, az: np.ndarray) -> np.ndarray:
@@ -99,9 +105,9 @@ def vandermonde_3d(ng: int, dtype=np.float64) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
-def inverse_3d(ng: int, dtype=np.float64) -> np.ndarray:
-    """B[p, n] = A^{-1} (Sec. 2.2, the matrix of Eq. 5)."""
-    b1 = inverse_1d(ng, dtype)
+def inverse_3d(ng: int, dtype=np.float64, ext: int = 0) -> np.ndarray:
+    """B[p, n] = A^{-1} (Sec. 2.2, the matrix of Eq. 5; of Eq. 6 for a target gridlet)."""
+    b1 = inverse_1d(ng, dtype, ext)
     return kron3(b1, b1, b1)
 
 
@@ -114,10 +120,10 @@ def multi_index(ng: int) -> np.ndarray:
 
 
 @lru_cache(maxsize=None)
-def node_positions(ng: int) -> np.ndarray:
-    """(M, 3) gridlet node coordinates x_p in cell units, raveled like p."""
-    xs = nodes(ng)
-    idx = multi_index(ng)
+def node_positions(ng: int, ext: int = 0) -> np.ndarray:
+    """((N_g + 2 ext)^3, 3) gridlet node coordinates x_p in cell units, raveled like p."""
+    xs = nodes(ng, ext)
+    idx = multi_index(ng + 2 * ext)
     return xs[idx]
 
 
