@@ -69,13 +69,13 @@ def traffic_from_profile(ng: int, prec: str):
 
 
 def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, kernel="newton",
-             screening=0.0, m2l="grid"):
+             screening=0.0, m2l="grid", extended=False):
     """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
     p = parts.astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
     x, y, z, m = (torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
     prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3,
-                       kernel=kernel, screening=screening, m2l=m2l)
+                       kernel=kernel, screening=screening, m2l=m2l, extended=extended)
     plan = hpm.Plan(prob, x, y, z)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(warmup):
@@ -276,6 +276,15 @@ def main():
                             "m2l_ms": round(stage(rcd, "m2l"), 4), "force_err_rms": ferr(ocd)[0]},
               "grid_m2l_ms": {"f32": round(stage(r32, "m2l"), 4), "f64": round(stage(r64, "m2l"), 4)},
               "paper_count_ratio_grid_over_cells": round(0.34 * (pg + 3) / (pg + 1), 3)}
+    # the extended target gridlet (Sec. 2.5, N_g + 2 nodes per axis) on the cell route, at this
+    # order and at N_g = 4: rate and force error beside the standard gridlet's
+    for g in sorted({ng, 4}):
+        for pr, st in (("f32", args.steps), ("f64", args.fp64_steps)):
+            re_, oe, _ = run_path(hpm, torch, parts, pr, g, st, 1, m2l="cells", extended=True)
+            routes[f"cells_extended_ng{g}_{pr}"] = {
+                "value": round(args.n / (re_["ms_per_step"] * 1e-3), 1),
+                "ms_per_step": round(re_["ms_per_step"], 4), "m2l_ms": round(stage(re_, "m2l"), 4),
+                "leaf_ms": round(stage(re_, "leaf"), 4), "force_err_rms": ferr(oe)[0]}
 
     # latency of the small uniform problem (4096 particles, uniform depth 3, N_g = 4, FP64)
     from synth import uniform_cube

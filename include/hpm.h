@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 3
+#define HPM_ABI_VERSION 4
 
 typedef enum {
   HPM_OK = 0,
@@ -92,6 +92,12 @@ typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1 } hpm_m2l_mode;
  *   kernel         an hpm_kernel value.
  *   m2l_mode       an hpm_m2l_mode value.
  *   screening      lam > 0 of HPM_KERNEL_YUKAWA (ignored for HPM_KERNEL_NEWTON).
+ *   extended       0 or 1. 1: target gridlets widened by one node on every side (Sec. 2.5), so
+ *                  the source-to-target output, parent-to-child and leaf interpolation use
+ *                  (N_g + 2)^3 nodes at the same spacing; sources keep N_g^3 effective masses.
+ *                  Built on the cell-by-cell route only: with HPM_M2L_GRID it returns
+ *                  HPM_ERR_UNSUPPORTED.
+ *   reserved       must be 0.
  */
 typedef struct {
   int32_t abi;
@@ -107,6 +113,8 @@ typedef struct {
   int32_t kernel;
   int32_t m2l_mode;
   double screening;
+  int32_t extended;
+  int32_t reserved;
 } hpm_problem;
 
 /* Per-solve statistics filled by hpm_plan_info (host struct owned by the caller). */
@@ -202,7 +210,8 @@ hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info);
  *                          count * N_g^3 values of the plan's dtype, node index
  *                          i + N_g (j + N_g k) fastest in x (Sec. 2.2). Defined for l >= 2.
  *   hpm_plan_copy_locals   gridlet part dPhi of the local potentials of level l cells after the
- *                          last execute, same layout, l >= 2. The local potential (far field
+ *                          last execute, same layout with N_g + 2 nodes per axis when
+ *                          problem.extended is 1 (node i at (i - 1/2)/N_g - 1/2), l >= 2. The local potential (far field
  *                          from source-to-target plus parent-to-child, Sec. 2.1 and 2.4) of cell
  *                          i is c_i + dPhi_i, with the per-cell constant c_i (double, count
  *                          values) from hpm_plan_copy_local_offsets.

@@ -46,6 +46,10 @@ static void check_problem(const hpm_problem* pr) {
   check_kernel(pr->kernel, pr->screening);
   if (pr->m2l_mode != HPM_M2L_GRID && pr->m2l_mode != HPM_M2L_CELLS)
     fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID or HPM_M2L_CELLS");
+  if (pr->extended != 0 && pr->extended != 1) fail(HPM_ERR_INVALID_ARG, "extended must be 0 or 1");
+  if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
+  if (pr->extended && pr->m2l_mode != HPM_M2L_CELLS)
+    fail(HPM_ERR_UNSUPPORTED, "extended gridlets are built on the cell-by-cell route only");
   if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
   if (pr->uniform_depth == 0) {
     if (pr->leaf_capacity < 1) fail(HPM_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
@@ -79,13 +83,13 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   build_virtual(p, s);
   const size_t cells = size_t(p.ncells);
   p.gridlet.reserve((cells + size_t(p.nvirt)) * p.M * p.elem);
-  p.local.reserve(cells * p.M * p.elem);
+  p.local.reserve(cells * p.ML * p.elem);
   const size_t rows = size_t(std::max<int64_t>({p.nleaves - p.nleaves_lt2, p.nvirt, 1}));
   p.moments.reserve(rows * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
   p.m2l_mean.reserve(cells * sizeof(double));
   if (p.prob.m2l_mode == HPM_M2L_CELLS && p.nlevels > 2) {
-    const size_t spec = cell_modes(p.ng) * 2 * p.elem;
+    const size_t spec = cell_modes(p.ng, p.ext) * 2 * p.elem;
     const size_t ntg = cells - size_t(p.level_off[2]);
     p.cell_src.reserve((ntg + size_t(p.nvirt) + 1) * spec);  // + a zero row
     p.cell_tgt.reserve(ntg * spec);
@@ -111,6 +115,9 @@ static void create_plan(const hpm_problem* pr, int64_t n, const void* x, const v
   p.prec = pr->precision;
   p.ng = pr->ng;
   p.M = pr->ng * pr->ng * pr->ng;
+  p.ext = pr->extended;
+  p.NL = pr->ng + 2 * p.ext;
+  p.ML = p.NL * p.NL * p.NL;
   p.elem = (p.prec == HPM_F32) ? 4 : 8;
   HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
                         hipHostMallocMapped | hipHostMallocCoherent));
@@ -354,8 +361,9 @@ static hpm_status copy_rows(const hpm_plan* plan, int32_t level, void* host, boo
     int off, cnt;
     level_range(p, level, &off, &cnt);
     const DevBuf& b = locals ? p.local : p.gridlet;
-    HPM_HIP(hipMemcpy(host, static_cast<const char*>(b.p) + size_t(off) * p.M * p.elem,
-                      size_t(cnt) * p.M * p.elem, hipMemcpyDeviceToHost));
+    const size_t row = size_t(locals ? p.ML : p.M) * p.elem;
+    HPM_HIP(hipMemcpy(host, static_cast<const char*>(b.p) + size_t(off) * row, size_t(cnt) * row,
+                      hipMemcpyDeviceToHost));
   });
 }
 

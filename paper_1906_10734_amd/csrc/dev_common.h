@@ -9,48 +9,53 @@ namespace hpm {
 
 constexpr int kMaxLevels = 11;  // levels 0..10 (30-bit Morton keys)
 
-// Gridlet node i of N_g per axis, in cell units centred on the cell: (i + 1/2)/N_g - 1/2.
-template <int NG>
-constexpr double node_xi(int i) { return (2.0 * i + 1.0 - NG) / (2.0 * NG); }
+// Gridlet node i of a gridlet of N_g points per axis widened by EXT nodes on each side (EXT = 1:
+// the extended target gridlet, Sec. 2.5), in cell units centred on the cell:
+// (i - EXT + 1/2)/N_g - 1/2 for i = 0 .. N_g + 2 EXT - 1.
+template <int NG, int EXT = 0>
+constexpr double node_xi(int i) { return (2.0 * (i - EXT) + 1.0 - NG) / (2.0 * NG); }
 
-// 1 / prod_{m != i} (xi_i - xi_m): denominators of the Lagrange basis on the gridlet nodes.
-template <int NG>
+// 1 / prod_{m != i} (xi_i - xi_m): denominators of the Lagrange basis on those nodes.
+template <int NG, int EXT = 0>
 constexpr double lagrange_inv_den(int i) {
   double d = 1.0;
-  for (int m = 0; m < NG; ++m)
-    if (m != i) d *= (node_xi<NG>(i) - node_xi<NG>(m));
+  for (int m = 0; m < NG + 2 * EXT; ++m)
+    if (m != i) d *= (node_xi<NG, EXT>(i) - node_xi<NG, EXT>(m));
   return 1.0 / d;
 }
 
 // l_i(u) = prod_{m != i} (u - xi_m)/(xi_i - xi_m) for all i, via prefix and suffix products.
-template <int NG, typename T>
-__device__ __forceinline__ void lagrange_basis(T u, T (&l)[NG]) {
-  T pre[NG], suf[NG];
+template <int NG, int EXT = 0, typename T>
+__device__ __forceinline__ void lagrange_basis(T u, T (&l)[NG + 2 * EXT]) {
+  constexpr int NP = NG + 2 * EXT;
+  T pre[NP], suf[NP];
   pre[0] = T(1);
 #pragma unroll
-  for (int m = 1; m < NG; ++m) pre[m] = pre[m - 1] * (u - T(node_xi<NG>(m - 1)));
-  suf[NG - 1] = T(1);
+  for (int m = 1; m < NP; ++m) pre[m] = pre[m - 1] * (u - T(node_xi<NG, EXT>(m - 1)));
+  suf[NP - 1] = T(1);
 #pragma unroll
-  for (int m = NG - 2; m >= 0; --m) suf[m] = suf[m + 1] * (u - T(node_xi<NG>(m + 1)));
+  for (int m = NP - 2; m >= 0; --m) suf[m] = suf[m + 1] * (u - T(node_xi<NG, EXT>(m + 1)));
 #pragma unroll
-  for (int i = 0; i < NG; ++i) l[i] = pre[i] * suf[i] * T(lagrange_inv_den<NG>(i));
+  for (int i = 0; i < NP; ++i) l[i] = pre[i] * suf[i] * T(lagrange_inv_den<NG, EXT>(i));
 }
 
 // l_i(u) and l_i'(u), by carrying (value, derivative) through the product.
-template <int NG, typename T>
-__device__ __forceinline__ void lagrange_basis_d(T u, T (&l)[NG], T (&dl)[NG]) {
+template <int NG, int EXT = 0, typename T>
+__device__ __forceinline__ void lagrange_basis_d(T u, T (&l)[NG + 2 * EXT],
+                                                 T (&dl)[NG + 2 * EXT]) {
+  constexpr int NP = NG + 2 * EXT;
 #pragma unroll
-  for (int i = 0; i < NG; ++i) {
+  for (int i = 0; i < NP; ++i) {
     T v = T(1), d = T(0);
 #pragma unroll
-    for (int m = 0; m < NG; ++m) {
+    for (int m = 0; m < NP; ++m) {
       if (m == i) continue;
-      const T f = u - T(node_xi<NG>(m));
+      const T f = u - T(node_xi<NG, EXT>(m));
       d = d * f + v;
       v = v * f;
     }
-    l[i] = v * T(lagrange_inv_den<NG>(i));
-    dl[i] = d * T(lagrange_inv_den<NG>(i));
+    l[i] = v * T(lagrange_inv_den<NG, EXT>(i));
+    dl[i] = d * T(lagrange_inv_den<NG, EXT>(i));
   }
 }
 

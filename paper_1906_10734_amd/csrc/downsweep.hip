@@ -412,9 +412,12 @@ struct LeafArgs {
   T gconst;
 };
 
-template <typename T, int NG>
+// The local potential of a leaf lives on NP = N_g + 2 EXT nodes per axis (EXT = 1: the extended
+// gridlet of Sec. 2.5).
+template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
-  constexpr int M = NG * NG * NG;
+  constexpr int NP = NG + 2 * EXT;
+  constexpr int M = NP * NP * NP;
   __shared__ int s_off[kMaxLevels + 1];
   __shared__ T s_phi[M];
   const int lane = threadIdx.x;
@@ -455,18 +458,18 @@ __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
     T pfar = T(0), gx = T(0), gy = T(0), gz = T(0);
     if (l >= 2) {
       const T xi = a.xs[i], yi = a.ys[i], zi = a.zs[i];
-      T lx[NG], dlx[NG], ly[NG], dly[NG], lz[NG], dlz[NG];
-      lagrange_basis_d<NG>((xi - cxc) * invL, lx, dlx);
-      lagrange_basis_d<NG>((yi - cyc) * invL, ly, dly);
-      lagrange_basis_d<NG>((zi - czc) * invL, lz, dlz);
+      T lx[NP], dlx[NP], ly[NP], dly[NP], lz[NP], dlz[NP];
+      lagrange_basis_d<NG, EXT>((xi - cxc) * invL, lx, dlx);
+      lagrange_basis_d<NG, EXT>((yi - cyc) * invL, ly, dly);
+      lagrange_basis_d<NG, EXT>((zi - czc) * invL, lz, dlz);
 #pragma unroll
-      for (int k = 0; k < NG; ++k) {
+      for (int k = 0; k < NP; ++k) {
 #pragma unroll
-        for (int j = 0; j < NG; ++j) {
+        for (int j = 0; j < NP; ++j) {
           T r0 = T(0), r1 = T(0);
 #pragma unroll
-          for (int q = 0; q < NG; ++q) {
-            const T v = s_phi[(k * NG + j) * NG + q];
+          for (int q = 0; q < NP; ++q) {
+            const T v = s_phi[(k * NP + j) * NP + q];
             r0 += lx[q] * v;
             r1 += dlx[q] * v;
           }
@@ -549,12 +552,12 @@ static void l2l_t(Plan& p, int level, hipStream_t s) {
   const int cnt = p.level_off[level + 1] - off;
   if (cnt <= 0) return;
   k_l2l<T, NG><<<cnt, 256, 0, s>>>(off, level >= 3 ? 1 : 0, p.cparent.as<int>(), p.ccoord.as<int>(),
-                                   p.tab.m2m.as<T>(), p.local.as<T>(), p.lofs.as<T>(),
+                                   p.tab.l2l.as<T>(), p.local.as<T>(), p.lofs.as<T>(),
                                    p.m2l_split ? p.m2l_mean.as<double>() : nullptr);
   HPM_LAUNCH_CHECK();
 }
 
-template <typename T, int NG>
+template <typename T, int NG, int EXT>
 static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
   if (p.nleaves <= 0 || p.n_items <= 0) return;
   P2PArgs<T> b;
@@ -600,34 +603,55 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   a.lo2 = p.prob.box_lo[2];
   a.size = p.prob.box_size;
   a.gconst = T(p.prob.gconst);
-  k_leaf<T, NG><<<int(p.nleaves), 64, 0, s>>>(a);
+  k_leaf<T, NG, EXT><<<int(p.nleaves), 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 
-#define HPM_DISPATCH_NG(FN, ...)                                                   \
-  do {                                                                             \
-    if (p.prec == HPM_F32) {                                                       \
-      switch (p.ng) {                                                              \
-        case 2: FN<float, 2>(__VA_ARGS__); break;                                  \
-        case 3: FN<float, 3>(__VA_ARGS__); break;                                  \
-        case 4: FN<float, 4>(__VA_ARGS__); break;                                  \
-        case 6: FN<float, 6>(__VA_ARGS__); break;                                  \
-        case 8: FN<float, 8>(__VA_ARGS__); break;                                  \
-      }                                                                            \
-    } else {                                                                       \
-      switch (p.ng) {                                                              \
-        case 2: FN<double, 2>(__VA_ARGS__); break;                                 \
-        case 3: FN<double, 3>(__VA_ARGS__); break;                                 \
-        case 4: FN<double, 4>(__VA_ARGS__); break;                                 \
-        case 6: FN<double, 6>(__VA_ARGS__); break;                                 \
-        case 8: FN<double, 8>(__VA_ARGS__); break;                                 \
-      }                                                                            \
-    }                                                                              \
-  } while (0)
+// parent-to-child runs on the target gridlet's NL = N_g + 2 ext nodes per axis
+void launch_l2l(Plan& p, int level, hipStream_t s) {
+  if (p.prec == HPM_F32) {
+    switch (p.NL) {
+      case 2: l2l_t<float, 2>(p, level, s); break;
+      case 3: l2l_t<float, 3>(p, level, s); break;
+      case 4: l2l_t<float, 4>(p, level, s); break;
+      case 5: l2l_t<float, 5>(p, level, s); break;
+      case 6: l2l_t<float, 6>(p, level, s); break;
+      case 8: l2l_t<float, 8>(p, level, s); break;
+      default: fail(HPM_ERR_UNSUPPORTED, "no parent-to-child kernel for this gridlet");
+    }
+  } else {
+    switch (p.NL) {
+      case 2: l2l_t<double, 2>(p, level, s); break;
+      case 3: l2l_t<double, 3>(p, level, s); break;
+      case 4: l2l_t<double, 4>(p, level, s); break;
+      case 5: l2l_t<double, 5>(p, level, s); break;
+      case 6: l2l_t<double, 6>(p, level, s); break;
+      case 8: l2l_t<double, 8>(p, level, s); break;
+      default: fail(HPM_ERR_UNSUPPORTED, "no parent-to-child kernel for this gridlet");
+    }
+  }
+}
 
-void launch_l2l(Plan& p, int level, hipStream_t s) { HPM_DISPATCH_NG(l2l_t, p, level, s); }
+template <typename T>
+static void leaf_dispatch(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
+  const int key = p.ng * 2 + p.ext;
+  switch (key) {
+    case 4: leaf_t<T, 2, 0>(p, phi, ax, ay, az, s); break;
+    case 5: leaf_t<T, 2, 1>(p, phi, ax, ay, az, s); break;
+    case 6: leaf_t<T, 3, 0>(p, phi, ax, ay, az, s); break;
+    case 7: leaf_t<T, 3, 1>(p, phi, ax, ay, az, s); break;
+    case 8: leaf_t<T, 4, 0>(p, phi, ax, ay, az, s); break;
+    case 9: leaf_t<T, 4, 1>(p, phi, ax, ay, az, s); break;
+    case 12: leaf_t<T, 6, 0>(p, phi, ax, ay, az, s); break;
+    case 13: leaf_t<T, 6, 1>(p, phi, ax, ay, az, s); break;
+    case 16: leaf_t<T, 8, 0>(p, phi, ax, ay, az, s); break;
+    default: fail(HPM_ERR_UNSUPPORTED, "no leaf kernel for this gridlet");
+  }
+}
+
 void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
-  HPM_DISPATCH_NG(leaf_t, p, phi, ax, ay, az, s);
+  if (p.prec == HPM_F32) leaf_dispatch<float>(p, phi, ax, ay, az, s);
+  else leaf_dispatch<double>(p, phi, ax, ay, az, s);
 }
 
 template <typename T>

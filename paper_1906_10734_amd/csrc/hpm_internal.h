@@ -81,6 +81,8 @@ struct PairKernel {
 // Constant tables of one (precision, N_g, softening, box, levels) combination, in device memory.
 struct Tables {
   DevBuf m2m;    // [2][NG][NG]: T1^a[p][q] = l_p((a + xi_q)/2), a = -1/2 (index 0), +1/2 (1)
+  DevBuf l2l;    // [2][NL][NL]: the same on the target gridlet's nodes (equal to m2m unless
+                 // the gridlets are extended)
   DevBuf fitw;   // [Kpad][Mpad]: W[n][p] = B^phi[p][n], Legendre-moment fit matrix, zero padded
   DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
   DevBuf gxy;    // [levels 2..L][4 N_g][n/2+1][n/2+1]: Green function transformed along x and y
@@ -96,7 +98,10 @@ struct Plan {
   hpm_problem prob{};
   int prec = HPM_F32;
   int ng = 4;
-  int M = 64;
+  int M = 64;       // source gridlet size N_g^3
+  int ext = 0;      // 1: extended target gridlets (N_g + 2 nodes per axis)
+  int NL = 4;       // target gridlet nodes per axis, N_g + 2 ext
+  int ML = 64;      // target gridlet size NL^3 (local potentials)
   int64_t n = 0;
   bool valid = false;  // a tree is built and consistent with the buffers
   int depth = 0;  // Morton key depth D
@@ -125,7 +130,7 @@ struct Plan {
   int blocks_first = 0;
   DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
   // gridlets
-  DevBuf gridlet, local, moments;
+  DevBuf gridlet, local, moments;  // gridlet [cells + virtual][M], local [cells][ML]
   DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
   DevBuf m2l_mean;          // [cells] double: mean of the source-to-target result, when split
   bool m2l_split = false;   // the source-to-target kernel writes (mean, zero-mean gridlet)
@@ -188,8 +193,9 @@ void launch_m2l(Plan& p, hipStream_t s);
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 
 // ---- m2l_cells.hip -------------------------------------------------------------------------------
-// modes of one cell spectrum, (2 N_g)^2 (N_g + 1)
-size_t cell_modes(int ng);
+// modes of one cell spectrum as stored: C^2 (C/2 + 1) with C = 2 N_g + 2 ext, rounded up to a
+// multiple of 16
+size_t cell_modes(int ng, int ext);
 // the list of split parents that the cell-by-cell route visits (with the tree build)
 void build_cell_parents(Plan& p, hipStream_t s);
 void launch_m2l_cells(Plan& p, hipStream_t s);

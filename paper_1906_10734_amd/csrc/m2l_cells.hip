@@ -42,13 +42,18 @@
 
 namespace hpm {
 
-template <int NG>
+// EXT = 1: extended target gridlets (N_g + 2 nodes per axis, Sec. 2.5). Target-minus-source
+// node offsets then span 2 N_g + 1 values per axis, and C = 2 N_g + 2 keeps them apart.
+template <int NG, int EXT>
 struct CellShape {
-  static constexpr int C = 2 * NG;
-  static constexpr int HC = NG + 1;
-  static constexpr int K = C * C * HC;  // modes, [kz][ky][kx]
-  static constexpr int M = NG * NG * NG;
-  static constexpr int OFFS = 343;      // d in [-3, 3]^3, index (dx+3) + 7 (dy+3) + 49 (dz+3)
+  static constexpr int C = 2 * NG + 2 * EXT;
+  static constexpr int HC = C / 2 + 1;
+  static constexpr int K = C * C * HC;      // modes, [kz][ky][kx]
+  static constexpr int KP = (K + 15) / 16 * 16;  // stored row: K modes, then zeros
+  static constexpr int M = NG * NG * NG;    // source gridlet
+  static constexpr int NL = NG + 2 * EXT;   // target gridlet nodes per axis
+  static constexpr int ML = NL * NL * NL;
+  static constexpr int OFFS = 343;          // d in [-3, 3]^3, index (dx+3) + 7 (dy+3) + 49 (dz+3)
 };
 
 // e^{sign 2 pi i j / C} for j < C, in LDS (double sincospi, rounded once to T)
@@ -81,17 +86,17 @@ struct CellArgs {
   double* m2l_mean;      // [cells]: mean of each target's result, FP32 plans
 };
 
-template <typename T, int NG>
+template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
-  using S = CellShape<NG>;
-  constexpr int C = S::C, HC = S::HC, K = S::K, M = S::M;
+  using S = CellShape<NG, EXT>;
+  constexpr int C = S::C, HC = S::HC, K = S::K, KP = S::KP, M = S::M;
   __shared__ cplx<T> tw[C];
   __shared__ T s_g[M];
   __shared__ cplx<T> s_a1[NG * NG * HC];  // [z][y][kx]
   __shared__ cplx<T> s_a2[NG * C * HC];   // [z][ky][kx]
   const int src = blockIdx.x, tid = threadIdx.x;
   if (src == a.nsources) {  // the zero row that empty block slots read
-    for (int e = tid; e < K; e += 256) a.sspec[size_t(src) * K + e] = {T(0), T(0)};
+    for (int e = tid; e < KP; e += 256) a.sspec[size_t(src) * KP + e] = {T(0), T(0)};
     return;
   }
   load_twiddles<T, C>(tw, -1.0);
@@ -126,7 +131,8 @@ __global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
     s_a2[e] = acc;
   }
   __syncthreads();
-  cplx<T>* out = a.sspec + size_t(src) * K;
+  cplx<T>* out = a.sspec + size_t(src) * KP;
+  for (int e = K + tid; e < KP; e += 256) out[e] = {T(0), T(0)};
   for (int e = tid; e < K; e += 256) {
     const int col = e % (C * HC), kz = e / (C * HC);  // col = ky * HC + kx
     cplx<T> acc = {T(0), T(0)};
@@ -151,12 +157,12 @@ struct AccumShape {
 
 // One launch per parent level; workgroup (chunk, group): modes [chunk KM, chunk KM + KM) of the
 // split parents plist[pbeg + group PP ...], one (parent, mode) per thread.
-template <typename T, int NG>
+template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, const int* plist,
                                                      int pbeg, int pend) {
-  using S = CellShape<NG>;
+  using S = CellShape<NG, EXT>;
   using A = AccumShape<T>;
-  constexpr int K = S::K, KM = A::KM, PP = A::PP;
+  constexpr int K = S::KP, KM = A::KM, PP = A::PP;  // the stored rows (zero-padded modes)
   static_assert(K % KM == 0, "mode chunks tile the spectrum");
   __shared__ cplx<T> s_g[S::OFFS * KM];  // [offset][mode]
   __shared__ int s_src[PP * 216];         // source spectrum rows of the group's blocks
@@ -229,43 +235,47 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
   }
 }
 
-template <typename T, int NG>
+// target node t (0 .. NL-1) of an axis sits at cyclic index t - EXT (mod C)
+template <int C, int EXT>
+__device__ __forceinline__ int cyc(int t) { return t >= EXT ? t - EXT : t - EXT + C; }
+
+template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
-  using S = CellShape<NG>;
-  constexpr int C = S::C, HC = S::HC, K = S::K, M = S::M;
+  using S = CellShape<NG, EXT>;
+  constexpr int C = S::C, HC = S::HC, K = S::K, NL = S::NL, M = S::ML;
   constexpr bool split = sizeof(T) == 4;
   __shared__ cplx<double> tw[C];
   __shared__ cplx<double> s_f[K];              // [kz][ky][kx]
-  __shared__ cplx<double> s_b1[NG * C * HC];   // [z][ky][kx], z < N_g
-  __shared__ cplx<double> s_b2[NG * NG * HC];  // [z][y][kx]
+  __shared__ cplx<double> s_b1[NL * C * HC];   // [z][ky][kx], target z
+  __shared__ cplx<double> s_b2[NL * NL * HC];  // [z][y][kx]
   __shared__ double s_out[M];
   __shared__ double s_red[4];
   const int t = blockIdx.x, tid = threadIdx.x;
   load_twiddles<double, C>(tw, 1.0);
-  const cplx<T>* f = a.tspec + size_t(t) * K;
+  const cplx<T>* f = a.tspec + size_t(t) * S::KP;
   for (int e = tid; e < K; e += 256) s_f[e] = {double(f[e].re), double(f[e].im)};
   __syncthreads();
-  for (int e = tid; e < NG * C * HC; e += 256) {
-    const int col = e % (C * HC), z = e / (C * HC);
+  for (int e = tid; e < NL * C * HC; e += 256) {
+    const int col = e % (C * HC), zc = cyc<C, EXT>(e / (C * HC));
     cplx<double> acc = {0.0, 0.0};
     int m = 0;
 #pragma unroll
     for (int kz = 0; kz < C; ++kz) {
       acc = cadd(acc, cmul(s_f[kz * C * HC + col], tw[m]));
-      m += z;
+      m += zc;
       if (m >= C) m -= C;
     }
     s_b1[e] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < NG * NG * HC; e += 256) {
-    const int kx = e % HC, y = (e / HC) % NG, z = e / (HC * NG);
+  for (int e = tid; e < NL * NL * HC; e += 256) {
+    const int kx = e % HC, yc = cyc<C, EXT>((e / HC) % NL), z = e / (HC * NL);
     cplx<double> acc = {0.0, 0.0};
     int m = 0;
 #pragma unroll
     for (int ky = 0; ky < C; ++ky) {
       acc = cadd(acc, cmul(s_b1[(z * C + ky) * HC + kx], tw[m]));
-      m += y;
+      m += yc;
       if (m >= C) m -= C;
     }
     s_b2[e] = acc;
@@ -275,8 +285,8 @@ __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
   T* out = a.local + size_t(g) * M;
   double part = 0.0;
   for (int e = tid; e < M; e += 256) {
-    const int x = e % NG, zy = e / NG;  // zy = z * N_g + y
-    // real part of the Hermitian sum over kx in (-N_g, N_g]: the kx = 0 and kx = N_g (Nyquist)
+    const int xc = cyc<C, EXT>(e % NL), zy = e / NL;  // zy = z * NL + y
+    // real part of the Hermitian sum over kx in (-C/2, C/2]: the kx = 0 and kx = C/2 (Nyquist)
     // terms once, the others twice
     double acc = 0.0;
     int m = 0;
@@ -284,8 +294,8 @@ __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
     for (int kx = 0; kx < HC; ++kx) {
       const cplx<double> v = s_b2[zy * HC + kx];
       const double re = v.re * tw[m].re - v.im * tw[m].im;
-      acc += (kx == 0 || kx == NG) ? re : 2.0 * re;
-      m += x;
+      acc += (kx == 0 || kx == C / 2) ? re : 2.0 * re;
+      m += xc;
       if (m >= C) m -= C;
     }
     if constexpr (split) {
@@ -305,9 +315,9 @@ __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
   }
 }
 
-template <typename T, int NG>
+template <typename T, int NG, int EXT>
 static void cells_t(Plan& p, hipStream_t s) {
-  using S = CellShape<NG>;
+  using S = CellShape<NG, EXT>;
   p.m2l_split = sizeof(T) == 4;
   if (p.nlevels <= 2) return;
   CellArgs<T> a;
@@ -328,26 +338,29 @@ static void cells_t(Plan& p, hipStream_t s) {
   a.tspec = p.cell_tgt.as<cplx<T>>();
   a.m2l_mean = p.m2l_mean.as<double>();
   if (p.tab.gcell_levels < p.nlevels - 2) fail(HPM_ERR_DEVICE, "cell Green tables missing");
-  if (p.cell_src.bytes < size_t(a.nsources + 1) * S::K * sizeof(cplx<T>) ||
-      p.cell_tgt.bytes < size_t(ntargets) * S::K * sizeof(cplx<T>))
+  if (p.cell_src.bytes < size_t(a.nsources + 1) * S::KP * sizeof(cplx<T>) ||
+      p.cell_tgt.bytes < size_t(ntargets) * S::KP * sizeof(cplx<T>) ||
+      p.local.bytes < size_t(p.ncells) * S::ML * sizeof(T))
     fail(HPM_ERR_DEVICE, "cell spectra buffers too small");
-  k_cells_forward<T, NG><<<a.nsources + 1, 256, 0, s>>>(a);
+  k_cells_forward<T, NG, EXT><<<a.nsources + 1, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
   using A = AccumShape<T>;
   for (int lp = 1; lp + 1 < p.nlevels; ++lp) {
     const int pbeg = p.cell_pbeg[lp], pend = p.cell_pbeg[lp + 1];
     if (pend <= pbeg) continue;
     const int groups = std::min((pend - pbeg + A::PP - 1) / A::PP, 65535);
-    k_cells_accum<T, NG><<<dim3(S::K / A::KM, groups), 256, 0, s>>>(a, lp + 1,
-                                                                       p.cell_plist.as<int>(),
-                                                                       pbeg, pend);
+    k_cells_accum<T, NG, EXT><<<dim3(S::KP / A::KM, groups), 256, 0, s>>>(
+        a, lp + 1, p.cell_plist.as<int>(), pbeg, pend);
     HPM_LAUNCH_CHECK();
   }
-  k_cells_inverse<T, NG><<<ntargets, 256, 0, s>>>(a);
+  k_cells_inverse<T, NG, EXT><<<ntargets, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 
-size_t cell_modes(int ng) { return size_t(2 * ng) * (2 * ng) * (ng + 1); }
+size_t cell_modes(int ng, int ext) {
+  const size_t c = size_t(2 * ng + 2 * ext), k = c * c * (c / 2 + 1);
+  return (k + 15) / 16 * 16;
+}
 
 // ---- list of split parents (cells of levels 1 .. L-2 with children), by level ----------------
 __global__ void k_split_flags(int first, int n, const int* cflags, int* flag) {
@@ -391,24 +404,25 @@ void build_cell_parents(Plan& p, hipStream_t s) {
   for (int l = 1; l <= p.nlevels - 1; ++l) p.cell_pbeg[l] = p.hbox[Plan::kBoxCellLevels + l];
 }
 
-void launch_m2l_cells(Plan& p, hipStream_t s) {
-  if (p.prec == HPM_F32) {
-    switch (p.ng) {
-      case 2: cells_t<float, 2>(p, s); break;
-      case 3: cells_t<float, 3>(p, s); break;
-      case 4: cells_t<float, 4>(p, s); break;
-      case 6: cells_t<float, 6>(p, s); break;
-      case 8: cells_t<float, 8>(p, s); break;
-    }
-  } else {
-    switch (p.ng) {
-      case 2: cells_t<double, 2>(p, s); break;
-      case 3: cells_t<double, 3>(p, s); break;
-      case 4: cells_t<double, 4>(p, s); break;
-      case 6: cells_t<double, 6>(p, s); break;
-      case 8: cells_t<double, 8>(p, s); break;
-    }
+template <typename T>
+static void cells_dispatch(Plan& p, hipStream_t s) {
+  switch (p.ng * 2 + p.ext) {
+    case 4: cells_t<T, 2, 0>(p, s); break;
+    case 5: cells_t<T, 2, 1>(p, s); break;
+    case 6: cells_t<T, 3, 0>(p, s); break;
+    case 7: cells_t<T, 3, 1>(p, s); break;
+    case 8: cells_t<T, 4, 0>(p, s); break;
+    case 9: cells_t<T, 4, 1>(p, s); break;
+    case 12: cells_t<T, 6, 0>(p, s); break;
+    case 13: cells_t<T, 6, 1>(p, s); break;
+    case 16: cells_t<T, 8, 0>(p, s); break;
+    default: fail(HPM_ERR_UNSUPPORTED, "no cell-by-cell kernels for this gridlet");
   }
+}
+
+void launch_m2l_cells(Plan& p, hipStream_t s) {
+  if (p.prec == HPM_F32) cells_dispatch<float>(p, s);
+  else cells_dispatch<double>(p, s);
 }
 
 }  // namespace hpm

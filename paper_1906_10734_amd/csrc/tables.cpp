@@ -9,7 +9,8 @@
 //                GEMM operand W[n][p] = B^phi[p][n], zero padded.
 //   child-to-parent  1-D factors of T^C (Sec. 2.3): T1^a[p][q] = l_p((a + x_q)/2) with
 //                a = -1/2 or +1/2, the Lagrange basis l_p on the gridlet nodes (the matrix of
-//                the paper's double sum, in closed form). Parent-to-child uses the transpose.
+//                the paper's double sum, in closed form). Parent-to-child uses the transpose,
+//                on the target gridlet's nodes (N_g + 2 of them when extended, Sec. 2.5).
 //   Green transform  per level l >= 2: the exact lattice Green function G(d) = g(h_l |d|_p) of
 //                Eq. (1) on the (8 N_g)^3 grid, h_l = size / (2^l N_g), with the problem's
 //                kernel g (softened Newtonian -G (r^2+eps^2)^{-1/2}, or the screened one;
@@ -21,10 +22,12 @@
 //                target node from a source node, and divided by n^2, serves the variant of the
 //                source-to-target step that convolves along z in real space.
 //   cell-by-cell Green transforms  (only for the cell-by-cell route, Sec. 2.5) per level and
-//                source cube offset d in [-3, 3]^3: the (2 N_g)^3 cyclic array whose entry u holds
-//                g(h_l |d N_g - u_c|), u_c = u for u < N_g and u - 2 N_g otherwise, so that each
-//                node offset between the two cubes sits on its own entry; its half spectrum
-//                [kz][ky][kx <= N_g] by separable direct sums, divided by (2 N_g)^3.
+//                source cube offset d in [-3, 3]^3: the C^3 cyclic array, C = 2 N_g + 2 ext,
+//                whose entry u holds g(h_l |d N_g - u_c|), u_c = u for u < N_g + ext and u - C
+//                otherwise, so that each node offset between a target node (N_g + 2 ext per
+//                axis) and a source node sits on its own entry; its half spectrum
+//                [kz][ky][kx <= C/2] by separable direct sums, divided by C^3, each offset's
+//                row padded with zeros to a multiple of 16 modes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,12 +37,13 @@
 
 namespace hpm {
 
-static double node(int ng, int i) { return (2.0 * i + 1.0 - ng) / (2.0 * ng); }
+// node i of a gridlet of N_g points per axis widened by ext nodes on each side
+static double node(int ng, int i, int ext = 0) { return (2.0 * (i - ext) + 1.0 - ng) / (2.0 * ng); }
 
-static double lagrange(int ng, int p, double u) {
+static double lagrange(int ng, int p, double u, int ext = 0) {
   double v = 1.0;
-  for (int m = 0; m < ng; ++m)
-    if (m != p) v *= (u - node(ng, m)) / (node(ng, p) - node(ng, m));
+  for (int m = 0; m < ng + 2 * ext; ++m)
+    if (m != p) v *= (u - node(ng, m, ext)) / (node(ng, p, ext) - node(ng, m, ext));
   return v;
 }
 
@@ -86,8 +90,9 @@ static std::vector<double> invert(std::vector<double> a, int n) {
 
 // Transforms of the cyclic Green arrays of the cell-by-cell route, all levels and offsets.
 static std::vector<double> cell_green(const Plan& p, int nlev) {
-  const int ng = p.ng, C = 2 * ng, HC = ng + 1, K = C * C * HC;
-  std::vector<double> out(size_t(std::max(nlev, 1)) * 343 * K * 2, 0.0);
+  const int ng = p.ng, ext = p.ext, C = 2 * ng + 2 * ext, HC = C / 2 + 1, K = C * C * HC;
+  const int Kp = int(cell_modes(ng, ext));
+  std::vector<double> out(size_t(std::max(nlev, 1)) * 343 * Kp * 2, 0.0);
   std::vector<double> cs(size_t(C) * C), sn(size_t(C) * C);
   for (int k = 0; k < C; ++k)
     for (int j = 0; j < C; ++j) {
@@ -110,7 +115,7 @@ static std::vector<double> cell_green(const Plan& p, int nlev) {
             const int u[3] = {x, y, z};
             double r2 = 0.0;
             for (int a = 0; a < 3; ++a) {
-              const double o = double(d[a] * ng - (u[a] < ng ? u[a] : u[a] - C));
+              const double o = double(d[a] * ng - (u[a] < ng + ext ? u[a] : u[a] - C));
               r2 += o * o;
             }
             const double sd = std::sqrt(r2 * h * h + eps * eps);
@@ -144,7 +149,7 @@ static std::vector<double> cell_green(const Plan& p, int nlev) {
             a2i[(size_t(z) * C + ky) * HC + kx] = im;
           }
       // z: [kz][ky][kx], interleaved (re, im), / C^3
-      double* o = &out[(size_t(li) * 343 + od) * K * 2];
+      double* o = &out[(size_t(li) * 343 + od) * Kp * 2];
       for (int kz = 0; kz < C; ++kz)
         for (int col = 0; col < C * HC; ++col) {
           double re = 0.0, im = 0.0;
@@ -197,6 +202,13 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
     for (int pp = 0; pp < ng; ++pp)
       for (int q = 0; q < ng; ++q)
         t1[(size_t(a) * ng + pp) * ng + q] = lagrange(ng, pp, ((a ? 0.5 : -0.5) + node(ng, q)) / 2.0);
+  const int nl = p.NL;
+  std::vector<double> t1l(size_t(2) * nl * nl);
+  for (int a = 0; a < 2; ++a)
+    for (int pp = 0; pp < nl; ++pp)
+      for (int q = 0; q < nl; ++q)
+        t1l[(size_t(a) * nl + pp) * nl + q] =
+            lagrange(ng, pp, ((a ? 0.5 : -0.5) + node(ng, q, p.ext)) / 2.0, p.ext);
 
   // Green transforms, levels 2 .. nlevels-1
   const int n = 8 * ng, H = n / 2 + 1;
@@ -275,11 +287,13 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
   if (p.prec == HPM_F32) {
     upload<float>(p.tab.fitw, w, s);
     upload<float>(p.tab.m2m, t1, s);
+    upload<float>(p.tab.l2l, t1l, s);
     upload<float>(p.tab.ghat, ghat, s);
     upload<float>(p.tab.gxy, gxy, s);
   } else {
     upload<double>(p.tab.fitw, w, s);
     upload<double>(p.tab.m2m, t1, s);
+    upload<double>(p.tab.l2l, t1l, s);
     upload<double>(p.tab.ghat, ghat, s);
     upload<double>(p.tab.gxy, gxy, s);
   }

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpm.so")
 
-HPM_ABI_VERSION = 3
+HPM_ABI_VERSION = 4
 HPM_F64, HPM_F32 = 0, 1
 HPM_KERNELS = {"newton": 0, "yukawa": 1}
 HPM_M2L_MODES = {"grid": 0, "cells": 1}
@@ -33,7 +33,8 @@ class HpmProblem(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("softening", ctypes.c_double),
                 ("gconst", ctypes.c_double), ("box_lo", ctypes.c_double * 3),
                 ("box_size", ctypes.c_double), ("kernel", ctypes.c_int32),
-                ("m2l_mode", ctypes.c_int32), ("screening", ctypes.c_double)]
+                ("m2l_mode", ctypes.c_int32), ("screening", ctypes.c_double),
+                ("extended", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class HpmPlanInfo(ctypes.Structure):
@@ -109,6 +110,12 @@ class Problem:
     kernel: str = "newton"          # "newton" or "yukawa" (screened, needs screening > 0)
     screening: float = 0.0
     m2l: str = "grid"               # "grid" (the method) or "cells" (cell-by-cell comparison)
+    extended: bool = False          # target gridlets widened by one node per side (cells route)
+
+    @property
+    def nl(self) -> int:
+        """Target (local) gridlet nodes per axis."""
+        return self.ng + (2 if self.extended else 0)
 
     @property
     def dtype(self) -> torch.dtype:
@@ -130,6 +137,8 @@ class Problem:
         p.kernel = HPM_KERNELS[self.kernel]
         p.m2l_mode = HPM_M2L_MODES[self.m2l]
         p.screening = self.screening
+        p.extended = 1 if self.extended else 0
+        p.reserved = 0
         return p
 
 
@@ -213,10 +222,10 @@ class Plan:
                "hpm_plan_copy_cells")
         return dict(coords=coords, pb=pb, pe=pe, split=split.astype(bool), parent=parent)
 
-    def _rows(self, fn, level: int) -> np.ndarray:
+    def _rows(self, fn, level: int, per_axis: int | None = None) -> np.ndarray:
         cnt = self.info()["cells_per_level"][level]
         npdt = np.float32 if self.problem.precision == "f32" else np.float64
-        out = np.empty((cnt, self.problem.ng ** 3), npdt)
+        out = np.empty((cnt, (per_axis or self.problem.ng) ** 3), npdt)
         _check(fn(self._h, level, out.ctypes.data), fn.__name__)
         return out
 
@@ -225,7 +234,7 @@ class Plan:
 
     def local_parts(self, level: int):
         """(c, dPhi): per-cell constant (float64) and gridlet part (plan dtype)."""
-        d = self._rows(_lib.hpm_plan_copy_locals, level)
+        d = self._rows(_lib.hpm_plan_copy_locals, level, self.problem.nl)
         c = np.empty(d.shape[0], np.float64)
         _check(_lib.hpm_plan_copy_local_offsets(self._h, level, c.ctypes.data),
                "hpm_plan_copy_local_offsets")

@@ -36,11 +36,12 @@ def particles(name: str, prec: str):
 
 @functools.lru_cache(maxsize=None)
 def oracle(name: str, prec: str, ng: int, eps: float = 1e-3, kernel: str = "newton",
-           screening: float = 0.0, mode: str = "fft"):
+           screening: float = 0.0, mode: str = "fft", extended: bool = False):
     """Oracle HPM on the same (rounded) inputs: (hpm object, phi, acc) in input order. ``mode``
     is the oracle's source-to-target route ("fft": the padded grid, "cells": cell by cell)."""
     p, kw = particles(name, prec)
-    prob = ohpm.Problem(ng=ng, softening=eps, kernel=kernel, screening=screening, **kw)
+    prob = ohpm.Problem(ng=ng, softening=eps, kernel=kernel, screening=screening,
+                        extended=extended, **kw)
     phi, acc, h = ohpm.solve(p.x, p.y, p.z, p.m, prob, mode=mode)
     return h, phi, acc
 
@@ -51,10 +52,10 @@ def device(p, torch):
 
 
 def gpu_problem(ng: int, prec: str, kw: dict, eps: float = 1e-3, kernel: str = "newton",
-                screening: float = 0.0, m2l: str = "grid"):
+                screening: float = 0.0, m2l: str = "grid", extended: bool = False):
     from paper_1906_10734_amd import hpm
     return hpm.Problem(ng=ng, precision=prec, softening=eps, kernel=kernel, screening=screening,
-                       m2l=m2l,
+                       m2l=m2l, extended=extended,
                        uniform_depth=kw.get("uniform_depth", 0),
                        leaf_capacity=kw.get("leaf_capacity", 64),
                        max_depth=kw.get("max_depth", 10))

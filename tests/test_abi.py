@@ -39,7 +39,7 @@ def test_binding_covers_the_header():
 
 def _problem(**kw):
     from paper_1906_10734_amd import hpm
-    raw = ("abi", "kernel_id", "m2l_mode")
+    raw = ("abi", "kernel_id", "m2l_mode", "extended_id", "reserved")
     p = hpm.Problem(**{k: v for k, v in kw.items() if k not in raw}).c()
     if "abi" in kw:
         p.abi = kw["abi"]
@@ -47,6 +47,10 @@ def _problem(**kw):
         p.kernel = kw["kernel_id"]
     if "m2l_mode" in kw:
         p.m2l_mode = kw["m2l_mode"]
+    if "extended_id" in kw:
+        p.extended = kw["extended_id"]
+    if "reserved" in kw:
+        p.reserved = kw["reserved"]
     return p
 
 
@@ -55,7 +59,8 @@ def _problem(**kw):
     (dict(softening=-1.0), 1), (dict(gconst=0.0), 1), (dict(uniform_depth=11), 1),
     (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=1), 1), (dict(abi=99), 1),
     (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
-    (dict(kernel="yukawa", screening=float("nan")), 1), (dict(m2l_mode=2), 1), (dict(abi=2), 1),
+    (dict(kernel="yukawa", screening=float("nan")), 1), (dict(m2l_mode=2), 1), (dict(abi=3), 1),
+    (dict(extended=True), 6), (dict(extended_id=2, m2l="cells"), 1), (dict(reserved=1), 1),
 ])
 def test_bad_problem_rejected_on_host(kw, status):
     from paper_1906_10734_amd import hpm

@@ -95,3 +95,40 @@ def test_cells_route_small_trees():
     phi_c = hpm.solve(gpu_problem(4, "f64", dict(leaf_capacity=64), m2l="cells"), x, y, z, m)[0]
     phi_g = hpm.solve(gpu_problem(4, "f64", dict(leaf_capacity=64)), x, y, z, m)[0]
     assert torch.equal(phi_c, phi_g)
+
+
+# ---- extended target gridlets (Sec. 2.5), built on the cell-by-cell route ---------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,ng,kern", [
+    ("plummer3000_cap16", 4, {}),
+    ("clustered5000_cap8", 2, {}),
+    ("uniform4096_d3", 3, {}),
+    ("plummer3000_cap64", 6, {}),
+    ("plummer3000_cap16", 4, dict(kernel="yukawa", screening=0.05)),
+])
+def test_extended_gridlet_matches_oracle(name, ng, kern, prec):
+    # N_g + 2 target nodes per axis: the gridlets, the potentials and the accelerations against
+    # the oracle's extended cell-by-cell mode, at the same bar as the other routes
+    log(f"[cells ext] {name} ng={ng} {prec} {kern}")
+    h, ophi, oacc = oracle(name, prec, ng, mode="cells", extended=True, **kern)
+    phi, acc, locs = _run(name, ng, prec, "cells", extended=True, **kern)
+    tol = TOL[prec]
+    olocs = h.all_locals()
+    for lvl in range(2, h.tree.max_level + 1):
+        assert locs[lvl].shape == olocs[lvl].shape == (len(olocs[lvl]), (ng + 2) ** 3)
+        e = rel_max(locs[lvl], olocs[lvl])
+        assert e < tol["local"], ("locals", lvl, e)
+    e_phi, e_acc = rel_rms(phi, ophi), rel_rms(acc, oacc)
+    log(f"   phi rel rms {e_phi:.2e}  acc rel rms {e_acc:.2e}")
+    assert e_phi < tol["phi"]
+    assert e_acc < tol["acc"]
+
+
+def test_extended_gridlet_needs_the_cell_route():
+    import torch
+    from paper_1906_10734_amd import hpm
+    p, kw = particles("plummer3000_cap16", "f64")
+    x, y, z, m = device(p, torch)
+    with pytest.raises(RuntimeError, match="HPM_ERR_UNSUPPORTED"):
+        hpm.Plan(gpu_problem(4, "f64", kw, extended=True), x, y, z)
