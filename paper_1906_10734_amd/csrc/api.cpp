@@ -93,9 +93,10 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
     const size_t ntg = cells - size_t(p.level_off[2]);
     p.cell_src.reserve((ntg + size_t(p.nvirt) + 1) * spec);  // + a zero row
     p.cell_tgt.reserve(ntg * spec);
-    build_cell_parents(p, s);
+    build_cell_parents(p, s);  // read after the synchronisation of the near-zone lists
   }
   build_near_lists(p, s);
+  if (p.prob.m2l_mode == HPM_M2L_CELLS) read_cell_parents(p);
   if (p.timing) {
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));
     HPM_HIP(hipEventSynchronize(p.tree_ev[1]));

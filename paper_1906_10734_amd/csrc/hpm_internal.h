@@ -152,9 +152,10 @@ struct Plan {
   DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff;
   // pinned, device-mapped words that kernels write and the host reads after a stream
   // synchronisation (counts that size the next step of the build, input error flags)
-  static constexpr int kBoxWords = 16;
+  static constexpr int kBoxWords = 24;
   static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
   static constexpr int kBoxCellLevels = 4;  // words 5 .. 4 + L-1: split-parent list bounds
+  static constexpr int kBoxLeaves = 16;     // leaf count (read after the first virtual-cube step)
   int* hbox = nullptr;
   int* dbox = nullptr;
 
@@ -177,10 +178,11 @@ struct Plan {
 void build_tables(Plan& p, int max_levels, hipStream_t s);
 
 // ---- tree.hip -----------------------------------------------------------------------------------
+// Leaves the leaf list's counts in the mailbox; build_virtual reads them.
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
 void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
 // lists the virtual cubes of the current tree, appends them to the cell arrays and builds the
-// per-parent table of block sources
+// per-parent table of block sources; sets p.nleaves and p.nleaves_lt2 from the mailbox
 void build_virtual(Plan& p, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------
@@ -196,8 +198,11 @@ int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 // modes of one cell spectrum as stored: C^2 (C/2 + 1) with C = 2 N_g + 2 ext, rounded up to a
 // multiple of 16
 size_t cell_modes(int ng, int ext);
-// the list of split parents that the cell-by-cell route visits (with the tree build)
+// the list of split parents that the cell-by-cell route visits (with the tree build): the
+// kernels are enqueued by build_cell_parents, the per-level bounds are read from the mailbox by
+// read_cell_parents after the stream has been synchronised
 void build_cell_parents(Plan& p, hipStream_t s);
+void read_cell_parents(Plan& p);
 void launch_m2l_cells(Plan& p, hipStream_t s);
 
 // ---- downsweep.hip -------------------------------------------------------------------------------

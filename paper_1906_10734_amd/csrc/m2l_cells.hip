@@ -400,7 +400,11 @@ void build_cell_parents(Plan& p, hipStream_t s) {
   k_split_bounds<<<1, 64, 0, s>>>(p.nlevels, p.dlevel.as<int>(), first, n, p.cell_pflag.as<int>(),
                                   p.cell_ppos.as<int>(), p.dbox);
   HPM_LAUNCH_CHECK();
-  HPM_HIP(hipStreamSynchronize(s));
+}
+
+void read_cell_parents(Plan& p) {
+  for (int l = 0; l <= kMaxLevelsHost; ++l) p.cell_pbeg[l] = 0;
+  if (p.nlevels <= 2 || p.level_off[p.nlevels - 1] <= p.level_off[1]) return;
   for (int l = 1; l <= p.nlevels - 1; ++l) p.cell_pbeg[l] = p.hbox[Plan::kBoxCellLevels + l];
 }
 

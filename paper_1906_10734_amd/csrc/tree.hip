@@ -199,7 +199,7 @@ __global__ void k_keys(int n, const T* x, const T* y, const T* z, double lo0, do
 // Stable LSD radix sort of (uint32 key, int32 value), 8 bits per pass
 // ---------------------------------------------------------------------------------------------
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
+constexpr int kRsItems = 4;
 constexpr int kRsTile = kRsThreads * kRsItems;
 
 __global__ __launch_bounds__(kRsThreads) void k_radix_hist(const uint32_t* keys, int n, int shift,
@@ -502,9 +502,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
                                                 p.dbox);
   }
   HPM_LAUNCH_CHECK();
-  HPM_HIP(hipStreamSynchronize(s));
-  if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
-  if (p.hbox[Plan::kBoxOutOfBox]) fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
+  // invalid positions got key 0, so the build below stays well defined; the flags are checked
+  // at the first synchronisation of the level loop
 
   radix_sort_pairs(p, 3 * D, s);
 
@@ -553,6 +552,11 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     HPM_LAUNCH_CHECK();
     exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), cnt, d_total, p.scan_tmp, s);
     HPM_HIP(hipStreamSynchronize(s));
+    if (l == 0) {
+      if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
+      if (p.hbox[Plan::kBoxOutOfBox])
+        fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
+    }
     const int total = p.hbox[Plan::kBoxTotal];
     const int off_next = off + cnt;
     ensure_cells(p, int64_t(off_next) + total, off_next, s);
@@ -578,17 +582,20 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   p.childoff.reserve(size_t(nc) * 4);
   k_leaf_flags<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.nchild.as<int>());
   HPM_LAUNCH_CHECK();
-  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nc, d_total, p.scan_tmp, s);
+  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nc, p.dbox + Plan::kBoxLeaves,
+                     p.scan_tmp, s);
   p.leaves.reserve(size_t(nc) * 4);  // at most one leaf per cell
   const int first2 = p.nlevels > 2 ? p.level_off[2] : -1;
   k_leaf_compact<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.childoff.as<int>(),
                                                p.leaves.as<int>(), first2,
                                                p.dbox + Plan::kBoxLeavesLt2);
   HPM_LAUNCH_CHECK();
-  HPM_HIP(hipStreamSynchronize(s));
-  const int nleaves = p.hbox[Plan::kBoxTotal];
-  p.nleaves = nleaves;
-  p.nleaves_lt2 = (p.nlevels > 2) ? p.hbox[Plan::kBoxLeavesLt2] : nleaves;
+  // the counts are read by build_virtual after its first synchronisation
+}
+
+static void read_leaf_counts(Plan& p) {
+  p.nleaves = p.hbox[Plan::kBoxLeaves];
+  p.nleaves_lt2 = (p.nlevels > 2) ? p.hbox[Plan::kBoxLeavesLt2] : p.nleaves;
 }
 
 
@@ -737,11 +744,14 @@ static void build_block_table(Plan& p, const VirtArgs& a, int nt, hipStream_t s)
 
 void build_virtual(Plan& p, hipStream_t s) {
   p.nvirt = 0;
-  if (p.nlevels <= 2) return;
   // parents of targets: cells of levels 1 .. nlevels-2
-  const int first = p.level_off[1];
-  const int nt = p.level_off[p.nlevels - 1] - first;
-  if (nt <= 0) return;
+  const int first = p.nlevels > 2 ? p.level_off[1] : 0;
+  const int nt = p.nlevels > 2 ? p.level_off[p.nlevels - 1] - first : 0;
+  if (nt <= 0) {
+    HPM_HIP(hipStreamSynchronize(s));
+    read_leaf_counts(p);
+    return;
+  }
   VirtArgs a;
   a.first_target = first;
   a.depth = p.depth;
@@ -765,6 +775,7 @@ void build_virtual(Plan& p, hipStream_t s) {
   int* d_total = p.dbox + Plan::kBoxTotal;
   exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
   HPM_HIP(hipStreamSynchronize(s));
+  read_leaf_counts(p);
   const int refs = p.hbox[Plan::kBoxTotal];
   if (refs <= 0) {
     build_block_table(p, a, nt, s);
