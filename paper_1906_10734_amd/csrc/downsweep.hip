@@ -258,10 +258,25 @@ struct P2PArgs {
   T inv_lam;  // 1 / screening length (screened kernel)
 };
 
+// 1/sqrt(x). In single precision the hardware reciprocal square root (about 1 ulp); the softened
+// squared distances it sees are far above the denormal range, so no input scaling is needed.
+// In double: the hardware's estimate refined by two Newton-Raphson steps for f(y) = 1/y^2 - x,
+// y <- y + y (1 - x y^2) / 2; each step squares the relative error, which leaves it at
+// rounding level. x = 0 keeps the estimate (+inf).
 template <typename T>
 __device__ __forceinline__ T inv_sqrt(T x) {
-  if constexpr (sizeof(T) == 4) return rsqrtf(x);
-  else return 1.0 / sqrt(x);
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_amdgcn_rsqf(x);
+  } else {
+    double y = __builtin_amdgcn_rsq(x);
+    if (!(x > 0.0) || isinf(x)) return y;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double e = fma(-x * y, y, 1.0);
+      y = fma(0.5 * y, e, y);
+    }
+    return y;
+  }
 }
 
 // Pair terms of the interaction kernel (without G) from inv = 1/s, s the softened distance:
@@ -286,14 +301,16 @@ struct alignas(4 * sizeof(T)) SrcP {
   T x, y, z, m;
 };
 
-// Lanes split as (target tl < kp, source group grp < 64/kp) when the chunk has fewer than 64
-// targets; sources are staged 64 at a time in LDS (position and mass in one 4-vector) and the
-// groups are combined with shuffles. The self pair is recognised by its place in the source
-// sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
+// Lanes split as (target tl < K, source group grp < 64/K) when the chunk has K < 64 targets
+// (lanes past the last whole group idle); sources are staged 64 at a time in LDS (position and
+// mass in one 4-vector), and the groups' partial sums are combined in group order through LDS.
+// The self pair is recognised by its place in the source sequence: the target leaf's own cube
+// is entry 13 of its 27 near cubes.
 template <typename T, int KER>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
   __shared__ SrcP<T> s_src[64];
+  __shared__ T s_part[5][64];
   const int lane = threadIdx.x;
   const int4 it = a.items[blockIdx.x];
   const int li = it.x, t0 = it.y, s0 = it.z, S = it.w;
@@ -312,12 +329,11 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     if (lane < 28) s_pre[lane] = x - len;  // exclusive prefix; s_pre[27] = total
   }
   __syncthreads();
-  int kp = 1;
-  while (kp < K) kp <<= 1;
+  const int kp = K;  // 1 .. 64
   const int G = 64 / kp;
   const int tl = lane % kp, grp = lane / kp;
   const int i = pb + t0 + tl;
-  const bool valid = tl < K;
+  const bool valid = grp < G;
   const int self = s_pre[13] + (i - s_rb[13]);  // the target's own place in the source sequence
   T xi = T(0), yi = T(0), zi = T(0);
   if (valid) {
@@ -327,6 +343,24 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   }
   T ph = T(0), phc = T(0), fx = T(0), fy = T(0), fz = T(0);
   const int s_end = min(S, s0 + kP2PChunk);
+  // the chunk's own targets occupy [self_lo, self_hi) of the source sequence
+  const int self_lo = s_pre[13] + (pb + t0 - s_rb[13]), self_hi = self_lo + K;
+  auto pair = [&](const SrcP<T>& q, bool skip) {
+    const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+    const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
+    const T inv = skip ? T(0) : inv_sqrt(r2);
+    T w, c;
+    pair_terms<KER>(r2, inv, a.inv_lam, w, c);
+    const T mi = q.m * w;
+    const T mi3 = q.m * c;
+    const T yv = -mi - phc;  // Kahan: ph += -m w
+    const T tv = ph + yv;
+    phc = (tv - ph) - yv;
+    ph = tv;
+    fx -= mi3 * dx;
+    fy -= mi3 * dy;
+    fz -= mi3 * dz;
+  };
   for (int tile = s0; tile < s_end; tile += 64) {
     const int sidx = tile + lane;
     __syncthreads();
@@ -343,37 +377,34 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     __syncthreads();
     const int cnt = min(64, s_end - tile);
     if (valid) {
-      for (int e = grp; e < cnt; e += G) {
-        const SrcP<T> q = s_src[e];
-        const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-        const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
-        const T inv = (tile + e == self) ? T(0) : inv_sqrt(r2);
-        T w, c;
-        pair_terms<KER>(r2, inv, a.inv_lam, w, c);
-        const T mi = q.m * w;
-        const T mi3 = q.m * c;
-        const T yv = -mi - phc;  // Kahan: ph += -m w
-        const T tv = ph + yv;
-        phc = (tv - ph) - yv;
-        ph = tv;
-        fx -= mi3 * dx;
-        fy -= mi3 * dy;
-        fz -= mi3 * dz;
+      if (tile < self_hi && tile + cnt > self_lo) {  // the tile may hold the target itself
+        for (int e = grp; e < cnt; e += G) pair(s_src[e], tile + e == self);
+      } else {
+#pragma unroll 4
+        for (int e = grp; e < cnt; e += G) pair(s_src[e], false);
       }
     }
   }
-  T phs = ph, phe = -phc;
-  for (int o = kp; o < 64; o <<= 1) {
-    const T ophs = __shfl_xor(phs, o, 64), ophe = __shfl_xor(phe, o, 64);
-    T s, err;
-    two_sum(phs, ophs, s, err);
-    phe += ophe + err;
-    phs = s;
-    fx += __shfl_xor(fx, o, 64);
-    fy += __shfl_xor(fy, o, 64);
-    fz += __shfl_xor(fz, o, 64);
+  if (G > 1) {
+    s_part[0][lane] = ph;
+    s_part[1][lane] = -phc;
+    s_part[2][lane] = fx;
+    s_part[3][lane] = fy;
+    s_part[4][lane] = fz;
   }
+  __syncthreads();
   if (grp == 0) {
+    T phs = ph, phe = -phc;
+    for (int q = 1; q < G; ++q) {
+      const int o = q * kp + tl;
+      T s, err;
+      two_sum(phs, s_part[0][o], s, err);
+      phe += s_part[1][o] + err;
+      phs = s;
+      fx += s_part[2][o];
+      fy += s_part[3][o];
+      fz += s_part[4][o];
+    }
     T* out = a.partial + (size_t(blockIdx.x) * 64 + tl) * 5;
     out[0] = phs;
     out[1] = phe;
