@@ -129,6 +129,7 @@ struct Plan {
   DevBuf blocks;
   int blocks_first = 0;
   DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
+  DevBuf dlev;    // the tree build's level table (cell ranges per level, overflow flag)
   // gridlets
   DevBuf gridlet, local, moments;  // gridlet [cells + virtual][M], local [cells][ML]
   DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
@@ -152,10 +153,11 @@ struct Plan {
   DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff;
   // pinned, device-mapped words that kernels write and the host reads after a stream
   // synchronisation (counts that size the next step of the build, input error flags)
-  static constexpr int kBoxWords = 24;
+  static constexpr int kBoxWords = 64;
   static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
   static constexpr int kBoxCellLevels = 4;  // words 5 .. 4 + L-1: split-parent list bounds
   static constexpr int kBoxLeaves = 16;     // leaf count (read after the first virtual-cube step)
+  static constexpr int kBoxLev = 24;        // words 24 .. 63: copy of the device level table
   int* hbox = nullptr;
   int* dbox = nullptr;
 

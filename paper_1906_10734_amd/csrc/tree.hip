@@ -47,8 +47,13 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* s_wave, int* tot
   return wave_pre + x - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, int n, int* sums) {
+// n is the length, or its upper bound when dn (the length in device memory) is given.
+__device__ __forceinline__ int scan_len(int n, const int* dn) { return dn ? min(*dn, n) : n; }
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, int n, const int* dn,
+                                                              int* sums) {
   __shared__ int s_wave[kScanThreads / 64];
+  n = scan_len(n, dn);
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v = 0;
 #pragma unroll
@@ -60,8 +65,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, int
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* out, int n,
-                                                            const int* block_off, int* total_out) {
+                                                            const int* dn, const int* block_off,
+                                                            int* total_out) {
   __shared__ int s_wave[kScanThreads / 64];
+  n = scan_len(n, dn);
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
   int sum = 0;
@@ -87,9 +94,10 @@ constexpr int kScanSingleThreads = 1024;
 constexpr int kScanSingleMax = kScanSingleThreads * kScanItems;
 
 __global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* in, int* out, int n,
-                                                                    int* total_out) {
+                                                                    const int* dn, int* total_out) {
   __shared__ int s_wave[kScanSingleThreads / 64];
   __shared__ int s_run;
+  n = scan_len(n, dn);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_run = 0;
   __syncthreads();
@@ -137,24 +145,27 @@ static size_t scan_tmp_ints(int n) {
   return t + 16;
 }
 
-static void scan_rec(const int* in, int* out, int n, int* total, int* tmp, hipStream_t s) {
+// Tiles are laid out for n; with dn the kernels scan only the first *dn (<= n) values, and the
+// tile sums past them are zero, so the recursion over the sums needs no device length.
+static void scan_rec(const int* in, int* out, int n, const int* dn, int* total, int* tmp,
+                     hipStream_t s) {
   const int nb = (n + kScanTile - 1) / kScanTile;
   if (nb <= 1) {
-    k_scan_tile<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total);
+    k_scan_tile<<<1, kScanThreads, 0, s>>>(in, out, n, dn, nullptr, total);
     HPM_LAUNCH_CHECK();
     return;
   }
   if (n <= kScanSingleMax) {
-    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, n, total);
+    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, n, dn, total);
     HPM_LAUNCH_CHECK();
     return;
   }
   int* sums = tmp;
   int* sums_scan = tmp + nb;
-  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, sums);
+  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, dn, sums);
   HPM_LAUNCH_CHECK();
-  scan_rec(sums, sums_scan, nb, total, tmp + 2 * nb, s);
-  k_scan_tile<<<nb, kScanThreads, 0, s>>>(in, out, n, sums_scan, nullptr);
+  scan_rec(sums, sums_scan, nb, nullptr, total, tmp + 2 * nb, s);
+  k_scan_tile<<<nb, kScanThreads, 0, s>>>(in, out, n, dn, sums_scan, nullptr);
   HPM_LAUNCH_CHECK();
 }
 
@@ -164,7 +175,16 @@ void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp,
   tmp.reserve(scan_tmp_ints(n) * sizeof(int));
   int* t = tmp.as<int>();
   // the last two ints of tmp hold a total when the caller passes none
-  scan_rec(in, out, n, total, t, s);
+  scan_rec(in, out, n, nullptr, total, t, s);
+}
+
+// The same over the first *dn values (device memory, at most nmax); tmp must already hold the
+// scratch for nmax (no allocation here, so that it can run between kernels still in flight).
+static void exclusive_scan_i32_dn(const int* in, int* out, int nmax, const int* dn, int* total,
+                                  DevBuf& tmp, hipStream_t s) {
+  if (nmax <= 0) return;
+  if (tmp.bytes < scan_tmp_ints(nmax) * sizeof(int)) fail(HPM_ERR_DEVICE, "scan scratch too small");
+  scan_rec(in, out, nmax, dn, total, tmp.as<int>(), s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -343,9 +363,16 @@ static CellArrays cells_of(Plan& p) {
           p.cparent.as<int>(),   p.cflags.as<int>(),  p.child8.as<int>(), p.nbr27.as<int>()};
 }
 
-__global__ void k_root(int n, CellArrays c) {
+// Level table in device memory, written by the level kernels as the tree grows, so that the
+// level loop runs without host round trips: first cell id and cell count of each level, and the
+// level whose children did not fit the cell arrays (-1: none; every later level kernel then
+// returns, and the host grows the arrays and resumes there).
+constexpr int kLevOff = 0, kLevCnt = 16, kLevOverflow = 32, kLevWords = 40;
+
+__global__ void k_root(int n, CellArrays c, int* lev) {
   const int t = threadIdx.x;
   if (t < 27) c.nbr27[t] = (t == 13) ? 0 : -1;
+  if (t < kLevWords) lev[t] = (t == kLevCnt) ? 1 : (t == kLevOverflow ? -1 : 0);
   if (t == 0) {
     c.key[0] = 0;
     c.coord[0] = 0;
@@ -355,91 +382,112 @@ __global__ void k_root(int n, CellArrays c) {
   }
 }
 
+__global__ void k_lev_resume(int* lev) { lev[kLevOverflow] = -1; }
+
 // Split decision and the 9 boundaries of the child ranges of each cell of level l: eight lanes
 // per cell, lane k finds the first particle of child octant k by binary search in the cell's
-// (key-sorted) range.
-__global__ void k_level_split(int l, int depth, int uniform, int cap, int off, int cnt,
+// (key-sorted) range. Grid-stride over the level's cells (count from the level table).
+__global__ void k_level_split(int l, int depth, int uniform, int cap, const int* lev,
                               const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = t >> 3, k = t & 7;
-  const bool live = i < cnt;
-  int b = 0, nonempty = 0;
-  bool split = false;
-  int pe = 0;
-  if (live) {
-    const int g = off + i;
-    const int pb = c.pb[g];
-    pe = c.pe[g];
-    split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
-    if (k == 0) c.flags[g] = split ? 1 : 0;
-    if (split) {
-      const int shift = 3 * (depth - l - 1);
-      const uint32_t base = c.key[g] << 3;
-      b = (k == 0) ? pb : lower_bound_u32(keys, pb, pe, (base + uint32_t(k)) << shift);
-      bounds[i * 9 + k] = b;
-      if (k == 7) bounds[i * 9 + 8] = pe;
-    }
-  }
-  // child k is nonempty if the next boundary is past this one (lanes k+1 of the same cell)
-  const int next = __shfl_down(b, 1, 8);
-  if (live && split) nonempty = ((k == 7) ? pe : next) > b ? 1 : 0;
-  int nc = nonempty;
-  nc += __shfl_xor(nc, 1, 8);
-  nc += __shfl_xor(nc, 2, 8);
-  nc += __shfl_xor(nc, 4, 8);
-  if (live && k == 0) nchild[i] = split ? nc : 0;
-}
-
-__global__ void k_level_emit(int off, int cnt, int off_next, const int* bounds,
-                             const int* childoff, CellArrays c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  const int g = off + i;
-  const bool split = c.flags[g] & 1;
-  const int cx = coord_x(c.coord[g]), cy = coord_y(c.coord[g]), cz = coord_z(c.coord[g]);
-  int r = 0;
-  for (int k = 0; k < 8; ++k) {
-    int id = -1;
-    if (split) {
-      const int b0 = bounds[i * 9 + k], b1 = bounds[i * 9 + k + 1];
-      if (b1 > b0) {
-        id = off_next + childoff[i] + r++;
-        c.key[id] = (c.key[g] << 3) | uint32_t(k);
-        c.coord[id] = pack_coord(2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + ((k >> 2) & 1));
-        c.pb[id] = b0;
-        c.pe[id] = b1;
-        c.parent[id] = g;
+  if (lev[kLevOverflow] >= 0) return;
+  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
+  for (int64_t t0 = int64_t(blockIdx.x) * blockDim.x; t0 < int64_t(cnt) * 8;
+       t0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t t = t0 + threadIdx.x;
+    const int i = int(t >> 3), k = int(t & 7);
+    const bool live = i < cnt;
+    int b = 0, nonempty = 0;
+    bool split = false;
+    int pe = 0;
+    if (live) {
+      const int g = off + i;
+      const int pb = c.pb[g];
+      pe = c.pe[g];
+      split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
+      if (k == 0) c.flags[g] = split ? 1 : 0;
+      if (split) {
+        const int shift = 3 * (depth - l - 1);
+        const uint32_t base = c.key[g] << 3;
+        b = (k == 0) ? pb : lower_bound_u32(keys, pb, pe, (base + uint32_t(k)) << shift);
+        bounds[i * 9 + k] = b;
+        if (k == 7) bounds[i * 9 + 8] = pe;
       }
     }
-    c.child8[g * 8 + k] = id;
+    // child k is nonempty if the next boundary is past this one (lanes k+1 of the same cell)
+    const int next = __shfl_down(b, 1, 8);
+    if (live && split) nonempty = ((k == 7) ? pe : next) > b ? 1 : 0;
+    int nc = nonempty;
+    nc += __shfl_xor(nc, 1, 8);
+    nc += __shfl_xor(nc, 2, 8);
+    nc += __shfl_xor(nc, 4, 8);
+    if (live && k == 0) nchild[i] = split ? nc : 0;
+  }
+}
+
+// Children of the cells of level l at ids off_next + childoff[i] + r (the scan of the split
+// counts left the number of level-(l+1) cells in the table); flags the overflow instead when they
+// do not fit in cap cells.
+__global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, const int* childoff,
+                             CellArrays c) {
+  if (lev[kLevOverflow] >= 0) return;
+  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l], total = lev[kLevCnt + l + 1];
+  const int off_next = off + cnt;
+  if (int64_t(off_next) + total > cap_cells) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) lev[kLevOverflow] = l;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) lev[kLevOff + l + 1] = off_next;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int g = off + i;
+    const bool split = c.flags[g] & 1;
+    const int cx = coord_x(c.coord[g]), cy = coord_y(c.coord[g]), cz = coord_z(c.coord[g]);
+    int r = 0;
+    for (int k = 0; k < 8; ++k) {
+      int id = -1;
+      if (split) {
+        const int b0 = bounds[i * 9 + k], b1 = bounds[i * 9 + k + 1];
+        if (b1 > b0) {
+          id = off_next + childoff[i] + r++;
+          c.key[id] = (c.key[g] << 3) | uint32_t(k);
+          c.coord[id] = pack_coord(2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + ((k >> 2) & 1));
+          c.pb[id] = b0;
+          c.pe[id] = b1;
+          c.parent[id] = g;
+        }
+      }
+      c.child8[g * 8 + k] = id;
+    }
   }
 }
 
 // 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
-// thread per (cell, neighbour) entry.
-__global__ void k_level_nbr(int l, int off, int cnt, CellArrays c) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = t / 27, j = t % 27;
-  if (i >= cnt) return;
-  const int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
-  const int g = off + i;
-  const int pc = c.coord[g];
-  const int x = coord_x(pc), y = coord_y(pc), z = coord_z(pc);
-  const int par = c.parent[g];
-  const int side = 1 << l;
-  const int qx = x + dx, qy = y + dy, qz = z + dz;
-  int v = -1;
-  if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
-    const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
-    const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
-    if (e >= 0) {
-      if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
-      else v = -2 - e;
-    } else {
-      v = e;
+// thread per (cell, neighbour) entry, grid-stride.
+__global__ void k_level_nbr(int l, const int* lev, CellArrays c) {
+  if (lev[kLevOverflow] >= 0) return;
+  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(cnt) * 27;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(t / 27), j = int(t % 27);
+    const int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
+    const int g = off + i;
+    const int pc = c.coord[g];
+    const int x = coord_x(pc), y = coord_y(pc), z = coord_z(pc);
+    const int par = c.parent[g];
+    const int side = 1 << l;
+    const int qx = x + dx, qy = y + dy, qz = z + dz;
+    int v = -1;
+    if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
+      const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
+      const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+      if (e >= 0) {
+        if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
+        else v = -2 - e;
+      } else {
+        v = e;
+      }
     }
+    c.nbr27[g * 27 + j] = v;
   }
-  c.nbr27[g * 27 + j] = v;
 }
 
 __global__ void k_leaf_flags(int ncells, const int* flags, int* isleaf) {
@@ -523,7 +571,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
                                                    p.zs.as<double>());
   HPM_LAUNCH_CHECK();
 
-  // levels
+  // levels, all enqueued back to back: every level kernel reads its level's cell range from the
+  // device table, and the host waits once, at the end (or where the cells outgrew the arrays)
   int64_t est = 64;
   if (uniform) {
     int64_t lvl = 1;
@@ -533,45 +582,75 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
       lvl *= 8;
     }
   } else {
-    est = std::max<int64_t>(1024, 3 * int64_t(n) / std::max(1, pr.leaf_capacity) + 64);
+    est = std::max<int64_t>(1024, 6 * int64_t(n) / std::max(1, pr.leaf_capacity) + 64);
   }
   ensure_cells(p, est, 0, s);
-  k_root<<<1, 64, 0, s>>>(n, cells_of(p));
+  p.dlev.reserve(kLevWords * sizeof(int));
+  int* lev = p.dlev.as<int>();
+  auto level_scratch = [&](int64_t keep) {
+    const size_t c = size_t(p.cap_cells);
+    p.bounds.grow(c * 9 * 4, size_t(keep) * 9 * 4, s);
+    p.childoff.grow(c * 4, size_t(keep) * 4, s);
+    p.nchild.grow(c * 4, 0, s);
+    p.scan_tmp.reserve(scan_tmp_ints(int(std::min<int64_t>(c, n))) * sizeof(int));
+  };
+  level_scratch(0);
+  k_root<<<1, 64, 0, s>>>(n, cells_of(p), lev);
   HPM_LAUNCH_CHECK();
-  int off = 0, cnt = 1;
-  p.level_off[0] = 0;
-  p.nlevels = 1;
-  int* d_total = p.dbox + Plan::kBoxTotal;
-  for (int l = 0; l <= D; ++l) {
-    p.bounds.reserve(size_t(cnt) * 9 * 4);
-    p.nchild.reserve(size_t(cnt) * 4);
-    p.childoff.reserve(size_t(cnt) * 4);
-    k_level_split<<<nblk(int64_t(cnt) * 8, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, off,
-                                                 cnt, p.keys.as<uint32_t>(), cells_of(p),
-                                                 p.bounds.as<int>(), p.nchild.as<int>());
-    HPM_LAUNCH_CHECK();
-    exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), cnt, d_total, p.scan_tmp, s);
+  auto grid = [](int64_t work, int t) { return int(std::max<int64_t>(1, std::min<int64_t>((work + t - 1) / t, 4096))); };
+  auto enqueue = [&](int from, bool resume_emit) {
+    const CellArrays c = cells_of(p);
+    for (int l = from; l <= D; ++l) {
+      // cells of level l: at most 8^l, n (nonempty) and the capacity
+      const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
+      if (!(l == from && resume_emit)) {
+        k_level_split<<<grid(ub * 8, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, lev,
+                                                      p.keys.as<uint32_t>(), c, p.bounds.as<int>(),
+                                                      p.nchild.as<int>());
+        HPM_LAUNCH_CHECK();
+        exclusive_scan_i32_dn(p.nchild.as<int>(), p.childoff.as<int>(), int(ub),
+                              lev + kLevCnt + l, lev + kLevCnt + l + 1, p.scan_tmp, s);
+      }
+      k_level_emit<<<grid(ub, 128), 128, 0, s>>>(l, int(p.cap_cells), lev, p.bounds.as<int>(),
+                                                 p.childoff.as<int>(), c);
+      HPM_LAUNCH_CHECK();
+      if (l < D) {
+        const int64_t ub1 = std::min<int64_t>({int64_t(1) << (3 * l + 3), int64_t(n), p.cap_cells});
+        k_level_nbr<<<grid(ub1 * 27, 256), 256, 0, s>>>(l + 1, lev, c);
+        HPM_LAUNCH_CHECK();
+      }
+    }
+  };
+  const int* hl = p.hbox + Plan::kBoxLev;
+  enqueue(0, false);
+  for (bool first = true;; first = false) {
+    HPM_HIP(hipMemcpyAsync(p.hbox + Plan::kBoxLev, lev, kLevWords * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
     HPM_HIP(hipStreamSynchronize(s));
-    if (l == 0) {
+    if (first) {
       if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
       if (p.hbox[Plan::kBoxOutOfBox])
         fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
     }
-    const int total = p.hbox[Plan::kBoxTotal];
-    const int off_next = off + cnt;
-    ensure_cells(p, int64_t(off_next) + total, off_next, s);
-    k_level_emit<<<nblk(cnt, 128), 128, 0, s>>>(off, cnt, off_next, p.bounds.as<int>(),
-                                                p.childoff.as<int>(), cells_of(p));
+    const int ov = hl[kLevOverflow];
+    if (ov < 0) break;
+    // the children of level ov did not fit: keep the levels up to ov (and ov's split), grow,
+    // and emit from level ov on
+    const int64_t keep = int64_t(hl[kLevOff + ov]) + hl[kLevCnt + ov];
+    const int64_t need = keep + hl[kLevCnt + ov + 1];
+    ensure_cells(p, need + need / 2 + 64, keep, s);
+    level_scratch(hl[kLevCnt + ov]);
+    k_lev_resume<<<1, 1, 0, s>>>(lev);
     HPM_LAUNCH_CHECK();
-    if (total == 0) break;
-    p.level_off[l + 1] = off_next;
-    p.nlevels = l + 2;
-    off = off_next;
-    cnt = total;
-    k_level_nbr<<<nblk(int64_t(cnt) * 27, 256), 256, 0, s>>>(l + 1, off, cnt, cells_of(p));
-    HPM_LAUNCH_CHECK();
+    enqueue(ov, true);
   }
-  p.ncells = off + cnt;
+  p.nlevels = 0;
+  for (int l = 0; l <= D; ++l) {
+    if (hl[kLevCnt + l] <= 0) break;
+    p.level_off[l] = hl[kLevOff + l];
+    p.nlevels = l + 1;
+  }
+  p.ncells = int64_t(p.level_off[p.nlevels - 1]) + hl[kLevCnt + p.nlevels - 1];
   for (int l = p.nlevels; l <= kMaxLevelsHost; ++l) p.level_off[l] = int(p.ncells);
   p.dlevel.reserve(sizeof(p.level_off));
   HPM_HIP(hipMemcpyAsync(p.dlevel.p, p.level_off, sizeof(p.level_off), hipMemcpyHostToDevice, s));

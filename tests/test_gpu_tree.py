@@ -58,3 +58,39 @@ def test_out_of_box_and_nan_are_reported():
     x[2] = 1.0  # the upper face belongs to the last cell
     plan = hpm.Plan(hpm.Problem(precision="f64"), x, y, y)
     assert plan.info()["n_particles"] == 3
+
+
+def test_rebuild_outgrowing_the_cell_arrays():
+    # 300 tight clumps of 65 particles (leaf capacity 64): each clump is a chain of one cell per
+    # level down to the maximum depth, about 2400 cells for 19500 particles, more than the plan's
+    # first estimate (6 n / capacity). The level loop stops where the cells outgrow the arrays,
+    # the host grows them and the build resumes there; the tree must equal the oracle's exactly,
+    # for a fresh plan and for a rebuild of a plan made for a small set.
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import uniform_cube
+    rng = np.random.default_rng(5)
+    centers = rng.random((300, 3)) * 0.98 + 0.01
+    pos = (centers[:, None, :] + rng.random((300, 65, 3)) * 1e-5).reshape(-1, 3)
+    t = Tree(pos, leaf_capacity=64, max_depth=10)
+    assert sum(len(l) for l in t.levels) > 6 * len(pos) // 64 + 64
+    x, y, z = (torch.tensor(pos[:, k], dtype=torch.float64, device="cuda") for k in range(3))
+    small = uniform_cube(64, 31).astype(np.float64)
+    xs, ys, zs, _ = device(small, torch)
+    kw = dict(leaf_capacity=64, max_depth=10)
+    fresh = hpm.Plan(gpu_problem(4, "f64", kw), x, y, z)
+    grown = hpm.Plan(gpu_problem(4, "f64", kw), xs, ys, zs)
+    grown.rebuild(x, y, z)
+    for plan in (fresh, grown):
+        info = plan.info()
+        log(f"[tree regrow] levels {info['cells_per_level']}")
+        assert info["cells_per_level"] == [len(l) for l in t.levels]
+        assert np.array_equal(plan.perm(), t.perm)
+        for l, lev in enumerate(t.levels):
+            c = plan.cells(l)
+            assert np.array_equal(c["coords"], lev.coords), l
+            assert np.array_equal(c["pb"], lev.pb), l
+            assert np.array_equal(c["pe"], lev.pe), l
+            assert np.array_equal(c["split"], lev.split), l
+            assert np.array_equal(c["parent"], lev.parent), l
+        plan.close()
