@@ -2,6 +2,9 @@
 (same problem, same plan calls), checked on sampled outputs against values the FP64 oracle wrote
 (tests/golden/make_plummer2p18.py): 256 particles' potentials and accelerations, and the local
 gridlet potentials of 48 target cells at levels >= 2, matched by level and integer coordinates.
+Every source-to-target route the benchmark times is checked: the padded grid, the cell-by-cell
+route (against the same values: the oracle's two modes agree to rounding) and the cell route with
+extended target gridlets (against the oracle's extended values).
 
 Tolerances as in the small-case parity tests: FP64 path 1e-10 relative, FP32 path 1e-5 relative
 RMS in potential (acceleration 1e-4, local gridlets 2e-5 of the level's largest value)."""
@@ -22,16 +25,27 @@ TOL = {"f64": dict(local=1e-10, phi=1e-10, acc=1e-9),
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("ng", [4, 6])
 def test_plummer2p18_sampled_outputs_match_oracle(ng, prec):
+    _check(ng, prec, "grid", False)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("ng,extended", [(4, False), (6, False), (4, True), (6, True)])
+def test_plummer2p18_cell_route_matches_oracle(ng, extended, prec):
+    _check(ng, prec, "cells", extended)
+
+
+def _check(ng, prec, m2l, extended):
     import torch
     from paper_1906_10734_amd import hpm
     from synth import plummer_sphere
-    gold = np.load(os.path.join(HERE, "golden", f"plummer2p18_ng{ng}_{prec}.npz"))
-    log(f"[fullsize] plummer 2^18 ng={ng} {prec}")
+    tag = "_ext" if extended else ""
+    gold = np.load(os.path.join(HERE, "golden", f"plummer2p18_ng{ng}{tag}_{prec}.npz"))
+    log(f"[fullsize] plummer 2^18 ng={ng} {prec} {m2l}{tag}")
     p = plummer_sphere(2 ** 18, 1001).astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
     x, y, z, m = (torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
     plan = hpm.Plan(hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10,
-                                softening=1e-3), x, y, z)
+                                softening=1e-3, m2l=m2l, extended=extended), x, y, z)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(2):  # the benchmark's step: rebuild, then execute
         plan.rebuild(x, y, z)
