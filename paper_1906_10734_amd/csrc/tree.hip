@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* 
 }
 
 // One workgroup scans up to kScanSingleMax values in chunks of 1024 x 8 with a running offset
-// (one launch instead of three for the medium sizes of the tree build).
+// (one launch instead of three for the medium sizes of the tree build; larger inputs scan faster
+// on many workgroups).
 constexpr int kScanSingleThreads = 1024;
 constexpr int kScanSingleMax = kScanSingleThreads * kScanItems;
 
@@ -384,13 +385,18 @@ __global__ void k_root(int n, CellArrays c, int* lev) {
 
 __global__ void k_lev_resume(int* lev) { lev[kLevOverflow] = -1; }
 
+__device__ void level_nbr(int l, int off, int cnt, CellArrays c);
+
 // Split decision and the 9 boundaries of the child ranges of each cell of level l: eight lanes
 // per cell, lane k finds the first particle of child octant k by binary search in the cell's
-// (key-sorted) range. Grid-stride over the level's cells (count from the level table).
+// (key-sorted) range. Grid-stride over the level's cells (count from the level table). For
+// l >= 1 the same launch first fills the level's 27-cube neighbourhoods (they read only level
+// l-1, which the previous launches completed).
 __global__ void k_level_split(int l, int depth, int uniform, int cap, const int* lev,
                               const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
   if (lev[kLevOverflow] >= 0) return;
   const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
+  if (l >= 1) level_nbr(l, off, cnt, c);
   for (int64_t t0 = int64_t(blockIdx.x) * blockDim.x; t0 < int64_t(cnt) * 8;
        t0 += int64_t(gridDim.x) * blockDim.x) {
     const int64_t t = t0 + threadIdx.x;
@@ -462,9 +468,7 @@ __global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, 
 
 // 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
 // thread per (cell, neighbour) entry, grid-stride.
-__global__ void k_level_nbr(int l, const int* lev, CellArrays c) {
-  if (lev[kLevOverflow] >= 0) return;
-  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
+__device__ void level_nbr(int l, int off, int cnt, CellArrays c) {
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(cnt) * 27;
        t += int64_t(gridDim.x) * blockDim.x) {
     const int i = int(t / 27), j = int(t % 27);
@@ -597,16 +601,18 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   level_scratch(0);
   k_root<<<1, 64, 0, s>>>(n, cells_of(p), lev);
   HPM_LAUNCH_CHECK();
-  auto grid = [](int64_t work, int t) { return int(std::max<int64_t>(1, std::min<int64_t>((work + t - 1) / t, 4096))); };
+  auto grid = [](int64_t work, int t) {
+    return int(std::max<int64_t>(1, std::min<int64_t>((work + t - 1) / t, 4096)));
+  };
   auto enqueue = [&](int from, bool resume_emit) {
     const CellArrays c = cells_of(p);
     for (int l = from; l <= D; ++l) {
       // cells of level l: at most 8^l, n (nonempty) and the capacity
       const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
       if (!(l == from && resume_emit)) {
-        k_level_split<<<grid(ub * 8, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity, lev,
-                                                      p.keys.as<uint32_t>(), c, p.bounds.as<int>(),
-                                                      p.nchild.as<int>());
+        k_level_split<<<grid(ub * 27, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
+                                                       lev, p.keys.as<uint32_t>(), c,
+                                                       p.bounds.as<int>(), p.nchild.as<int>());
         HPM_LAUNCH_CHECK();
         exclusive_scan_i32_dn(p.nchild.as<int>(), p.childoff.as<int>(), int(ub),
                               lev + kLevCnt + l, lev + kLevCnt + l + 1, p.scan_tmp, s);
@@ -614,11 +620,6 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
       k_level_emit<<<grid(ub, 128), 128, 0, s>>>(l, int(p.cap_cells), lev, p.bounds.as<int>(),
                                                  p.childoff.as<int>(), c);
       HPM_LAUNCH_CHECK();
-      if (l < D) {
-        const int64_t ub1 = std::min<int64_t>({int64_t(1) << (3 * l + 3), int64_t(n), p.cap_cells});
-        k_level_nbr<<<grid(ub1 * 27, 256), 256, 0, s>>>(l + 1, lev, c);
-        HPM_LAUNCH_CHECK();
-      }
     }
   };
   const int* hl = p.hbox + Plan::kBoxLev;
