@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--sweep-steps", type=int, default=3,
+                    help="timed solves per point of the gridlet-order accuracy sweep")
     ap.add_argument("--profile", action="store_true",
                     help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
     ap.add_argument("--m2l", choices=("grid", "cells"), default="grid",
@@ -286,6 +288,23 @@ def main():
                 "ms_per_step": round(re_["ms_per_step"], 4), "m2l_ms": round(stage(re_, "m2l"), 4),
                 "leaf_ms": round(stage(re_, "leaf"), 4), "force_err_rms": ferr(oe)[0]}
 
+    # accuracy sweep over the gridlet order (the paper's accuracy-versus-cost comparison, Sec. 3.2):
+    # force error against the direct sum and time per solve, both precisions on the padded grid,
+    # and the extended gridlet on the cell route (FP32)
+    sweep = {}
+    for g in (2, 3, 4, 6):
+        point = {}
+        for pr in ("f32", "f64"):
+            rs, os_, _ = run_path(hpm, torch, parts, pr, g, args.sweep_steps, 1)
+            point[pr] = {"ms_per_step": round(rs["ms_per_step"], 4), "force_err_rms": ferr(os_)[0]}
+        rs, os_, _ = run_path(hpm, torch, parts, "f32", g, args.sweep_steps, 1, m2l="cells",
+                              extended=True)
+        point["f32_cells_extended"] = {"ms_per_step": round(rs["ms_per_step"], 4),
+                                       "force_err_rms": ferr(os_)[0]}
+        sweep[f"ng{g}"] = point
+    meets = [g for g in (2, 3, 4, 6) if sweep[f"ng{g}"]["f32"]["force_err_rms"] < 1e-4]
+    sweep["smallest_ng_at_1e-4"] = meets[0] if meets else None
+
     # latency of the small uniform problem (4096 particles, uniform depth 3, N_g = 4, FP64)
     from synth import uniform_cube
     pu = uniform_cube(4096, 1000)
@@ -333,6 +352,7 @@ def main():
         "kernels": {"yukawa_f32": yukawa},
         "other_orders": {"ng4": ng4},
         "m2l_routes": routes,
+        "accuracy_sweep": sweep,
         "small_solve": small,
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
