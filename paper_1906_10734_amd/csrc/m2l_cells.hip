@@ -73,7 +73,6 @@ struct CellArgs {
   int nsources;      // cells of levels >= 2, then the virtual cubes (row nsources of the
                      // source spectra is zero)
   int first_parent;  // first row of the block table (cells of level 1)
-  int nparents;
   int nlevels;
   const int* level_off;
   const int* child8;
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
     for (int c = 0; c < 8; ++c) acc[c] = {T(0), T(0)};
     // two planes at a time in FP32, so that one plane's loads overlap the other's arithmetic
     // (FP64 has no registers to spare for it)
-#pragma unroll(sizeof(T) == 4 ? 2 : 1)
+#pragma unroll sizeof(T) == 4 ? 2 : 1
     for (int bz = 0; bz < 6; ++bz) {
       cplx<T> sp[36];
 #pragma unroll
@@ -326,7 +325,6 @@ static void cells_t(Plan& p, hipStream_t s) {
   if (ntargets <= 0) return;
   a.nsources = ntargets + int(p.nvirt);
   a.first_parent = p.blocks_first;
-  a.nparents = p.level_off[p.nlevels - 1] - p.blocks_first;
   a.nlevels = p.nlevels;
   a.level_off = p.dlevel.as<int>();
   a.child8 = p.child8.as<int>();

@@ -90,8 +90,8 @@ static std::vector<double> invert(std::vector<double> a, int n) {
 
 // Transforms of the cyclic Green arrays of the cell-by-cell route, all levels and offsets.
 static std::vector<double> cell_green(const Plan& p, int nlev) {
-  const int ng = p.ng, ext = p.ext, C = 2 * ng + 2 * ext, HC = C / 2 + 1, K = C * C * HC;
-  const int Kp = int(cell_modes(ng, ext));
+  const int ng = p.ng, ext = p.ext, C = 2 * ng + 2 * ext, HC = C / 2 + 1;
+  const int Kp = int(cell_modes(ng, ext));  // C^2 HC modes, padded
   std::vector<double> out(size_t(std::max(nlev, 1)) * 343 * Kp * 2, 0.0);
   std::vector<double> cs(size_t(C) * C), sn(size_t(C) * C);
   for (int k = 0; k < C; ++k)
