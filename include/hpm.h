@@ -161,7 +161,9 @@ hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x,
  *   L2P + P2P  Eq. (7) and its gradient at each particle plus the near-zone direct sum over
  *         the 27 neighbouring cubes (Sec. 1), combined with compensated addition.
  * Outputs phi, ax, ay, az (device, n elements, input order, caller-allocated) are overwritten.
- * Enqueued on "stream" without host synchronisation and without allocation.
+ * Enqueued on "stream" without host synchronisation and without allocation. For n >= 2^16 the
+ * near-zone sums run on a stream the plan owns, forked from "stream" before the source-to-target
+ * step and joined back before the leaf pass, so the call is ordered on "stream" as a whole.
  * Errors: HPM_ERR_INVALID_ARG (NULL pointer), HPM_ERR_DEVICE (launch failure).
  */
 hpm_status hpm_plan_execute(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,

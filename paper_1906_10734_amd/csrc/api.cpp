@@ -123,6 +123,9 @@ static void create_plan(const hpm_problem* pr, int64_t n, const void* x, const v
   HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
                         hipHostMallocMapped | hipHostMallocCoherent));
   HPM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&p.dbox), p.hbox, 0));
+  HPM_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+  HPM_HIP(hipEventCreateWithFlags(&p.fork_ev, hipEventDisableTiming));
+  HPM_HIP(hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming));
   const int depth = pr->uniform_depth > 0 ? pr->uniform_depth : pr->max_depth;
   build_tables(p, depth + 1, s);
   size_t slot_bytes = 0;
@@ -144,6 +147,9 @@ static void drain_one(Plan& p) {
   p.ring_count -= 1;
 }
 
+// particles from which the near zone of an execution runs beside the source-to-target step
+constexpr int64_t kForkMinParticles = int64_t(1) << 16;
+
 static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az,
                          hipStream_t s) {
   hipEvent_t* ev = nullptr;
@@ -159,16 +165,34 @@ static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, 
   if (ev) HPM_HIP(hipEventRecord(ev[1], s));
   for (int l = p.nlevels - 2; l >= 2; --l) launch_m2m(p, l, s);
   if (ev) HPM_HIP(hipEventRecord(ev[2], s));
+  // the near zone needs only the tree and the sorted masses: for large problems it runs on the
+  // side stream beside the source-to-target step (which leaves ALU and memory slots idle) and
+  // the leaf pass waits for it; small ones keep it in line, where the fork costs more than it hides
+  const bool fork = p.n >= kForkMinParticles;
+  if (fork) {
+    HPM_HIP(hipEventRecord(p.fork_ev, s));
+    HPM_HIP(hipStreamWaitEvent(p.side, p.fork_ev, 0));
+    launch_p2p(p, p.side);
+    HPM_HIP(hipEventRecord(p.join_ev, p.side));
+  }
   if (p.prob.m2l_mode == HPM_M2L_CELLS) launch_m2l_cells(p, s);
   else launch_m2l(p, s);
   if (ev) HPM_HIP(hipEventRecord(ev[3], s));
   for (int l = 2; l < p.nlevels; ++l) launch_l2l(p, l, s);  // level 2: re-centring only
   if (ev) HPM_HIP(hipEventRecord(ev[4], s));
+  if (fork) HPM_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
+  else launch_p2p(p, s);
   launch_leaf(p, phi, ax, ay, az, s);
   if (ev) HPM_HIP(hipEventRecord(ev[5], s));
 }
 
 Plan::~Plan() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
+  if (join_ev) (void)hipEventDestroy(join_ev);
   if (hbox) (void)hipHostFree(hbox);
   if (events_created) {
     for (auto& set : ev)

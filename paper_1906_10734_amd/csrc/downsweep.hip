@@ -588,8 +588,8 @@ static void l2l_t(Plan& p, int level, hipStream_t s) {
   HPM_LAUNCH_CHECK();
 }
 
-template <typename T, int NG, int EXT>
-static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
+template <typename T>
+static void p2p_t(Plan& p, hipStream_t s) {
   if (p.nleaves <= 0 || p.n_items <= 0) return;
   P2PArgs<T> b;
   b.items = p.items.as<int4>();
@@ -608,6 +608,11 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   if (p.prob.kernel == HPM_KERNEL_YUKAWA) k_p2p<T, HPM_KERNEL_YUKAWA><<<int(p.n_items), 64, 0, s>>>(b);
   else k_p2p<T, HPM_KERNEL_NEWTON><<<int(p.n_items), 64, 0, s>>>(b);
   HPM_LAUNCH_CHECK();
+}
+
+template <typename T, int NG, int EXT>
+static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
+  if (p.nleaves <= 0 || p.n_items <= 0) return;
   LeafArgs<T> a;
   a.n = int(p.n);
   a.leaves = p.leaves.as<int>();
@@ -678,6 +683,11 @@ static void leaf_dispatch(Plan& p, void* phi, void* ax, void* ay, void* az, hipS
     case 16: leaf_t<T, 8, 0>(p, phi, ax, ay, az, s); break;
     default: fail(HPM_ERR_UNSUPPORTED, "no leaf kernel for this gridlet");
   }
+}
+
+void launch_p2p(Plan& p, hipStream_t s) {
+  if (p.prec == HPM_F32) p2p_t<float>(p, s);
+  else p2p_t<double>(p, s);
 }
 
 void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s) {

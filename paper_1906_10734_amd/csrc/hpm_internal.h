@@ -160,6 +160,10 @@ struct Plan {
   static constexpr int kBoxLev = 24;        // words 24 .. 63: copy of the device level table
   int* hbox = nullptr;
   int* dbox = nullptr;
+  // a second stream (default priority) on which the near-zone sums run beside the far-field
+  // chain of an execution, with the events that fork it from and join it to the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
   // stage timing with HIP events (off unless enabled): a ring of pending executions
   static constexpr int kStages = 5;   // P2M, M2M, M2L, L2L, leaves
@@ -210,6 +214,8 @@ void launch_m2l_cells(Plan& p, hipStream_t s);
 // ---- downsweep.hip -------------------------------------------------------------------------------
 void build_near_lists(Plan& p, hipStream_t s);
 void launch_l2l(Plan& p, int level, hipStream_t s);
+// near-zone partial sums (independent of the far-field chain), then the per-leaf combination
+void launch_p2p(Plan& p, hipStream_t s);
 void launch_leaf(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t s);
 void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const void* z,
                        const void* m, int64_t nt, const int32_t* targets, double G, double eps,
