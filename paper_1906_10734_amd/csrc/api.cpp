@@ -84,8 +84,8 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   const size_t cells = size_t(p.ncells);
   p.gridlet.reserve((cells + size_t(p.nvirt)) * p.M * p.elem);
   p.local.reserve(cells * p.ML * p.elem);
-  const size_t rows = size_t(std::max<int64_t>({p.nleaves - p.nleaves_lt2, p.nvirt, 1}));
-  p.moments.reserve(rows * p.tab.kpad * p.elem);
+  build_p2m_rows(p, s);
+  p.moments.reserve(size_t(std::max<int64_t>(p.p2m_rows, 1)) * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
   p.m2l_mean.reserve(cells * sizeof(double));
   if (p.prob.m2l_mode == HPM_M2L_CELLS && p.nlevels > 2) {

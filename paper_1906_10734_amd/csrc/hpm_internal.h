@@ -132,6 +132,9 @@ struct Plan {
   DevBuf dlev;    // the tree build's level table (cell ranges per level, overflow flag)
   // gridlets
   DevBuf gridlet, local, moments;  // gridlet [cells + virtual][M], local [cells][ML]
+  // rows of the P2M fit: leaves of levels >= 2, then the virtual cubes (cell ids, levels)
+  DevBuf p2m_list, p2m_level;
+  int64_t p2m_rows = 0;
   DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
   DevBuf m2l_mean;          // [cells] double: mean of the source-to-target result, when split
   bool m2l_split = false;   // the source-to-target kernel writes (mean, zero-mean gridlet)
@@ -193,6 +196,7 @@ void build_virtual(Plan& p, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------
 void launch_gather_masses(Plan& p, const void* m, hipStream_t s);
+void build_p2m_rows(Plan& p, hipStream_t s);
 void launch_p2m(Plan& p, hipStream_t s);
 void launch_m2m(Plan& p, int level, hipStream_t s);
 

@@ -292,12 +292,39 @@ static void p2m_rows(Plan& p, const int* list, int first, int rows, const int* r
   HPM_LAUNCH_CHECK();
 }
 
-// leaves at levels >= 2, then the virtual cubes (the moments buffer is reused in stream order)
+// the leaves at levels >= 2 and the virtual cubes, in one pass over the combined row list
 template <typename T, int NG>
 static void p2m_t(Plan& p, hipStream_t s) {
-  p2m_rows<T, NG>(p, p.leaves.as<int>(), int(p.nleaves_lt2), int(p.nleaves - p.nleaves_lt2),
-                  nullptr, s);
-  p2m_rows<T, NG>(p, p.vlist.as<int>(), 0, int(p.nvirt), p.vlevel.as<int>(), s);
+  p2m_rows<T, NG>(p, p.p2m_list.as<int>(), 0, int(p.p2m_rows), p.p2m_level.as<int>(), s);
+}
+
+// rows of the fit: leaf r of levels >= 2 (list position first2 + r), then virtual cube v (cell
+// id ncells + v), each with its level
+__global__ void k_p2m_rows(int nl2, int first2, const int* leaves, int nvirt, int ncells,
+                           const int* vlevel, const int* level_off, int nlevels, int* list,
+                           int* level) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nl2) {
+    const int g = leaves[first2 + r];
+    list[r] = g;
+    level[r] = level_of(g, level_off, nlevels);
+  } else if (r < nl2 + nvirt) {
+    list[r] = ncells + (r - nl2);
+    level[r] = vlevel[r - nl2];
+  }
+}
+
+void build_p2m_rows(Plan& p, hipStream_t s) {
+  const int nl2 = int(p.nleaves - p.nleaves_lt2), nv = int(p.nvirt);
+  p.p2m_rows = nl2 + nv;
+  if (p.p2m_rows <= 0) return;
+  p.p2m_list.reserve(size_t(p.p2m_rows) * 4);
+  p.p2m_level.reserve(size_t(p.p2m_rows) * 4);
+  k_p2m_rows<<<nblk(p.p2m_rows, 256), 256, 0, s>>>(nl2, int(p.nleaves_lt2), p.leaves.as<int>(), nv,
+                                                   int(p.ncells), p.vlevel.as<int>(),
+                                                   p.dlevel.as<int>(), p.nlevels,
+                                                   p.p2m_list.as<int>(), p.p2m_level.as<int>());
+  HPM_LAUNCH_CHECK();
 }
 
 template <typename T, int NG>
