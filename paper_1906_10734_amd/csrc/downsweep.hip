@@ -197,6 +197,13 @@ __global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, co
 
 static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
 
+// leaf list index of every sorted particle (a leaf's particles are one contiguous range)
+__global__ void k_leaf_of(const int* leaves, const int* pb, const int* pe, int* leaf_of) {
+  const int li = blockIdx.x;
+  const int g = leaves[li];
+  for (int j = pb[g] + threadIdx.x; j < pe[g]; j += blockDim.x) leaf_of[j] = li;
+}
+
 void build_near_lists(Plan& p, hipStream_t s) {
   const int nl = int(p.nleaves);
   p.near_rb.reserve(size_t(nl) * 27 * 4);
@@ -205,6 +212,13 @@ void build_near_lists(Plan& p, hipStream_t s) {
   p.item_off.reserve(size_t(nl) * 4);
   p.pairs.reserve(16);
   HPM_HIP(hipMemsetAsync(p.pairs.p, 0, 8, s));
+  p.leaf_of.reserve(size_t(std::max<int64_t>(p.n, 1)) * 4);
+  HPM_HIP(hipMemsetAsync(p.leaf_of.p, 0xff, size_t(p.n) * 4, s));
+  if (nl > 0) {
+    k_leaf_of<<<nl, 64, 0, s>>>(p.leaves.as<int>(), p.cpb.as<int>(), p.cpe.as<int>(),
+                                p.leaf_of.as<int>());
+    HPM_LAUNCH_CHECK();
+  }
   NearArgs a;
   a.nleaves = nl;
   a.depth = p.depth;
@@ -428,6 +442,7 @@ struct LeafArgs {
   const int* pe;
   const int* item_off;
   const int* item_cnt;
+  const int* leaf_of;  // leaf list index of each sorted particle
   const int* perm;
   const T* xs;
   const T* ys;
@@ -443,40 +458,49 @@ struct LeafArgs {
   T gconst;
 };
 
-// The local potential of a leaf lives on NP = N_g + 2 EXT nodes per axis (EXT = 1: the extended
-// gridlet of Sec. 2.5).
+// One lane per sorted particle: workgroup b takes particles [64 b, 64 b + 64). They belong to a
+// few leaves (runs of consecutive particles), whose local potentials are staged in LDS kLeafRuns
+// at a time; a lane's near-zone partials are found from its place in its leaf. The local
+// potential lives on NP = N_g + 2 EXT nodes per axis (EXT = 1: the extended gridlet of Sec. 2.5).
+constexpr int kLeafRuns = 4;
+
 template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
   constexpr int NP = NG + 2 * EXT;
   constexpr int M = NP * NP * NP;
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ T s_phi[M];
+  __shared__ int s_run_leaf[64];
+  __shared__ T s_phi[kLeafRuns][M];
   const int lane = threadIdx.x;
   if (lane <= kMaxLevels) s_off[lane] = a.level_off[lane];
+  const int i = blockIdx.x * 64 + lane;
+  const int li = i < a.n ? a.leaf_of[i] : -1;  // -1: past the end (or in no leaf)
+  const bool valid = li >= 0;
+  const int prev = __shfl_up(li, 1, 64);
+  const bool start = valid && (lane == 0 || prev != li);
+  const uint64_t starts = __ballot(start);
+  const int run = __popcll(starts & ((2ull << lane) - 1ull)) - 1;  // run of this lane
+  const int nruns = __popcll(starts);
+  if (start) s_run_leaf[run] = li;
   __syncthreads();
-  const int li = blockIdx.x;
-  const int g = a.leaves[li];
-  const int l = level_of(g, s_off, a.nlevels);
-  const int pc = a.coord[g];
-  const int pb = a.pb[g], K = a.pe[g] - pb;
-  if (l >= 2)
-    for (int e = lane; e < M; e += 64) s_phi[e] = a.local[size_t(g) * M + e];
-  __syncthreads();
-  const T c_hi = (l >= 2) ? a.lofs[2 * g] : T(0), c_lo = (l >= 2) ? a.lofs[2 * g + 1] : T(0);
+
+  int g = 0, l = 0, pb = 0, K = 1, pc = 0;
+  if (valid) {
+    g = a.leaves[li];
+    l = level_of(g, s_off, a.nlevels);
+    pb = a.pb[g];
+    K = a.pe[g] - pb;
+    pc = a.coord[g];
+  }
   const double L = a.size / double(1 << l);
-  const T cxc = T(a.lo0 + (coord_x(pc) + 0.5) * L), cyc = T(a.lo1 + (coord_y(pc) + 0.5) * L),
-          czc = T(a.lo2 + (coord_z(pc) + 0.5) * L);
   const T invL = T(1.0 / L);
-  const int nt = (K + 63) / 64;
-  const int ns = a.item_cnt[li] / nt;
-  for (int tc = 0; tc < nt; ++tc) {
-    const int t = tc * 64 + lane;
-    if (t >= K) continue;
-    const int i = pb + t;
-    // near zone: partials of this target chunk, source chunks in order
-    T ph = T(0), phe = T(0), fx = T(0), fy = T(0), fz = T(0);
+  // near zone: partials of this particle's target chunk, source chunks in order
+  T ph = T(0), phe = T(0), fx = T(0), fy = T(0), fz = T(0);
+  if (valid) {
+    const int t = i - pb, nt = (K + 63) / 64, tc = t / 64;
+    const int ns = a.item_cnt[li] / nt;
     for (int sc = 0; sc < ns; ++sc) {
-      const T* q = a.partial + (size_t(a.item_off[li] + tc * ns + sc) * 64 + lane) * 5;
+      const T* q = a.partial + (size_t(a.item_off[li] + tc * ns + sc) * 64 + (t % 64)) * 5;
       T s, err;
       two_sum(ph, q[0], s, err);
       ph = s;
@@ -485,9 +509,21 @@ __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
       fy += q[3];
       fz += q[4];
     }
-    // far field from c + dPhi
-    T pfar = T(0), gx = T(0), gy = T(0), gz = T(0);
-    if (l >= 2) {
+  }
+  // far field from c + dPhi, the leaves' potentials staged kLeafRuns at a time
+  T pfar = T(0), gx = T(0), gy = T(0), gz = T(0);
+  for (int r0 = 0; r0 < nruns; r0 += kLeafRuns) {
+    __syncthreads();  // the previous round's gridlets are consumed
+    for (int q = 0; q < kLeafRuns && r0 + q < nruns; ++q) {
+      const int gq = a.leaves[s_run_leaf[r0 + q]];
+      if (level_of(gq, s_off, a.nlevels) >= 2)
+        for (int e = lane; e < M; e += 64) s_phi[q][e] = a.local[size_t(gq) * M + e];
+    }
+    __syncthreads();
+    if (valid && l >= 2 && run >= r0 && run < r0 + kLeafRuns) {
+      const T* phi = s_phi[run - r0];
+      const T cxc = T(a.lo0 + (coord_x(pc) + 0.5) * L), cyc = T(a.lo1 + (coord_y(pc) + 0.5) * L),
+              czc = T(a.lo2 + (coord_z(pc) + 0.5) * L);
       const T xi = a.xs[i], yi = a.ys[i], zi = a.zs[i];
       T lx[NP], dlx[NP], ly[NP], dly[NP], lz[NP], dlz[NP];
       lagrange_basis_d<NG, EXT>((xi - cxc) * invL, lx, dlx);
@@ -497,34 +533,36 @@ __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
       for (int k = 0; k < NP; ++k) {
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-          T r0 = T(0), r1 = T(0);
+          T r0v = T(0), r1v = T(0);
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
-            const T v = s_phi[(k * NP + j) * NP + q];
-            r0 += lx[q] * v;
-            r1 += dlx[q] * v;
+            const T v = phi[(k * NP + j) * NP + q];
+            r0v += lx[q] * v;
+            r1v += dlx[q] * v;
           }
-          pfar += lz[k] * ly[j] * r0;
-          gx += lz[k] * ly[j] * r1;
-          gy += lz[k] * dly[j] * r0;
-          gz += dlz[k] * ly[j] * r0;
+          pfar += lz[k] * ly[j] * r0v;
+          gx += lz[k] * ly[j] * r1v;
+          gy += lz[k] * dly[j] * r0v;
+          gz += dlz[k] * ly[j] * r0v;
         }
       }
     }
-    // phi = G*near + c + dPhi(x), added with compensation
-    const T gn = a.gconst;
-    const T n_hi = gn * ph;
-    const T n_lo = fma(gn, ph, -n_hi) + gn * phe;
-    T s1, e1, s2, e2;
-    two_sum(n_hi, c_hi, s1, e1);
-    two_sum(s1, pfar, s2, e2);
-    const int o = a.perm[i];
-    if (o < 0 || o >= a.n) continue;
-    a.phi[o] = s2 + (e2 + (e1 + (n_lo + c_lo)));
-    a.ax[o] = gn * fx - gx * invL;
-    a.ay[o] = gn * fy - gy * invL;
-    a.az[o] = gn * fz - gz * invL;
   }
+  if (!valid) return;
+  // phi = G*near + c + dPhi(x), added with compensation
+  const T c_hi = (l >= 2) ? a.lofs[2 * g] : T(0), c_lo = (l >= 2) ? a.lofs[2 * g + 1] : T(0);
+  const T gn = a.gconst;
+  const T n_hi = gn * ph;
+  const T n_lo = fma(gn, ph, -n_hi) + gn * phe;
+  T s1, e1, s2, e2;
+  two_sum(n_hi, c_hi, s1, e1);
+  two_sum(s1, pfar, s2, e2);
+  const int o = a.perm[i];
+  if (o < 0 || o >= a.n) return;
+  a.phi[o] = s2 + (e2 + (e1 + (n_lo + c_lo)));
+  a.ax[o] = gn * fx - gx * invL;
+  a.ay[o] = gn * fy - gy * invL;
+  a.az[o] = gn * fz - gz * invL;
 }
 
 template <typename T, int KER>
@@ -623,6 +661,7 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   a.pe = p.cpe.as<int>();
   a.item_off = p.item_off.as<int>();
   a.item_cnt = p.item_cnt.as<int>();
+  a.leaf_of = p.leaf_of.as<int>();
   a.perm = p.perm.as<int>();
   a.xs = p.xs.as<T>();
   a.ys = p.ys.as<T>();
@@ -639,7 +678,7 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   a.lo2 = p.prob.box_lo[2];
   a.size = p.prob.box_size;
   a.gconst = T(p.prob.gconst);
-  k_leaf<T, NG, EXT><<<int(p.nleaves), 64, 0, s>>>(a);
+  k_leaf<T, NG, EXT><<<nblk(p.n, 64), 64, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 

@@ -140,6 +140,7 @@ struct Plan {
   bool m2l_split = false;   // the source-to-target kernel writes (mean, zero-mean gridlet)
   // near-zone lists and the P2P work items (see downsweep.hip)
   DevBuf near_rb, near_re, item_cnt, item_off, items, partial, pairs;
+  DevBuf leaf_of;  // [n] leaf list index of each sorted particle
   int64_t n_items = 0;
   int64_t p2p_pairs = 0;
   DevBuf m2l_work;
