@@ -438,10 +438,10 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
       __syncthreads();
     }
 
-    // The inverse y transform runs in FP32 (the N_g target values of each column kept) and the
-    // inverse x transform in double precision as direct sums against a double twiddle table:
-    // the last rounding then happens at the magnitude of the potential's variation across the
-    // target, not at that of the interaction zone's large smooth potential.
+    // The inverse y transform runs in the plan's precision (the N_g target values of each column
+    // kept) and the inverse x transform in double precision as direct sums against a double
+    // twiddle table: the last rounding then happens at the magnitude of the potential's variation
+    // across the target, not at that of the interaction zone's large smooth potential.
     static_assert(ZB >= NG, "the slab buffer holds the N_g accumulated planes");
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -502,12 +502,13 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   }
 }
 
-// Which kernel serves (T, N_g): the whole stage in LDS when it fits; else the z-slab kernel in
-// FP32; else the full-grid kernel with a global stage slice per workgroup.
+// Which kernel serves (T, N_g): the whole stage in LDS when it fits; else the z-slab kernel (both
+// precisions; in FP64 one workgroup per CU fits); else the full-grid kernel with a global stage
+// slice per workgroup.
 template <typename T, int NG>
 constexpr int m2l_kind() {
   if constexpr (M2LShape<T, NG>::lds) return 0;
-  else if constexpr (sizeof(T) == 4 && SlabShape<T, NG>::fits) return 1;
+  else if constexpr (SlabShape<T, NG>::fits) return 1;
   else return 2;
 }
 
