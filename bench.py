@@ -10,7 +10,15 @@ this workload). Inputs are seeded and synthetic and resident in device memory be
 
   python bench.py [--steps K] [--warmup W] [--ng 6] [--n 262144] [--no-cpu-baseline]
 
-Prints ONE JSON line.
+Prints ONE JSON line. Two other workloads run on their own flag, each printing its own line:
+
+  --batch   512 independent FP32 solves (N log-uniform in [2^10, 2^18], half uniform cube and
+            half Plummer, N_g 4 or 6) through one hpm_server_run_batch call on a warm server;
+  --serve   a Poisson stream of solves (N log-uniform in [2^12, 2^20], uniform, Plummer or
+            clustered, force tolerance 1e-2 at N_g = 4 or 1e-4 at N_g = 6, extended gridlets on
+            the cell route) at 0.5, 0.7 and 0.9 of
+            the saturated rate: p50/p99 latency from submission to completion, particles/s, and
+            every result checked against its tolerance and against the same solve alone.
 """
 from __future__ import annotations
 
@@ -153,6 +161,170 @@ def cpu_baseline(parts, ng: int, budget_s: float):
                        f"leaves; scaled to the full solve ({est:.1f} s est.)")}
 
 
+def _device_set(torch, p, dt):
+    return tuple(torch.tensor(a, dtype=dt, device="cuda") for a in (p.x, p.y, p.z, p.m))
+
+
+def _force_err(torch, out, sub, ref):
+    a = torch.stack([o[sub].double() for o in out[1:]], 1)
+    e = (a - ref).norm(dim=1) / ref.norm(dim=1)
+    return float(e.pow(2).mean().sqrt())
+
+
+def batch_bench(args):
+    """512 independent FP32 solves in one hpm_server_run_batch call (the largest first, `slots`
+    in flight at once), on a server whose plans are already resident (one warm-up batch)."""
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import batch_requests, random_subset, request_particles
+    reqs = batch_requests(args.batch_count)
+    probs, sets = [], []
+    for r in reqs:
+        p = request_particles(r).astype(np.float32)
+        sets.append(_device_set(torch, p, torch.float32))
+        probs.append(hpm.Problem(ng=r["ng"], precision="f32", leaf_capacity=64, max_depth=10,
+                                 softening=1e-3))
+    torch.cuda.synchronize()
+    total = sum(r["n"] for r in reqs)
+    print(f"[batch] {len(reqs)} solves, {total} particles on the device", file=sys.stderr,
+          flush=True)
+    times = []
+    with hpm.Server(slots=args.slots) as sv:
+        st, outs = sv.run_batch(probs, sets)  # warm-up: plans created and grown
+        assert all(v == "HPM_OK" for v in st), st
+        for k in range(args.steps):
+            t0 = time.perf_counter()
+            st, outs = sv.run_batch(probs, sets, outs)
+            times.append(time.perf_counter() - t0)
+            assert all(v == "HPM_OK" for v in st), st
+            print(f"[batch] step {k}: {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        stats = sv.stats()
+    # every 16th solve: its result alone (bit for bit) and its force error on 64 particles
+    same, errs = 0, {4: [], 6: []}
+    checked = list(range(0, len(reqs), 16))
+    for i in checked:
+        solo = hpm.solve(probs[i], *sets[i])
+        same += int(all(torch.equal(a, b) for a, b in zip(solo, outs[i])))
+        x, y, z, m = sets[i]
+        sub = torch.tensor(random_subset(reqs[i]["n"], 64, 5000 + i), device="cuda")
+        _, rx, ry, rz = hpm.direct_sum(x, y, z, m, sub, 1.0, 1e-3)
+        errs[reqs[i]["ng"]].append(_force_err(torch, outs[i], sub, torch.stack([rx, ry, rz], 1)))
+    ms = float(np.median(times)) * 1e3
+    rec = {"mode": "batch", "metric": "particles/s of a batch of independent solves",
+           "value": round(total / (ms * 1e-3), 1), "unit": "particles/s",
+           "solves_per_s": round(len(reqs) / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3),
+           "ms_per_batch_all": [round(t * 1e3, 3) for t in times], "steps": args.steps,
+           "dtype": "f32", "data": "synthetic (seeded uniform cubes and Plummer spheres)",
+           "config": {"workload": f"{len(reqs)} solves, N log-uniform 2^10..2^18, half uniform "
+                                  "half Plummer, N_g 4 or 6, leaf<=64, eps=1e-3",
+                      "solves": len(reqs), "particles": total, "slots": args.slots,
+                      "ng4_solves": sum(r["ng"] == 4 for r in reqs)},
+           "checked": {"solves": len(checked), "identical_to_alone": same,
+                       "force_err_rms_median": {f"ng{g}": (float(np.median(v)) if v else None)
+                                                for g, v in errs.items()}},
+           "server": stats}
+    return rec
+
+
+def serve_bench(args):
+    """A Poisson stream of requests drawn from a pool of seeded particle sets, on a server with
+    `slots` workers and a memory budget; latency from submission to completion."""
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import random_subset, request_particles, serve_requests
+    pool = serve_requests(args.serve_pool)
+    sets, probs, refs, solos, subs = [], [], [], [], []
+    for i, r in enumerate(pool):
+        p = request_particles(r).astype(np.float32)
+        dev = _device_set(torch, p, torch.float32)
+        # the order for the request's tolerance: the cheapest form whose force error on the 2^18
+        # Plummer workload is at least 4x below it (the extended gridlet on the cell route: 2.7e-4
+        # at N_g = 4, 1.7e-5 at N_g = 6; the standard N_g = 6 gridlet, 8e-5, leaves no margin)
+        ng = 4 if r["tolerance"] >= 1e-2 else 6
+        prob = hpm.Problem(ng=ng, precision="f32", leaf_capacity=64, max_depth=10, softening=1e-3,
+                           m2l="cells", extended=True)
+        sub = torch.tensor(random_subset(r["n"], 256, 6000 + i), device="cuda")
+        _, rx, ry, rz = hpm.direct_sum(*dev, sub, 1.0, 1e-3)
+        solo = hpm.solve(prob, *dev)
+        sets.append(dev)
+        probs.append(prob)
+        subs.append(sub)
+        refs.append(torch.stack([rx, ry, rz], 1))
+        solos.append([o[sub].clone() for o in solo])
+        r["ng"] = ng
+        r["force_err_rms"] = _force_err(torch, solo, sub, refs[-1])
+    torch.cuda.synchronize()
+    print(f"[serve] pool of {len(pool)} request sets ready", file=sys.stderr, flush=True)
+    rng = np.random.Generator(np.random.PCG64(1004))
+
+    def run(stream_of, gaps):
+        """Submits pool entries `stream_of` at cumulative times `gaps` (s); returns results."""
+        tick, t0 = [], time.perf_counter()
+        due = np.cumsum(gaps)
+        for k, i in enumerate(stream_of):
+            while True:
+                left = due[k] - (time.perf_counter() - t0)
+                if left <= 0:
+                    break
+                time.sleep(left if left > 2e-3 else 0)
+            tick.append(sv.submit(probs[i], *sets[i], sync=False))
+        return [sv.wait(t) for t in tick]
+
+    def check(stream_of, res):
+        bad_tol, not_same = 0, 0
+        for i, (info, out) in zip(stream_of, res):
+            assert info["status"] == "HPM_OK", info
+            e = _force_err(torch, out, subs[i], refs[i])
+            bad_tol += int(e > pool[i]["tolerance"])
+            not_same += int(not all(torch.equal(o[subs[i]], s) for o, s in zip(out, solos[i])))
+        return bad_tol, not_same
+
+    out = {}
+    with hpm.Server(slots=args.slots, hbm_budget=args.serve_budget_gib << 30) as sv:
+        # warm-up, then the saturated rate: everything submitted at once
+        warm = rng.integers(0, len(pool), 2 * len(pool))
+        run(warm, np.zeros(len(warm)))
+        sat = rng.integers(0, len(pool), args.serve_requests // 2)
+        t0 = time.perf_counter()
+        res = run(sat, np.zeros(len(sat)))
+        t_sat = time.perf_counter() - t0
+        rate_sat = len(sat) / t_sat
+        print(f"[serve] saturated: {rate_sat:.1f} solves/s", file=sys.stderr, flush=True)
+        out["saturated"] = {"solves_per_s": round(rate_sat, 1),
+                            "particles_per_s": round(sum(pool[i]["n"] for i in sat) / t_sat, 1)}
+        for frac in (0.5, 0.7, 0.9):
+            lam = frac * rate_sat
+            picks = rng.integers(0, len(pool), args.serve_requests)
+            gaps = rng.exponential(1.0 / lam, args.serve_requests)
+            t0 = time.perf_counter()
+            res = run(picks, gaps)
+            wall = time.perf_counter() - t0
+            lat = np.array([i["latency_ms"] for i, _ in res])
+            bad_tol, not_same = check(picks, res)
+            out[f"load_{frac}"] = {
+                "arrival_rate_per_s": round(lam, 1), "requests": len(picks),
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                               "p99": round(float(np.percentile(lat, 99)), 3)},
+                "particles_per_s": round(sum(pool[i]["n"] for i in picks) / wall, 1),
+                "over_tolerance": bad_tol, "differs_from_alone": not_same}
+            print(f"[serve] load {frac}: p50 {np.percentile(lat, 50):.2f} ms, "
+                  f"p99 {np.percentile(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+            del res
+        stats = sv.stats()
+    rec = {"mode": "serve", "metric": "solve p50/p99 latency under a Poisson request stream",
+           "unit": "ms", "dtype": "f32", "data": "synthetic (seeded uniform, Plummer, clustered)",
+           "config": {"workload": "Poisson arrivals, N log-uniform 2^12..2^20, uniform/Plummer/"
+                                  "clustered, tolerance 1e-2 (N_g=4) or 1e-4 (N_g=6), extended "
+                                  "gridlets on the cell route, leaf<=64, eps=1e-3",
+                      "pool": len(pool), "slots": args.slots,
+                      "hbm_budget_gib": args.serve_budget_gib},
+           "results": out, "server": stats,
+           "pool_over_tolerance": [{k: r[k] for k in ("kind", "n", "ng", "tolerance",
+                                                      "force_err_rms")}
+                                   for r in pool if r["force_err_rms"] > r["tolerance"]]}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,10 +343,23 @@ def main():
                     help="source-to-target route of the --profile run")
     ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
                     help="precision of the --profile run")
+    ap.add_argument("--batch", action="store_true", help="the batched workload instead")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve", action="store_true", help="the served workload instead")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=8, help="server slots of --batch and --serve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.batch:
+        print(json.dumps(batch_bench(args)))
+        return
+    if args.serve:
+        print(json.dumps(serve_bench(args)))
+        return
 
     import torch
     from paper_1906_10734_amd import hpm
@@ -356,6 +541,14 @@ def main():
         "small_solve": small,
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
+    # the batched and served workloads, shortened (their own flags run them in full)
+    for key, fn, kw in (("batched", batch_bench, dict(steps=2)),
+                        ("served", serve_bench, dict(serve_requests=300))):
+        try:
+            sub_args = argparse.Namespace(**{**vars(args), **kw})
+            rec[key] = fn(sub_args)
+        except Exception as e:  # a failure here must not hide the main measurement
+            rec[key] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(parts, ng, args.cpu_seconds)
     else:

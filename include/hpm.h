@@ -25,7 +25,8 @@
  *     (a position on the upper face belongs to the last cell). On failure nothing is written to
  *     the caller's output arrays and *out pointers are set to NULL. hpm_last_error() returns a
  *     thread-local message about the last failure.
- *   - A plan or context is used by one host thread at a time.
+ *   - A plan is used by one host thread at a time; distinct plans may be used from distinct
+ *     threads. A server (below) may be called from several host threads.
  */
 #ifndef HPM_H
 #define HPM_H
@@ -37,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 4
+#define HPM_ABI_VERSION 5
 
 typedef enum {
   HPM_OK = 0,
@@ -46,7 +47,8 @@ typedef enum {
   HPM_ERR_NONFINITE = 3,
   HPM_ERR_NO_MEMORY = 4,
   HPM_ERR_DEVICE = 5,
-  HPM_ERR_UNSUPPORTED = 6
+  HPM_ERR_UNSUPPORTED = 6,
+  HPM_ERR_NOT_READY = 7
 } hpm_status;
 
 typedef enum { HPM_F64 = 0, HPM_F32 = 1 } hpm_precision;
@@ -127,6 +129,7 @@ typedef struct {
   int64_t n_targets;            /* cells at level >= 2: one source-to-target FFT each */
   int64_t cells_per_level[11];
   int64_t p2p_pairs;            /* near-zone pairs (including i == j slots), 0 until computed */
+  int64_t device_bytes;         /* device memory the plan holds (buffers and tables) */
 } hpm_plan_info;
 
 typedef struct hpm_plan_s hpm_plan;
@@ -240,6 +243,117 @@ hpm_status hpm_direct_sum(int32_t precision, int64_t n, const void* x, const voi
                           const void* z, const void* m, int64_t n_targets, const int32_t* targets,
                           double gconst, double softening, int32_t kernel, double screening,
                           double* phi, double* ax, double* ay, double* az, void* stream);
+
+/*
+ * Estimated device memory of a plan for n particles of this problem (the admission measure of
+ * the server below), made before the tree is known: 10 n / leaf_capacity + 64 cells (a uniform
+ * density whose leaves hold just over an eighth of the capacity gives about 9.2 n /
+ * leaf_capacity), or every cell of a uniform tree; one virtual cube per cell; four near-zone
+ * work items per cell; and the Green tables of every level. It is an estimate: trees with many
+ * particles at the deepest level, or leaves next to much denser regions, can need more. *bytes:
+ * host.
+ * Errors: HPM_ERR_INVALID_ARG, HPM_ERR_UNSUPPORTED (the checks of hpm_plan_create).
+ */
+hpm_status hpm_plan_bytes_estimate(const hpm_problem* problem, int64_t n, int64_t* bytes);
+
+/*
+ * Serving: many independent solves (each the whole method above on its own particle set) in
+ * flight on one device at once.
+ *
+ * A server owns "slots" host worker threads. Each has its own HIP stream (default priority)
+ * and runs one request at a time: tree, then one evaluation, then a synchronisation of its
+ * stream. Requests wait in one first-in-first-out queue. The request at the head is admitted
+ * when a worker is free and its memory fits: the estimate of hpm_plan_bytes_estimate beyond
+ * what the plan it will use already holds, plus the memory that all plans hold, must stay
+ * within hbm_budget. Plans stay resident between requests, keyed by the whole hpm_problem: a
+ * request with a problem seen before rebuilds an idle plan of that problem (no table build,
+ * no allocation once the plan is large enough). When the head does not fit, idle plans are
+ * released, least recently used first; if it still does not fit and nothing else runs, the
+ * request fails with HPM_ERR_NO_MEMORY. Once a plan has served a request, its measured size
+ * replaces the estimate in the total. Requests in flight on different workers overlap on the
+ * device; each result is the one the same problem and particles give alone (the kernels do
+ * not depend on what else runs).
+ *
+ * Buffers of a request (x, y, z, m, phi, ax, ay, az: device, n elements, the problem's
+ * dtype, input order) are owned by the caller. Their contents must be complete on the device
+ * when hpm_server_submit is called (synchronise the stream that wrote them), and they must
+ * stay allocated, and the inputs unchanged, until the request has finished. The outputs are
+ * valid once hpm_server_poll or hpm_server_wait reports the request.
+ */
+typedef struct {
+  int32_t abi;          /* HPM_ABI_VERSION */
+  int32_t slots;        /* 1..16 requests in flight at once */
+  int64_t hbm_budget;   /* bytes of device memory the server's plans may hold; 0: no limit */
+  int32_t reserved[4];  /* must be 0 */
+} hpm_server_config;
+
+/* What a finished request reports (host struct owned by the caller). */
+typedef struct {
+  int32_t status;       /* hpm_status of the solve */
+  int32_t slot;         /* worker that ran it, -1 if it never ran */
+  int64_t n;
+  double submit_ms;     /* host clock, milliseconds since the server was created */
+  double start_ms;      /* admitted: tree build starts */
+  double done_ms;       /* outputs complete on the device */
+  int64_t plan_bytes;   /* device memory of the plan that served it (after the solve) */
+  int64_t estimate_bytes;  /* hpm_plan_bytes_estimate of the request */
+} hpm_request_info;
+
+/* Counters of a server (host struct owned by the caller). */
+typedef struct {
+  int64_t submitted, completed, failed;
+  int32_t queued, running;
+  int64_t plans;            /* resident plans */
+  int64_t held_bytes;       /* device memory the plans hold, with reservations of running ones */
+  int64_t peak_held_bytes;
+  int64_t plans_created, plans_released;
+} hpm_server_stats;
+
+typedef struct hpm_server_s hpm_server;
+
+/*
+ * Starts a server on the calling thread's current device. cfg: host.
+ * Errors: HPM_ERR_INVALID_ARG (abi, slots, negative budget, reserved != 0), HPM_ERR_DEVICE.
+ */
+hpm_status hpm_server_create(const hpm_server_config* cfg, hpm_server** out);
+
+/*
+ * Queues one solve and returns its ticket (host) at once. The problem is checked here, as by
+ * hpm_plan_create (HPM_ERR_INVALID_ARG, HPM_ERR_UNSUPPORTED); the other errors of a solve
+ * (out of box, non-finite, memory, device) arrive with the request's result.
+ */
+hpm_status hpm_server_submit(hpm_server* server, const hpm_problem* problem, int64_t n,
+                             const void* x, const void* y, const void* z, const void* m,
+                             void* phi, void* ax, void* ay, void* az, uint64_t* ticket);
+
+/*
+ * Result of a ticket. poll returns HPM_ERR_NOT_READY while the request is queued or running;
+ * wait blocks until it has finished. Once finished, either returns the request's own status and
+ * fills *info (host, may be NULL); that releases the ticket, and a later call on it returns
+ * HPM_ERR_INVALID_ARG, as does an unknown ticket.
+ */
+hpm_status hpm_server_poll(hpm_server* server, uint64_t ticket, hpm_request_info* info);
+hpm_status hpm_server_wait(hpm_server* server, uint64_t ticket, hpm_request_info* info);
+
+/*
+ * A batch of independent solves: submits count requests (host arrays of problems, sizes and
+ * device pointers, one entry per solve), the largest first, and waits for all of them.
+ * status (host, count entries, may be NULL) receives each solve's status. Returns HPM_OK when
+ * every solve succeeded, else the status of the first failed solve in index order.
+ */
+hpm_status hpm_server_run_batch(hpm_server* server, int32_t count, const hpm_problem* problems,
+                                const int64_t* n, const void* const* x, const void* const* y,
+                                const void* const* z, const void* const* m, void* const* phi,
+                                void* const* ax, void* const* ay, void* const* az,
+                                int32_t* status);
+
+hpm_status hpm_server_stats_get(hpm_server* server, hpm_server_stats* stats);
+
+/*
+ * Finishes every queued and running request, then stops the workers and releases the plans
+ * (NULL is ignored). Tickets not yet reported are released with it.
+ */
+void hpm_server_destroy(hpm_server* server);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhpm.so")
-SOURCES = ["api.cpp", "tables.cpp", "tree.hip", "upsweep.hip", "m2l.hip", "m2l_cells.hip", "downsweep.hip"]
+SOURCES = ["api.cpp", "server.cpp", "tables.cpp", "tree.hip", "upsweep.hip", "m2l.hip",
+           "m2l_cells.hip", "downsweep.hip"]
 ARCH = os.environ.get("HPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -44,7 +45,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,16 +1,13 @@
 // C ABI of the HPM library: argument checks, plan lifetime, the order of the method's steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "hpm_internal.h"
-
-struct hpm_plan_s {
-  hpm::Plan p;
-};
 
 namespace hpm {
 
@@ -26,7 +23,7 @@ static void check_kernel(int32_t kernel, double screening) {
     fail(HPM_ERR_INVALID_ARG, "the Yukawa kernel needs screening > 0");
 }
 
-static void check_problem(const hpm_problem* pr) {
+void check_problem(const hpm_problem* pr) {
   if (!pr) fail(HPM_ERR_INVALID_ARG, "problem is NULL");
   if (pr->abi != HPM_ABI_VERSION) fail(HPM_ERR_INVALID_ARG, "problem.abi != HPM_ABI_VERSION");
   if (pr->precision != HPM_F32 && pr->precision != HPM_F64)
@@ -57,25 +54,7 @@ static void check_problem(const hpm_problem* pr) {
   }
 }
 
-template <typename F>
-static hpm_status guarded(F&& f) {
-  try {
-    f();
-    return HPM_OK;
-  } catch (const HpmError& e) {
-    set_last_error(e.msg);
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return HPM_ERR_NO_MEMORY;
-  } catch (...) {
-    set_last_error("unexpected exception");
-    return HPM_ERR_DEVICE;
-  }
-}
-
-static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z,
-                         hipStream_t s) {
+void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z, hipStream_t s) {
   p.valid = false;
   if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
   p.n = n;
@@ -109,9 +88,8 @@ static void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const
   p.valid = true;
 }
 
-static void create_plan(const hpm_problem* pr, int64_t n, const void* x, const void* y,
-                        const void* z, hipStream_t s, hpm_plan_s* pl) {
-  Plan& p = pl->p;
+void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const void* y,
+                 const void* z, hipStream_t s) {
   p.prob = *pr;
   p.prec = pr->precision;
   p.ng = pr->ng;
@@ -150,8 +128,8 @@ static void drain_one(Plan& p) {
 // particles from which the near zone of an execution runs beside the source-to-target step
 constexpr int64_t kForkMinParticles = int64_t(1) << 16;
 
-static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az,
-                         hipStream_t s) {
+void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az,
+                  hipStream_t s) {
   hipEvent_t* ev = nullptr;
   if (p.timing) {
     if (p.ring_count == Plan::kRing) drain_one(p);
@@ -186,6 +164,53 @@ static void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, 
   if (ev) HPM_HIP(hipEventRecord(ev[5], s));
 }
 
+size_t Plan::device_bytes() const {
+  const DevBuf* bufs[] = {
+      &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
+      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vids, &vtmp, &blocks, &dlevel, &dlev, &gridlet,
+      &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
+      &item_off, &items, &partial, &pairs, &leaf_of, &m2l_work, &cell_src, &cell_tgt, &cell_plist,
+      &cell_pflag, &cell_ppos, &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
+      &tmp_keys, &tmp_vals, &hist, &scan_tmp, &bounds, &nchild, &childoff};
+  size_t total = 0;
+  for (const DevBuf* b : bufs) total += b->bytes;
+  return total;
+}
+
+size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
+  const size_t s = pr.precision == HPM_F32 ? 4 : 8;
+  const size_t ng = size_t(pr.ng), nl = ng + 2 * size_t(pr.extended != 0);
+  const size_t M = ng * ng * ng, ML = nl * nl * nl, kpad = (M + 3) / 4 * 4;
+  const int depth = pr.uniform_depth > 0 ? pr.uniform_depth : pr.max_depth;
+  int64_t cells = 0;
+  if (pr.uniform_depth > 0) {
+    int64_t lvl = 1;
+    for (int l = 0; l <= pr.uniform_depth; ++l, lvl *= 8) cells += std::min<int64_t>(lvl, n);
+  } else {
+    // a tree whose leaves hold just over an eighth of the capacity has about 9.2 n / capacity
+    // cells, the most a uniform particle density gives
+    cells = std::max<int64_t>(1024, 10 * n / std::max(1, pr.leaf_capacity) + 64);
+  }
+  const size_t c = size_t(cells), np = size_t(n);
+  size_t b = np * (5 * 4 + 4 * s);          // keys, perm, sort scratch, leaf map; sorted x, y, z, m
+  b += c * (6 * 4 + 8 * 4 + 27 * 4);        // cell arrays (key, coords, range, parent, flags,
+                                            // children, neighbours)
+  b += c * (9 * 4 + 3 * 4 + 216 * 4 / 8);   // level scratch, leaf list, block tables of parents
+  b += c * (2 * M * s + ML * s + 2 * kpad * s + 2 * s + 8);  // gridlets of cells and virtual
+                                                              // cubes, locals, fit rows
+  b += c * (27 * 8 + 8 + 4 * (16 + 64 * 5 * s));  // near-zone ranges and work items
+  const size_t H = 4 * ng + 1, levels = size_t(std::max(depth - 1, 1));
+  b += levels * (H * H * H + 4 * ng * H * H) * s;  // Green transforms
+  if (pr.m2l_mode == HPM_M2L_CELLS) {
+    const size_t spec = cell_modes(int(ng), pr.extended) * 2 * s;
+    b += (2 * c + 1) * spec + levels * 343 * spec + 3 * 4 * c;
+  }
+  size_t slot_bytes = 0;
+  const int slots = m2l_workspace_slots(pr.precision, pr.ng, &slot_bytes);
+  b += slot_bytes * size_t(slots);
+  return b + (size_t(1) << 20);
+}
+
 Plan::~Plan() {
   if (side) {
     (void)hipStreamSynchronize(side);
@@ -218,6 +243,7 @@ const char* hpm_status_string(hpm_status s) {
     case HPM_ERR_NO_MEMORY: return "HPM_ERR_NO_MEMORY";
     case HPM_ERR_DEVICE: return "HPM_ERR_DEVICE";
     case HPM_ERR_UNSUPPORTED: return "HPM_ERR_UNSUPPORTED";
+    case HPM_ERR_NOT_READY: return "HPM_ERR_NOT_READY";
   }
   return "HPM_ERR_UNKNOWN";
 }
@@ -236,7 +262,7 @@ hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x,
     if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
     if (!x || !y || !z) fail(HPM_ERR_INVALID_ARG, "position pointer is NULL");
     pl = new hpm_plan_s();
-    create_plan(problem, n, x, y, z, (hipStream_t)stream, pl);
+    create_plan(pl->p, problem, n, x, y, z, (hipStream_t)stream);
   });
   if (st != HPM_OK) {
     delete pl;
@@ -332,6 +358,7 @@ hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info) {
       HPM_HIP(hipMemcpy(&pairs, p.pairs.p, sizeof(pairs), hipMemcpyDeviceToHost));
     }
     info->p2p_pairs = pairs;
+    info->device_bytes = int64_t(p.device_bytes());
   });
 }
 
@@ -419,6 +446,15 @@ hpm_status hpm_plan_copy_local_offsets(const hpm_plan* plan, int32_t level, doub
         host[i] = ci[0] + ci[1];
       }
     }
+  });
+}
+
+hpm_status hpm_plan_bytes_estimate(const hpm_problem* problem, int64_t n, int64_t* bytes) {
+  return guarded([&] {
+    if (!bytes) fail(HPM_ERR_INVALID_ARG, "bytes is NULL");
+    check_problem(problem);
+    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    *bytes = int64_t(plan_bytes_estimate(*problem, n));
   });
 }
 

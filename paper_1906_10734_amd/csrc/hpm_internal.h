@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
@@ -21,6 +22,25 @@ struct HpmError {
 
 void set_last_error(const std::string& msg);
 [[noreturn]] void fail(hpm_status s, const std::string& msg);
+
+// Runs f and turns a thrown HpmError (or a host allocation failure) into its status; the message
+// goes to the calling thread's last error.
+template <typename F>
+hpm_status guarded(F&& f) {
+  try {
+    f();
+    return HPM_OK;
+  } catch (const HpmError& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return HPM_ERR_NO_MEMORY;
+  } catch (...) {
+    set_last_error("unexpected exception");
+    return HPM_ERR_DEVICE;
+  }
+}
 
 #define HPM_HIP(call)                                                                       \
   do {                                                                                      \
@@ -181,7 +201,23 @@ struct Plan {
   int64_t n_exec = 0, n_build = 0;
   ~Plan();
 
+  // device memory the plan holds (every buffer above and its tables)
+  size_t device_bytes() const;
 };
+
+// ---- api.cpp ------------------------------------------------------------------------------------
+// host checks of a problem description (throws HpmError)
+void check_problem(const hpm_problem* pr);
+// tables, streams and the first tree of a plan; the tree for new positions; one evaluation.
+// Plans are independent of each other: distinct plans may be used from distinct host threads.
+void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const void* y,
+                 const void* z, hipStream_t s);
+void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z, hipStream_t s);
+void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az, hipStream_t s);
+// an estimate of the device memory of a plan for n particles, made before its tree is known
+// (10 n / leaf capacity + 64 cells, or every cell of a uniform tree; one virtual cube per cell;
+// the near-zone work of four source chunks per cell)
+size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n);
 
 // ---- tables.cpp -------------------------------------------------------------------------------
 // tables for levels 2..max_levels-1 (the Green transforms depend on the level, not on the tree)
@@ -228,3 +264,7 @@ void launch_direct_sum(int prec, int64_t n, const void* x, const void* y, const 
                        hipStream_t s);
 
 }  // namespace hpm
+
+struct hpm_plan_s {
+  hpm::Plan p;
+};

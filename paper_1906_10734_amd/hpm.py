@@ -16,12 +16,14 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpm.so")
 
-HPM_ABI_VERSION = 4
+HPM_ABI_VERSION = 5
 HPM_F64, HPM_F32 = 0, 1
 HPM_KERNELS = {"newton": 0, "yukawa": 1}
 HPM_M2L_MODES = {"grid": 0, "cells": 1}
 STATUS = {0: "HPM_OK", 1: "HPM_ERR_INVALID_ARG", 2: "HPM_ERR_OUT_OF_BOX", 3: "HPM_ERR_NONFINITE",
-          4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED"}
+          4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED",
+          7: "HPM_ERR_NOT_READY"}
+HPM_ERR_NOT_READY = 7
 
 # Entry points declared in include/hpm.h: name -> (restype, argtypes)
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -41,7 +43,28 @@ class HpmPlanInfo(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("ng", ctypes.c_int32),
                 ("n_particles", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("n_leaves", ctypes.c_int64), ("n_targets", ctypes.c_int64),
-                ("cells_per_level", ctypes.c_int64 * 11), ("p2p_pairs", ctypes.c_int64)]
+                ("cells_per_level", ctypes.c_int64 * 11), ("p2p_pairs", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class HpmServerConfig(ctypes.Structure):
+    _fields_ = [("abi", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class HpmRequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double), ("plan_bytes", ctypes.c_int64),
+                ("estimate_bytes", ctypes.c_int64)]
+
+
+class HpmServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("plans", ctypes.c_int64),
+                ("held_bytes", ctypes.c_int64), ("peak_held_bytes", ctypes.c_int64),
+                ("plans_created", ctypes.c_int64), ("plans_released", ctypes.c_int64)]
 
 
 SIGNATURES = {
@@ -65,6 +88,18 @@ SIGNATURES = {
     "hpm_plan_copy_local_offsets": (_i32, [_vp, _i32, _vp]),
     "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _i32, _d, _vp,
                               _vp, _vp, _vp, _vp]),
+    "hpm_plan_bytes_estimate": (_i32, [ctypes.POINTER(HpmProblem), _i64,
+                                       ctypes.POINTER(_i64)]),
+    "hpm_server_create": (_i32, [ctypes.POINTER(HpmServerConfig), ctypes.POINTER(_vp)]),
+    "hpm_server_submit": (_i32, [_vp, ctypes.POINTER(HpmProblem), _i64, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "hpm_server_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(HpmRequestInfo)]),
+    "hpm_server_wait": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(HpmRequestInfo)]),
+    "hpm_server_run_batch": (_i32, [_vp, _i32, ctypes.POINTER(HpmProblem),
+                                    ctypes.POINTER(_i64)] + [ctypes.POINTER(_vp)] * 8 +
+                             [ctypes.POINTER(_i32)]),
+    "hpm_server_stats_get": (_i32, [_vp, ctypes.POINTER(HpmServerStats)]),
+    "hpm_server_destroy": (None, [_vp]),
 }
 
 
@@ -206,7 +241,8 @@ class Plan:
         _check(_lib.hpm_plan_info_get(self._h, ctypes.byref(i)), "hpm_plan_info_get")
         return dict(n_levels=i.n_levels, ng=i.ng, n_particles=i.n_particles, n_cells=i.n_cells,
                     n_leaves=i.n_leaves, n_targets=i.n_targets,
-                    cells_per_level=list(i.cells_per_level)[:i.n_levels])
+                    cells_per_level=list(i.cells_per_level)[:i.n_levels],
+                    device_bytes=i.device_bytes)
 
     def perm(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.int32)
@@ -279,3 +315,114 @@ def direct_sum(x, y, z, m, targets, gconst: float = 1.0, softening: float = 0.0,
                                *(o.data_ptr() for o in out),
                                _stream(stream)), "hpm_direct_sum")
     return tuple(out)
+
+
+def plan_bytes_estimate(problem: Problem, n: int) -> int:
+    """hpm_plan_bytes_estimate: the server's admission measure of one request."""
+    out = _i64()
+    c = problem.c()
+    _check(_lib.hpm_plan_bytes_estimate(ctypes.byref(c), int(n), ctypes.byref(out)),
+           "hpm_plan_bytes_estimate")
+    return out.value
+
+
+def _request_dict(i: HpmRequestInfo) -> dict:
+    return dict(status=STATUS.get(i.status, str(i.status)), slot=i.slot, n=i.n,
+                submit_ms=i.submit_ms, start_ms=i.start_ms, done_ms=i.done_ms,
+                latency_ms=i.done_ms - i.submit_ms, plan_bytes=i.plan_bytes,
+                estimate_bytes=i.estimate_bytes)
+
+
+class Server:
+    """hpm_server_*: independent solves in flight on the device at once, admitted by memory.
+
+    submit() queues one solve and returns a ticket; wait()/poll() return (info, (phi, ax, ay, az)).
+    The binding keeps the request's tensors alive until it has been reported. Inputs must be
+    complete on the device when submitted: submit() synchronises the current stream first.
+    """
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 0):
+        cfg = HpmServerConfig()
+        cfg.abi = HPM_ABI_VERSION
+        cfg.slots = slots
+        cfg.hbm_budget = int(hbm_budget)
+        h = _vp()
+        _check(_lib.hpm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "hpm_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, problem: Problem, x, y, z, m, out=None, sync: bool = True) -> int:
+        n, dt = int(x.numel()), problem.dtype
+        if out is None:
+            out = tuple(torch.empty(n, dtype=dt, device=x.device) for _ in range(4))
+        ptrs = [_dev(t, dt, n, nm) for t, nm in zip((x, y, z, m) + tuple(out),
+                                                   ("x", "y", "z", "m", "phi", "ax", "ay", "az"))]
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        c = problem.c()
+        t = ctypes.c_uint64()
+        _check(_lib.hpm_server_submit(self._h, ctypes.byref(c), n, *ptrs, ctypes.byref(t)),
+               "hpm_server_submit")
+        self._live[t.value] = (x, y, z, m, tuple(out))
+        return t.value
+
+    def _call(self, fn, ticket: int):
+        i = HpmRequestInfo()
+        i.status = -1  # filled by the library only when it reports the request
+        st = fn(self._h, ticket, ctypes.byref(i))
+        if st == HPM_ERR_NOT_READY:
+            return None
+        if i.status == -1:
+            raise HpmError(st, fn.__name__)
+        keep = self._live.pop(ticket, None)
+        return _request_dict(i), (keep[4] if keep else None)
+
+    def wait(self, ticket: int):
+        """Blocks until the request has finished: (info, (phi, ax, ay, az)); info["status"] is
+        the solve's status."""
+        return self._call(_lib.hpm_server_wait, ticket)
+
+    def poll(self, ticket: int):
+        """None while the request is queued or running, else as wait()."""
+        return self._call(_lib.hpm_server_poll, ticket)
+
+    def run_batch(self, problems, particles, outs=None):
+        """hpm_server_run_batch over lists of problems and (x, y, z, m) tuples; returns
+        (statuses, outputs)."""
+        k = len(problems)
+        torch.cuda.current_stream().synchronize()
+        if outs is None:
+            outs = [tuple(torch.empty(int(p[0].numel()), dtype=pr.dtype, device=p[0].device)
+                          for _ in range(4)) for pr, p in zip(problems, particles)]
+        cprobs = (HpmProblem * k)(*[pr.c() for pr in problems])
+        ns = (_i64 * k)(*[int(p[0].numel()) for p in particles])
+        cols = []
+        for j in range(4):
+            cols.append((_vp * k)(*[_dev(p[j], pr.dtype, int(p[0].numel()), "xyzm"[j])
+                                    for pr, p in zip(problems, particles)]))
+        for j in range(4):
+            cols.append((_vp * k)(*[_dev(o[j], pr.dtype, int(p[0].numel()), "output")
+                                    for pr, p, o in zip(problems, particles, outs)]))
+        st = (_i32 * k)()
+        _lib.hpm_server_run_batch(self._h, k, cprobs, ns, *cols, st)
+        return [STATUS.get(v, str(v)) for v in st], outs
+
+    def stats(self) -> dict:
+        s = HpmServerStats()
+        _check(_lib.hpm_server_stats_get(self._h, ctypes.byref(s)), "hpm_server_stats_get")
+        return {f: getattr(s, f) for f, _ in HpmServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hpm_server_destroy(self._h)
+        self._h = None
+        self._live = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

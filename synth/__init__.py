@@ -13,4 +13,7 @@ from .generators import (  # noqa: F401
     random_subset,
     workload,
     WORKLOADS,
+    batch_requests,
+    serve_requests,
+    request_particles,
 )

@@ -183,3 +183,38 @@ def workload(name: str, n: int | None = None) -> Particles:
     count = w["n"] if n is None else int(n)
     gen = {"uniform": uniform_cube, "plummer": plummer_sphere, "clustered": clustered_spheres}[w["gen"]]
     return gen(count, w["seed"])
+
+
+# Mixes of independent solves. Each request is described by its particle count, distribution and
+# seed; request_particles draws its set.
+def batch_requests(count: int = 512, seed: int = 1003) -> list[dict]:
+    """The batched workload: ``count`` solves with N log-uniform in [2^10, 2^18] (rounded), even
+    indices a uniform cube and odd ones a Plummer sphere (as the 2^18 workload), gridlet order 4
+    or 6 by a seeded coin."""
+    rng = _rng(seed)
+    n = np.rint(2.0 ** rng.uniform(10.0, 18.0, count)).astype(np.int64)
+    ng = np.where(rng.random(count) < 0.5, 4, 6)
+    return [dict(n=int(n[i]), kind="uniform" if i % 2 == 0 else "plummer", ng=int(ng[i]),
+                 seed=seed * 1000 + i) for i in range(count)]
+
+
+def serve_requests(count: int, seed: int = 1004) -> list[dict]:
+    """The served workload's request pool: N log-uniform in [2^12, 2^20] (rounded); uniform cube,
+    Plummer sphere or clustered set (8 spheres on a 10% background) with equal odds; a relative
+    force tolerance of 1e-2 or 1e-4 with equal odds."""
+    rng = _rng(seed)
+    n = np.rint(2.0 ** rng.uniform(12.0, 20.0, count)).astype(np.int64)
+    kind = rng.integers(0, 3, count)
+    tol = np.where(rng.random(count) < 0.5, 1e-2, 1e-4)
+    names = ("uniform", "plummer", "clustered")
+    return [dict(n=int(n[i]), kind=names[int(kind[i])], tolerance=float(tol[i]),
+                 seed=seed * 1000 + i) for i in range(count)]
+
+
+def request_particles(req: dict) -> Particles:
+    """Particle set of one request of batch_requests or serve_requests."""
+    if req["kind"] == "uniform":
+        return uniform_cube(req["n"], req["seed"])
+    if req["kind"] == "plummer":
+        return plummer_sphere(req["n"], req["seed"])
+    return clustered_spheres(req["n"], req["seed"], n_spheres=8)

@@ -60,6 +60,7 @@ def _problem(**kw):
     (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=1), 1), (dict(abi=99), 1),
     (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
     (dict(kernel="yukawa", screening=float("nan")), 1), (dict(m2l_mode=2), 1), (dict(abi=3), 1),
+    (dict(abi=4), 1),
     (dict(extended=True), 6), (dict(extended_id=2, m2l="cells"), 1), (dict(reserved=1), 1),
 ])
 def test_bad_problem_rejected_on_host(kw, status):
@@ -93,3 +94,63 @@ def test_null_and_size_checks():
                               dummy, dummy, dummy, None) == 1
     assert lib.hpm_status_string(2) == b"HPM_ERR_OUT_OF_BOX"
     lib.hpm_plan_destroy(None)
+
+
+def _config(**kw):
+    from paper_1906_10734_amd import hpm
+    c = hpm.HpmServerConfig()
+    c.abi = kw.get("abi", hpm.HPM_ABI_VERSION)
+    c.slots = kw.get("slots", 2)
+    c.hbm_budget = kw.get("hbm_budget", 0)
+    c.reserved[0] = kw.get("reserved", 0)
+    return c
+
+
+@pytest.mark.parametrize("kw", [dict(abi=4), dict(slots=0), dict(slots=17),
+                                dict(hbm_budget=-1), dict(reserved=3)])
+def test_bad_server_config_rejected_on_host(kw):
+    from paper_1906_10734_amd import hpm
+    lib = hpm._lib
+    c = _config(**kw)
+    out = ctypes.c_void_p(123)
+    assert lib.hpm_server_create(ctypes.byref(c), ctypes.byref(out)) == 1
+    assert out.value is None
+    assert len(lib.hpm_last_error()) > 0
+
+
+def test_server_calls_check_their_arguments():
+    from paper_1906_10734_amd import hpm
+    lib = hpm._lib
+    dummy = ctypes.c_void_p(1)
+    t = ctypes.c_uint64()
+    info = hpm.HpmRequestInfo()
+    p = _problem()
+    assert lib.hpm_server_create(None, None) == 1
+    assert lib.hpm_server_submit(None, ctypes.byref(p), 16, *([dummy] * 8), ctypes.byref(t)) == 1
+    assert lib.hpm_server_poll(None, 1, ctypes.byref(info)) == 1
+    assert lib.hpm_server_wait(None, 1, ctypes.byref(info)) == 1
+    assert lib.hpm_server_stats_get(None, None) == 1
+    assert lib.hpm_server_run_batch(None, 0, None, None, *([None] * 8), None) == 1
+    lib.hpm_server_destroy(None)
+    assert lib.hpm_status_string(7) == b"HPM_ERR_NOT_READY"
+
+
+def test_plan_bytes_estimate():
+    """The admission estimate: checked like a plan's problem, grows with n, and covers the cell
+    arrays of the densest tree a uniform density gives (about 9.2 n / capacity cells)."""
+    from paper_1906_10734_amd import hpm
+    lib = hpm._lib
+    out = ctypes.c_int64()
+    bad = _problem(ng=5)
+    assert lib.hpm_plan_bytes_estimate(ctypes.byref(bad), 1000, ctypes.byref(out)) == 6
+    good = _problem()
+    assert lib.hpm_plan_bytes_estimate(ctypes.byref(good), 0, ctypes.byref(out)) == 1
+    assert lib.hpm_plan_bytes_estimate(ctypes.byref(good), 1000, None) == 1
+    f32 = [hpm.plan_bytes_estimate(hpm.Problem(ng=6), n) for n in (1 << 12, 1 << 16, 1 << 20)]
+    assert f32[0] < f32[1] < f32[2]
+    assert hpm.plan_bytes_estimate(hpm.Problem(ng=6, precision="f64"), 1 << 16) > f32[1]
+    assert hpm.plan_bytes_estimate(hpm.Problem(ng=6, m2l="cells"), 1 << 16) > f32[1]
+    n, cap = 1 << 20, 64
+    cells = 9.2 * n / cap
+    gridlets = cells * (2 * 216 + 216) * 4  # cells and virtual cubes, locals
+    assert hpm.plan_bytes_estimate(hpm.Problem(ng=6, leaf_capacity=cap), n) > gridlets
