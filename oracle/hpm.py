@@ -13,6 +13,13 @@ Steps (Sec. 1, enumerated list, and Sec. 2):
                    source cube a zero-padded (2 N_g)^3 transform times the transform of the
                    Green function at that cube's offset, the products summed and transformed
                    back once.
+         "shared": the transform shared by the children of one parent. Every child's zone lies
+                   in the parent's 6^3 block of cubes; the 152 cubes outside the block's central
+                   4^3 are in the zone of all 8 children, so one zero-padded (8 N_g)^3 transform
+                   of them per parent serves every child (its window read out per child). The
+                   zone's other 37 cubes (the central 4^3 minus the child's 27 near cubes) are
+                   added cell by cell. The two sets partition the zone, so nothing is
+                   subtracted.
   L2L  parent-to-child: potential multipoles Eq. (6), polynomial Eq. (7) at the child nodes.
   L2P  Eq. (7) at each particle, its gradient for the acceleration.
 
@@ -176,6 +183,9 @@ class HPM:
         self.ML = self.ne ** 3
         self._virtual = {}
         self._ghat = {}
+        self._shared = {}
+        if mode == "shared" and self.ext:
+            raise ValueError("the shared-transform route has no extended gridlet")
         self.gridlets = {}
         self.locals = {}
         self._upsweep()
@@ -237,6 +247,8 @@ class HPM:
             return self._m2l_direct(l, coord, sources)
         if self.mode == "cells":
             return self._m2l_cells(l, coord, sources)
+        if self.mode == "shared":
+            return self._m2l_shared(l, coord, sources)
         return self._m2l_fft(l, coord, sources)
 
     def _green_offset(self, l: int, d: tuple) -> np.ndarray:
@@ -304,6 +316,33 @@ class HPM:
         e = self.ext   # the extended gridlet reaches one node into the neighbouring cubes
         return pot[tb[2] * ng - e:(tb[2] + 1) * ng + e, tb[1] * ng - e:(tb[1] + 1) * ng + e,
                    tb[0] * ng - e:(tb[0] + 1) * ng + e].ravel().copy()
+
+    def _m2l_shared(self, l, coord, sources):
+        """Outer cubes of the parent's block (some block coordinate outside 1..4) through one
+        padded transform per parent, cached and read out at this child's window; the central
+        cubes of this child's zone cell by cell."""
+        ng = self.ng
+        n = 8 * ng
+        origin = 2 * ((coord >> 1) - 1)
+        outer, central = [], []
+        for q, g in sources:
+            b = np.asarray(q) - origin
+            (central if np.all((b >= 1) & (b <= 4)) else outer).append((q, g))
+        key = (l, tuple(int(v) for v in (coord >> 1)))
+        if key not in self._shared:
+            grid = np.zeros((n, n, n))
+            for q, g in outer:
+                b = np.asarray(q) - origin
+                grid[b[2] * ng:(b[2] + 1) * ng, b[1] * ng:(b[1] + 1) * ng,
+                     b[0] * ng:(b[0] + 1) * ng] = g.reshape(ng, ng, ng)
+            self._shared[key] = sfft.irfftn(sfft.rfftn(grid) * self._ghat_level(l), s=grid.shape)
+        pot = self._shared[key]
+        tb = coord - origin
+        out = pot[tb[2] * ng:(tb[2] + 1) * ng, tb[1] * ng:(tb[1] + 1) * ng,
+                  tb[0] * ng:(tb[0] + 1) * ng].ravel().copy()
+        if central:
+            out += self._m2l_cells(l, coord, central)
+        return out
 
     # ---- step 4: parent-to-child, level by level ------------------------------------------------
     def local(self, l: int, i: int) -> np.ndarray:

@@ -113,3 +113,48 @@ def test_cell_by_cell_transforms_equal_direct_mode(kernel, screening):
     phi_d, acc_d, _ = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="direct")
     assert potential_error(phi_c, phi_d) < 1e-13
     assert force_error(acc_c, acc_d)[0] < 1e-11
+
+
+def test_outer_and_central_cubes_partition_every_childs_zone():
+    # The sets the shared-transform route splits a child's zone into: the block cubes outside the
+    # central 4^3 (common to all 8 children) and the central cubes off the child's near zone.
+    # Brute force over the 8 children of an interior parent: disjoint, and their union is the
+    # zone (189 = 152 + 37).
+    from oracle.tree import Tree
+    parent = np.array([5, 6, 7])
+    origin = 2 * (parent - 1)
+    for c in range(8):
+        child = 2 * parent + np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1])
+        zone = {tuple(q) for q in Tree.interaction_positions(child, 5)}
+        outer = {tuple(origin + np.array(b)) for b in np.ndindex(6, 6, 6)
+                 if not all(1 <= v <= 4 for v in b)}
+        central = {tuple(origin + np.array(b)) for b in np.ndindex(6, 6, 6)
+                   if all(1 <= v <= 4 for v in b)}
+        near = {tuple(child + np.array(d) - 1) for d in np.ndindex(3, 3, 3)}
+        assert len(zone) == 189 and len(outer) == 152
+        assert outer <= zone and (central - near) <= zone
+        assert outer | (central - near) == zone and not (outer & (central - near))
+        assert len(central - near) == 37
+
+
+@pytest.mark.parametrize("kernel,screening", [("newton", 0.0), ("yukawa", 0.2)])
+def test_shared_transform_equals_direct_mode(kernel, screening):
+    # The transform shared by siblings (one padded grid of the outer cubes per parent, the central
+    # cubes cell by cell) computes the same sums as the definition, on an adaptive tree with
+    # cubes inside coarser leaves and zones cut by the box faces.
+    p = plummer_sphere(1500, 21, a=0.1)
+    prob = hpm.Problem(ng=4, softening=1e-3, leaf_capacity=16, max_depth=7, kernel=kernel,
+                       screening=screening)
+    phi_s, acc_s, h = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="shared")
+    assert len(h._shared) > 0 and len(h._virtual) > 0
+    phi_d, acc_d, _ = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="direct")
+    assert potential_error(phi_s, phi_d) < 1e-13
+    assert force_error(acc_s, acc_d)[0] < 1e-11
+
+
+def test_shared_transform_on_the_node_lattice_equals_direct_sum():
+    p = gridlet_node_lattice(3, 2, seed=7)
+    prob = hpm.Problem(ng=3, softening=1e-3, uniform_depth=2)
+    phi, _, _ = hpm.solve(p.x, p.y, p.z, p.m, prob, mode="shared")
+    ref, _ = direct_sum(p.x, p.y, p.z, p.m, 1.0, 1e-3)
+    assert potential_error(phi, ref) < 1e-13
