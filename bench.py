@@ -339,7 +339,7 @@ def main():
                     help="timed solves per point of the gridlet-order accuracy sweep")
     ap.add_argument("--profile", action="store_true",
                     help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
-    ap.add_argument("--m2l", choices=("grid", "cells"), default="grid",
+    ap.add_argument("--m2l", choices=("grid", "cells", "shared"), default="grid",
                     help="source-to-target route of the --profile run")
     ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
                     help="precision of the --profile run")
@@ -454,6 +454,8 @@ def main():
         return r["stages"][k] / max(r["stages"]["n_exec"], 1)
     rc, oc, _ = run_path(hpm, torch, parts, "f32", ng, args.steps, 1, m2l="cells")
     rcd, ocd, _ = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1, m2l="cells")
+    rs_, os__, _ = run_path(hpm, torch, parts, "f32", ng, args.steps, 1, m2l="shared")
+    rsd, osd, _ = run_path(hpm, torch, parts, "f64", ng, args.fp64_steps, 1, m2l="shared")
     pg = float(np.log2(ng))
     routes = {"cells_f32": {"value": round(args.n / (rc["ms_per_step"] * 1e-3), 1),
                             "ms_per_step": round(rc["ms_per_step"], 4),
@@ -461,6 +463,12 @@ def main():
               "cells_f64": {"value": round(args.n / (rcd["ms_per_step"] * 1e-3), 1),
                             "ms_per_step": round(rcd["ms_per_step"], 4),
                             "m2l_ms": round(stage(rcd, "m2l"), 4), "force_err_rms": ferr(ocd)[0]},
+              "shared_f32": {"value": round(args.n / (rs_["ms_per_step"] * 1e-3), 1),
+                             "ms_per_step": round(rs_["ms_per_step"], 4),
+                             "m2l_ms": round(stage(rs_, "m2l"), 4), "force_err_rms": ferr(os__)[0]},
+              "shared_f64": {"value": round(args.n / (rsd["ms_per_step"] * 1e-3), 1),
+                             "ms_per_step": round(rsd["ms_per_step"], 4),
+                             "m2l_ms": round(stage(rsd, "m2l"), 4), "force_err_rms": ferr(osd)[0]},
               "grid_m2l_ms": {"f32": round(stage(r32, "m2l"), 4), "f64": round(stage(r64, "m2l"), 4)},
               "paper_count_ratio_grid_over_cells": round(0.34 * (pg + 3) / (pg + 1), 3)}
     # the extended target gridlet (Sec. 2.5, N_g + 2 nodes per axis) on the cell route, at this

@@ -73,8 +73,16 @@ typedef enum { HPM_KERNEL_NEWTON = 0, HPM_KERNEL_YUKAWA = 1 } hpm_kernel;
  *                  transform of the Green function at that pair's cube offset, the products
  *                  summed and transformed back once per target (the alternative the paper
  *                  weighs in Sec. 2.5; kept for comparison).
+ *   HPM_M2L_SHARED one zero-padded (8 N_g)^3 convolution per split parent, shared by its children:
+ *                  the 152 cubes of the parent's 6^3 block outside its central 4^3 lie in the
+ *                  interaction zone of all 8 children, so their transform is taken once and
+ *                  read out at every child's window; the other 37 cubes of each child's zone
+ *                  (the central 4^3 minus its 27 near cubes) are added cell by cell as in
+ *                  HPM_M2L_CELLS. The two sets partition the zone, so nothing is subtracted
+ *                  (the sharing of transforms among siblings that Sec. 2.1 leaves open).
+ *                  N_g in {2, 3, 4, 6}; no extended gridlet.
  */
-typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1 } hpm_m2l_mode;
+typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1, HPM_M2L_SHARED = 2 } hpm_m2l_mode;
 
 /*
  * Problem description.

@@ -41,8 +41,9 @@ void check_problem(const hpm_problem* pr) {
   if (!(std::isfinite(pr->softening) && pr->softening >= 0.0)) fail(HPM_ERR_INVALID_ARG, "softening must be >= 0");
   if (!(std::isfinite(pr->gconst) && pr->gconst > 0.0)) fail(HPM_ERR_INVALID_ARG, "gconst must be > 0");
   check_kernel(pr->kernel, pr->screening);
-  if (pr->m2l_mode != HPM_M2L_GRID && pr->m2l_mode != HPM_M2L_CELLS)
-    fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID or HPM_M2L_CELLS");
+  if (pr->m2l_mode != HPM_M2L_GRID && pr->m2l_mode != HPM_M2L_CELLS &&
+      pr->m2l_mode != HPM_M2L_SHARED)
+    fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID, HPM_M2L_CELLS or HPM_M2L_SHARED");
   if (pr->extended != 0 && pr->extended != 1) fail(HPM_ERR_INVALID_ARG, "extended must be 0 or 1");
   if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
   if (pr->extended && pr->m2l_mode != HPM_M2L_CELLS)
@@ -67,7 +68,7 @@ void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* 
   p.moments.reserve(size_t(std::max<int64_t>(p.p2m_rows, 1)) * p.tab.kpad * p.elem);
   p.lofs.reserve(cells * 2 * p.elem);
   p.m2l_mean.reserve(cells * sizeof(double));
-  if (p.prob.m2l_mode == HPM_M2L_CELLS && p.nlevels > 2) {
+  if (p.prob.m2l_mode != HPM_M2L_GRID && p.nlevels > 2) {
     const size_t spec = cell_modes(p.ng, p.ext) * 2 * p.elem;
     const size_t ntg = cells - size_t(p.level_off[2]);
     p.cell_src.reserve((ntg + size_t(p.nvirt) + 1) * spec);  // + a zero row
@@ -75,7 +76,7 @@ void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* 
     build_cell_parents(p, s);  // read after the synchronisation of the near-zone lists
   }
   build_near_lists(p, s);
-  if (p.prob.m2l_mode == HPM_M2L_CELLS) read_cell_parents(p);
+  if (p.prob.m2l_mode != HPM_M2L_GRID) read_cell_parents(p);
   if (p.timing) {
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));
     HPM_HIP(hipEventSynchronize(p.tree_ev[1]));
@@ -154,6 +155,7 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
     HPM_HIP(hipEventRecord(p.join_ev, p.side));
   }
   if (p.prob.m2l_mode == HPM_M2L_CELLS) launch_m2l_cells(p, s);
+  else if (p.prob.m2l_mode == HPM_M2L_SHARED) launch_m2l_shared(p, s);
   else launch_m2l(p, s);
   if (ev) HPM_HIP(hipEventRecord(ev[3], s));
   for (int l = 2; l < p.nlevels; ++l) launch_l2l(p, l, s);  // level 2: re-centring only
@@ -201,7 +203,7 @@ size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
   b += c * (27 * 8 + 8 + 4 * (16 + 64 * 5 * s));  // near-zone ranges and work items
   const size_t H = 4 * ng + 1, levels = size_t(std::max(depth - 1, 1));
   b += levels * (H * H * H + 4 * ng * H * H) * s;  // Green transforms
-  if (pr.m2l_mode == HPM_M2L_CELLS) {
+  if (pr.m2l_mode != HPM_M2L_GRID) {
     const size_t spec = cell_modes(int(ng), pr.extended) * 2 * s;
     b += (2 * c + 1) * spec + levels * 343 * spec + 3 * 4 * c;
   }

@@ -107,7 +107,7 @@ struct Tables {
   DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
   DevBuf gxy;    // [levels 2..L][4 N_g][n/2+1][n/2+1]: Green function transformed along x and y
                  // only, at z offsets d < 4 N_g, [d][ky][kx], / n^2
-  DevBuf gcell;  // cell-by-cell route only: [levels 2..L][343 offsets][(2N_g)^2 (N_g+1)] complex,
+  DevBuf gcell;  // cell-by-cell and shared-transform routes only: [levels 2..L][343 offsets][(2N_g)^2 (N_g+1)] complex,
                  // transform of the cyclic Green array of each source cube offset, / (2 N_g)^3
   int kpad = 0, mpad = 0;
   int ghat_levels = 0;
@@ -239,6 +239,9 @@ void launch_m2m(Plan& p, int level, hipStream_t s);
 
 // ---- m2l.hip -------------------------------------------------------------------------------------
 void launch_m2l(Plan& p, hipStream_t s);
+// the transform shared by the children of each split parent (outer cubes of its block); writes
+// each child's (mean, zero-mean gridlet)
+void launch_m2l_parents(Plan& p, hipStream_t s);
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 
 // ---- m2l_cells.hip -------------------------------------------------------------------------------
@@ -251,6 +254,9 @@ size_t cell_modes(int ng, int ext);
 void build_cell_parents(Plan& p, hipStream_t s);
 void read_cell_parents(Plan& p);
 void launch_m2l_cells(Plan& p, hipStream_t s);
+// the shared-transform route: the central cubes cell by cell, the outer cubes by
+// launch_m2l_parents, both added into each target's (mean, zero-mean gridlet)
+void launch_m2l_shared(Plan& p, hipStream_t s);
 
 // ---- downsweep.hip -------------------------------------------------------------------------------
 void build_near_lists(Plan& p, hipStream_t s);

@@ -58,6 +58,10 @@ struct M2LArgs {
   const T* gxy;
   cplx<T>* work;
   double lo0, lo1, lo2, size;
+  // per-parent kernel: the split parents (cell ids) and every cell's 8 children (or -1)
+  const int* plist;
+  int nparents;
+  const int* child8;
 };
 
 constexpr int fold_k(int k, int n) { return k <= n / 2 ? k : n - k; }
@@ -332,6 +336,82 @@ struct SlabShape {
   static constexpr bool fits = slab_bytes + red_bytes <= 150 * 1024;
 };
 
+// The slab loop of the z-slab scheme: every source z row of the 6 N_g block (the cubes of s_src)
+// through the x and y transforms in LDS and into the real-space z sum (pr, pi) at the N_g target
+// z values Zt .. Zt + N_g - 1. Called by all threads of the workgroup; the accumulators are
+// per thread, entry e = tid + NT r.
+template <typename T, int NG>
+__device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, cplx<T>* slab,
+                                         const T* gtab, int Zt,
+                                         T (&pr)[SlabShape<T, NG>::PER][NG],
+                                         T (&pi)[SlabShape<T, NG>::PER][NG]) {
+  using S = SlabShape<T, NG>;
+  constexpr int n = S::n, H = S::H, W = S::W, NT = S::NT, ZB = S::ZB, PER = S::PER, NJ = S::NJ,
+                ENT = S::ENT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < PER; ++r)
+#pragma unroll
+    for (int zz = 0; zz < NG; ++zz) pr[r][zz] = pi[r][zz] = T(0);
+
+  for (int z0 = 0; z0 < W; z0 += ZB) {
+    // x: rows (zb, y) of the slab, y fastest, one real row per thread
+    for (int w = tid; w < ZB * W; w += NT) {
+      const int zb = w / W, yr = w % W;
+      cplx<T> X[H];
+      xpass_row<T, NG>(a, yr, z0 + zb, s_src, X);
+      cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
+#pragma unroll
+      for (int k = 0; k < H; ++k) row[k] = X[k];
+    }
+    __syncthreads();
+    // y: columns (zb, kx); rows y >= 6 N_g are zero
+    for (int w = tid; w < ZB * H; w += NT) {
+      const int kx = w % H, zb = w / H;
+      cplx<T>* col = slab + size_t(zb) * n * H + kx;
+      cplx<T> in[n], out[n];
+#pragma unroll
+      for (int y = 0; y < n; ++y) in[y] = (y < W) ? col[size_t(y) * H] : cplx<T>{T(0), T(0)};
+      fft<n, -1>(in, out);
+#pragma unroll
+      for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
+    }
+    __syncthreads();
+    // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab, the slab's
+    // terms chained with FMAs before they join the running sum
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + NT * r;
+      if (e < ENT) {
+        const int ky = e / H, kx = e % H;
+        const int kyf = ky <= n / 2 ? ky : n - ky;
+        T g[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int d = Zt - z0 + j - (ZB - 1);
+          g[j] = gtab[(size_t(d < 0 ? -d : d) * H + kyf) * H + kx];
+        }
+        cplx<T> sv[ZB];
+#pragma unroll
+        for (int zb = 0; zb < ZB; ++zb) sv[zb] = slab[(size_t(zb) * n + ky) * H + kx];
+#pragma unroll
+        for (int zz = 0; zz < NG; ++zz) {
+          T ar = g[zz + ZB - 1] * sv[0].re, ai = g[zz + ZB - 1] * sv[0].im;
+#pragma unroll
+          for (int zb = 1; zb < ZB; ++zb) {
+            const T gv = g[zz - zb + ZB - 1];
+            ar = fma(gv, sv[zb].re, ar);
+            ai = fma(gv, sv[zb].im, ai);
+          }
+          pr[r][zz] += ar;
+          pi[r][zz] += ai;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int NG>
 __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   using S = SlabShape<T, NG>;
@@ -376,67 +456,7 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     const int Zt = (2 + t.cz) * NG;
 
     T pr[PER][NG], pi[PER][NG];
-#pragma unroll
-    for (int r = 0; r < PER; ++r)
-#pragma unroll
-      for (int zz = 0; zz < NG; ++zz) pr[r][zz] = pi[r][zz] = T(0);
-
-    for (int z0 = 0; z0 < W; z0 += ZB) {
-      // x: rows (zb, y) of the slab, y fastest, one real row per thread
-      for (int w = tid; w < ZB * W; w += NT) {
-        const int zb = w / W, yr = w % W;
-        cplx<T> X[H];
-        xpass_row<T, NG>(a, yr, z0 + zb, s_src, X);
-        cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
-#pragma unroll
-        for (int k = 0; k < H; ++k) row[k] = X[k];
-      }
-      __syncthreads();
-      // y: columns (zb, kx); rows y >= 6 N_g are zero
-      for (int w = tid; w < ZB * H; w += NT) {
-        const int kx = w % H, zb = w / H;
-        cplx<T>* col = slab + size_t(zb) * n * H + kx;
-        cplx<T> in[n], out[n];
-#pragma unroll
-        for (int y = 0; y < n; ++y) in[y] = (y < W) ? col[size_t(y) * H] : cplx<T>{T(0), T(0)};
-        fft<n, -1>(in, out);
-#pragma unroll
-        for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
-      }
-      __syncthreads();
-      // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab, the slab's
-      // terms chained with FMAs before they join the running sum
-#pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int e = tid + NT * r;
-        if (e < ENT) {
-          const int ky = e / H, kx = e % H;
-          const int kyf = ky <= n / 2 ? ky : n - ky;
-          T g[NJ];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            const int d = Zt - z0 + j - (ZB - 1);
-            g[j] = gtab[(size_t(d < 0 ? -d : d) * H + kyf) * H + kx];
-          }
-          cplx<T> sv[ZB];
-#pragma unroll
-          for (int zb = 0; zb < ZB; ++zb) sv[zb] = slab[(size_t(zb) * n + ky) * H + kx];
-#pragma unroll
-          for (int zz = 0; zz < NG; ++zz) {
-            T ar = g[zz + ZB - 1] * sv[0].re, ai = g[zz + ZB - 1] * sv[0].im;
-#pragma unroll
-            for (int zb = 1; zb < ZB; ++zb) {
-              const T gv = g[zz - zb + ZB - 1];
-              ar = fma(gv, sv[zb].re, ar);
-              ai = fma(gv, sv[zb].im, ai);
-            }
-            pr[r][zz] += ar;
-            pi[r][zz] += ai;
-          }
-        }
-      }
-      __syncthreads();
-    }
+    slab_sum<T, NG>(a, s_src, slab, gtab, Zt, pr, pi);
 
     // The inverse y transform runs in the plan's precision (the N_g target values of each column
     // kept) and the inverse x transform in double precision as direct sums against a double
@@ -499,6 +519,131 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     mean *= 1.0 / M;
     for (int e = tid; e < M; e += NT) a.local[size_t(t.g) * M + e] = T(s_out[e] - mean);
     if (tid == 0) a.m2l_mean[t.g] = mean;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The transform shared by the children of one split parent. Every child's interaction zone lies
+// in the parent's 6^3 block; the 152 block cubes outside the central 4^3 are in the zone of all
+// 8 children. One workgroup per parent runs the z-slab scheme over those cubes for each half cz
+// of the children (target z window (2 + cz) N_g .. (3 + cz) N_g - 1, the accumulators of one
+// window per pass), then the inverse y transform keeping both children's y windows, then for
+// each existing child the inverse x transform, its mean and its zero-mean gridlet. The other 37
+// cubes of each child's zone are added afterwards, cell by cell.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int NG>
+struct ParentShape {
+  using S = SlabShape<T, NG>;
+  static constexpr size_t red_bytes = size_t(NG) * 2 * NG * S::H * sizeof(cplx<T>) +
+                                      size_t(S::M) * 8 + size_t(S::n) * sizeof(cplx<double>);
+  static constexpr bool fits = S::slab_bytes + red_bytes + 216 * 4 + 64 <= 150 * 1024;
+};
+
+template <typename T, int NG>
+__global__ __launch_bounds__(kSlabThreads) void k_m2l_parent(M2LArgs<T> a) {
+  using S = SlabShape<T, NG>;
+  constexpr int n = S::n, H = S::H, M = S::M, NT = S::NT, D = S::D, PER = S::PER, ENT = S::ENT;
+  static_assert(ParentShape<T, NG>::fits, "parent buffers exceed the LDS budget");
+  static_assert(S::ZB >= NG, "the slab buffer holds the N_g accumulated planes");
+  __shared__ int s_src[216];
+  __shared__ int s_kid[8];
+  __shared__ int s_off[kMaxLevels + 1];
+  __shared__ __align__(16) cplx<T> slab[S::ZB * n * H];
+  __shared__ cplx<T> red[NG * 2 * NG * H];  // after y^-1: [Z][Y, both children's windows][kx]
+  __shared__ double s_out[M];
+  __shared__ double s_red[NT / 64];
+  __shared__ cplx<double> s_tw[n];  // e^{+2 pi i m / n}
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  for (int m = tid; m < n; m += NT) {
+    double sv, cv;
+    sincospi(2.0 * m / n, &sv, &cv);
+    s_tw[m] = {cv, sv};
+  }
+
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, jb = blockIdx.x >> 3;
+  const int p_begin = int((int64_t(a.nparents) * xcd) / 8);
+  const int p_end = int((int64_t(a.nparents) * (xcd + 1)) / 8);
+
+  for (int pi_ = p_begin + jb; pi_ < p_end; pi_ += per) {
+    __syncthreads();
+    const int par = a.plist[pi_];
+    const int l = level_of(par, s_off, a.nlevels) + 1;  // the children's level (>= 2)
+    if (tid < 216) {
+      const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
+      const bool central = bx >= 1 && bx <= 4 && by >= 1 && by <= 4 && bz >= 1 && bz <= 4;
+      s_src[tid] = central ? -1 : a.blocks[size_t(par - a.first_parent) * 216 + tid];
+    }
+    if (tid < 8) s_kid[tid] = a.child8[size_t(par) * 8 + tid];
+    __syncthreads();
+    const T* gtab = a.gxy + size_t(l - 2) * D * H * H;
+
+    for (int cz = 0; cz < 2; ++cz) {
+      // block-uniform: every thread reads the same child ids
+      if (s_kid[4 * cz] < 0 && s_kid[4 * cz + 1] < 0 && s_kid[4 * cz + 2] < 0 &&
+          s_kid[4 * cz + 3] < 0)
+        continue;
+      T pr[PER][NG], pim[PER][NG];
+      slab_sum<T, NG>(a, s_src, slab, gtab, (2 + cz) * NG, pr, pim);
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int e = tid + NT * r;
+        if (e < ENT) {
+#pragma unroll
+          for (int zz = 0; zz < NG; ++zz) slab[size_t(zz) * ENT + e] = {pr[r][zz], pim[r][zz]};
+        }
+      }
+      __syncthreads();
+      // y^-1: red[Z][Y][kx], Y = 2 N_g + yy for yy < 2 N_g (the windows of cy = 0 and 1)
+      for (int w = tid; w < NG * H; w += NT) {
+        const int kx = w % H, zz = w / H;
+        const cplx<T>* col = slab + size_t(zz) * ENT + kx;
+        cplx<T> in[n], out[n];
+#pragma unroll
+        for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
+        fft<n, +1>(in, out);
+#pragma unroll
+        for (int yy = 0; yy < 2 * NG; ++yy) red[(size_t(zz) * 2 * NG + yy) * H + kx] = out[2 * NG + yy];
+      }
+      __syncthreads();
+      for (int c = 4 * cz; c < 4 * cz + 4; ++c) {
+        const int g = s_kid[c];
+        if (g < 0) continue;  // block-uniform
+        const int cx = c & 1, cy = (c >> 1) & 1;
+        // x^-1 (Hermitian half spectrum) in double: out = sum_k w_k Re(F_k e^{+2 pi i k X / n}),
+        // w_k = 1 at k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g + xx
+        const int Xt = (2 + cx) * NG;
+        for (int q = tid; q < M; q += NT) {
+          const int xx = q % NG, yy = (q / NG) % NG, zz = q / (NG * NG);
+          const int X = Xt + xx;
+          const cplx<T>* F = red + (size_t(zz) * 2 * NG + cy * NG + yy) * H;
+          double acc = 0.0;
+          int m = 0;
+          for (int k = 0; k < H; ++k) {
+            const cplx<double> f = {double(F[k].re), double(F[k].im)};
+            const cplx<double> w = s_tw[m];
+            const double v = f.re * w.re - f.im * w.im;
+            acc += (k == 0 || k == n / 2) ? v : 2.0 * v;
+            m += X;
+            if (m >= n) m -= n;
+          }
+          s_out[q] = acc;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int e = tid; e < M; e += NT) part += s_out[e];
+        part = wave_sum(part);
+        if ((tid & 63) == 0) s_red[tid >> 6] = part;
+        __syncthreads();
+        double mean = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) mean += s_red[w];
+        mean *= 1.0 / M;
+        for (int e = tid; e < M; e += NT) a.local[size_t(g) * M + e] = T(s_out[e] - mean);
+        if (tid == 0) a.m2l_mean[g] = mean;
+        __syncthreads();  // s_out and s_red are reused by the next child
+      }
+    }
   }
 }
 
@@ -571,6 +716,63 @@ static void m2l_t(Plan& p, hipStream_t s) {
   if constexpr (m2l_kind<T, NG>() == 1) k_m2l_slab<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
   else k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
+}
+
+// The per-parent shared transform over the outer cubes of every split parent's block; it writes
+// each child's result as (mean, zero-mean gridlet), which the cell-by-cell pass over the central
+// cubes then adds to.
+template <typename T, int NG>
+static void parents_t(Plan& p, hipStream_t s) {
+  if constexpr (!ParentShape<T, NG>::fits) {
+    fail(HPM_ERR_UNSUPPORTED, "no shared-transform kernel for this gridlet");
+  } else {
+    p.m2l_split = true;
+    if (p.nlevels <= 2) return;
+    M2LArgs<T> a{};
+    a.nparents = p.cell_pbeg[p.nlevels - 1];
+    if (a.nparents <= 0) return;
+    const int64_t first = p.level_off[1], last = p.level_off[p.nlevels - 1];
+    if (p.cell_plist.bytes < size_t(a.nparents) * 4 ||
+        p.blocks.bytes < size_t(last - first) * 216 * 4 || p.blocks_first != first ||
+        p.local.bytes < size_t(p.ncells) * SlabShape<T, NG>::M * sizeof(T))
+      fail(HPM_ERR_DEVICE, "shared-transform buffers inconsistent with the tree");
+    a.nlevels = p.nlevels;
+    a.depth = p.depth;
+    a.level_off = p.dlevel.as<int>();
+    a.blocks = p.blocks.as<int>();
+    a.first_parent = p.blocks_first;
+    a.gridlet = p.gridlet.as<T>();
+    a.local = p.local.as<T>();
+    a.m2l_mean = p.m2l_mean.as<double>();
+    a.gxy = p.tab.gxy.as<T>();
+    a.size = p.prob.box_size;
+    a.plist = p.cell_plist.as<int>();
+    a.child8 = p.child8.as<int>();
+    int grid = ((a.nparents + 7) / 8) * 8;
+    if (grid > kSlabGrid) grid = kSlabGrid;
+    k_m2l_parent<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
+    HPM_LAUNCH_CHECK();
+  }
+}
+
+void launch_m2l_parents(Plan& p, hipStream_t s) {
+  if (p.prec == HPM_F32) {
+    switch (p.ng) {
+      case 2: parents_t<float, 2>(p, s); break;
+      case 3: parents_t<float, 3>(p, s); break;
+      case 4: parents_t<float, 4>(p, s); break;
+      case 6: parents_t<float, 6>(p, s); break;
+      default: fail(HPM_ERR_UNSUPPORTED, "no shared-transform kernel for this gridlet");
+    }
+  } else {
+    switch (p.ng) {
+      case 2: parents_t<double, 2>(p, s); break;
+      case 3: parents_t<double, 3>(p, s); break;
+      case 4: parents_t<double, 4>(p, s); break;
+      case 6: parents_t<double, 6>(p, s); break;
+      default: fail(HPM_ERR_UNSUPPORTED, "no shared-transform kernel for this gridlet");
+    }
+  }
 }
 
 void launch_m2l(Plan& p, hipStream_t s) {

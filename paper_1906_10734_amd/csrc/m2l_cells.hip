@@ -155,8 +155,10 @@ struct AccumShape {
 };
 
 // One launch per parent level; workgroup (chunk, group): modes [chunk KM, chunk KM + KM) of the
-// split parents plist[pbeg + group PP ...], one (parent, mode) per thread.
-template <typename T, int NG, int EXT>
+// split parents plist[pbeg + group PP ...], one (parent, mode) per thread. CENTRAL: only the
+// sources in the central 4^3 of the block (block coordinates 1..4; the rest of every child's
+// zone comes from the transform shared by the parent's children).
+template <typename T, int NG, int EXT, bool CENTRAL = false>
 __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, const int* plist,
                                                      int pbeg, int pend) {
   using S = CellShape<NG, EXT>;
@@ -192,10 +194,14 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
     // two planes at a time in FP32, so that one plane's loads overlap the other's arithmetic
     // (FP64 has no registers to spare for it)
 #pragma unroll sizeof(T) == 4 ? 2 : 1
-    for (int bz = 0; bz < 6; ++bz) {
+    for (int bz = CENTRAL ? 1 : 0; bz < (CENTRAL ? 5 : 6); ++bz) {
       cplx<T> sp[36];
 #pragma unroll
-      for (int j = 0; j < 36; ++j) sp[j] = a.sspec[size_t(row[bz * 36 + j]) * K + k];
+      for (int j = 0; j < 36; ++j) {
+        const int jx = j % 6, jy = j / 6;
+        if (CENTRAL && (jx < 1 || jx > 4 || jy < 1 || jy > 4)) continue;
+        sp[j] = a.sspec[size_t(row[bz * 36 + j]) * K + k];
+      }
 #pragma unroll
       for (int cz = 0; cz < 2; ++cz) {
         const int dz = bz - 2 - cz;  // in [-3, 3]
@@ -214,6 +220,7 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
               for (int cx = 0; cx < 2; ++cx) {
                 const int by = dy + 2 + cy, bx = dx + 2 + cx;
                 if (by < 0 || by > 5 || bx < 0 || bx > 5) continue;
+                if (CENTRAL && (by < 1 || by > 4 || bx < 1 || bx > 4)) continue;
                 cplx<T>& o = acc[cx | (cy << 1) | (cz << 2)];
                 const cplx<T> sv = sp[by * 6 + bx];
                 o.re = fma(gv.re, sv.re, o.re);
@@ -238,11 +245,13 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
 template <int C, int EXT>
 __device__ __forceinline__ int cyc(int t) { return t >= EXT ? t - EXT : t - EXT + C; }
 
-template <typename T, int NG, int EXT>
+// ADD: the target already holds (mean, zero-mean gridlet) from the transform shared by its
+// parent's children; this pass adds its own mean and zero-mean part to them (both precisions).
+template <typename T, int NG, int EXT, bool ADD = false>
 __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
   using S = CellShape<NG, EXT>;
   constexpr int C = S::C, HC = S::HC, K = S::K, NL = S::NL, M = S::ML;
-  constexpr bool split = sizeof(T) == 4;
+  constexpr bool split = ADD || sizeof(T) == 4;
   __shared__ cplx<double> tw[C];
   __shared__ cplx<double> s_f[K];              // [kz][ky][kx]
   __shared__ cplx<double> s_b1[NL * C * HC];   // [z][ky][kx], target z
@@ -309,15 +318,22 @@ __global__ __launch_bounds__(256) void k_cells_inverse(CellArgs<T> a) {
     if ((tid & 63) == 0) s_red[tid >> 6] = part;
     __syncthreads();
     const double mean = (s_red[0] + s_red[1] + s_red[2] + s_red[3]) * (1.0 / M);
-    for (int e = tid; e < M; e += 256) out[e] = T(s_out[e] - mean);
-    if (tid == 0) a.m2l_mean[g] = mean;
+    if constexpr (ADD) {
+      for (int e = tid; e < M; e += 256) out[e] = T(double(out[e]) + (s_out[e] - mean));
+      if (tid == 0) a.m2l_mean[g] += mean;
+    } else {
+      for (int e = tid; e < M; e += 256) out[e] = T(s_out[e] - mean);
+      if (tid == 0) a.m2l_mean[g] = mean;
+    }
   }
 }
 
-template <typename T, int NG, int EXT>
+// SHARED: the route with the transform shared by siblings (the central cubes here, the outer
+// cubes by the per-parent kernel before the inverse adds to its result)
+template <typename T, int NG, int EXT, bool SHARED = false>
 static void cells_t(Plan& p, hipStream_t s) {
   using S = CellShape<NG, EXT>;
-  p.m2l_split = sizeof(T) == 4;
+  p.m2l_split = SHARED || sizeof(T) == 4;
   if (p.nlevels <= 2) return;
   CellArgs<T> a;
   a.first_cell = p.level_off[2];
@@ -347,11 +363,12 @@ static void cells_t(Plan& p, hipStream_t s) {
     const int pbeg = p.cell_pbeg[lp], pend = p.cell_pbeg[lp + 1];
     if (pend <= pbeg) continue;
     const int groups = std::min((pend - pbeg + A::PP - 1) / A::PP, 65535);
-    k_cells_accum<T, NG, EXT><<<dim3(S::KP / A::KM, groups), 256, 0, s>>>(
+    k_cells_accum<T, NG, EXT, SHARED><<<dim3(S::KP / A::KM, groups), 256, 0, s>>>(
         a, lp + 1, p.cell_plist.as<int>(), pbeg, pend);
     HPM_LAUNCH_CHECK();
   }
-  k_cells_inverse<T, NG, EXT><<<ntargets, 256, 0, s>>>(a);
+  if constexpr (SHARED) launch_m2l_parents(p, s);
+  k_cells_inverse<T, NG, EXT, SHARED><<<ntargets, 256, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 
@@ -425,6 +442,23 @@ static void cells_dispatch(Plan& p, hipStream_t s) {
 void launch_m2l_cells(Plan& p, hipStream_t s) {
   if (p.prec == HPM_F32) cells_dispatch<float>(p, s);
   else cells_dispatch<double>(p, s);
+}
+
+template <typename T>
+static void shared_dispatch(Plan& p, hipStream_t s) {
+  if (p.ext) fail(HPM_ERR_UNSUPPORTED, "the shared-transform route has no extended gridlet");
+  switch (p.ng) {
+    case 2: cells_t<T, 2, 0, true>(p, s); break;
+    case 3: cells_t<T, 3, 0, true>(p, s); break;
+    case 4: cells_t<T, 4, 0, true>(p, s); break;
+    case 6: cells_t<T, 6, 0, true>(p, s); break;
+    default: fail(HPM_ERR_UNSUPPORTED, "no shared-transform kernels for this gridlet");
+  }
+}
+
+void launch_m2l_shared(Plan& p, hipStream_t s) {
+  if (p.prec == HPM_F32) shared_dispatch<float>(p, s);
+  else shared_dispatch<double>(p, s);
 }
 
 }  // namespace hpm

@@ -278,7 +278,7 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
         }
   }
   p.tab.ghat_levels = nlev;
-  if (p.prob.m2l_mode == HPM_M2L_CELLS) {
+  if (p.prob.m2l_mode != HPM_M2L_GRID) {
     const std::vector<double> gc = cell_green(p, nlev);
     if (p.prec == HPM_F32) upload<float>(p.tab.gcell, gc, s);
     else upload<double>(p.tab.gcell, gc, s);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libhpm.so")
 HPM_ABI_VERSION = 5
 HPM_F64, HPM_F32 = 0, 1
 HPM_KERNELS = {"newton": 0, "yukawa": 1}
-HPM_M2L_MODES = {"grid": 0, "cells": 1}
+HPM_M2L_MODES = {"grid": 0, "cells": 1, "shared": 2}
 STATUS = {0: "HPM_OK", 1: "HPM_ERR_INVALID_ARG", 2: "HPM_ERR_OUT_OF_BOX", 3: "HPM_ERR_NONFINITE",
           4: "HPM_ERR_NO_MEMORY", 5: "HPM_ERR_DEVICE", 6: "HPM_ERR_UNSUPPORTED",
           7: "HPM_ERR_NOT_READY"}
@@ -144,7 +144,8 @@ class Problem:
     box_size: float = 1.0
     kernel: str = "newton"          # "newton" or "yukawa" (screened, needs screening > 0)
     screening: float = 0.0
-    m2l: str = "grid"               # "grid" (the method) or "cells" (cell-by-cell comparison)
+    m2l: str = "grid"               # "grid" (the method), "cells" (cell by cell) or "shared"
+                                    # (one transform per parent for its children's common cubes)
     extended: bool = False          # target gridlets widened by one node per side (cells route)
 
     @property

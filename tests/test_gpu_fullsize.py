@@ -3,8 +3,9 @@
 (tests/golden/make_plummer2p18.py): 256 particles' potentials and accelerations, and the local
 gridlet potentials of 48 target cells at levels >= 2, matched by level and integer coordinates.
 Every source-to-target route the benchmark times is checked: the padded grid, the cell-by-cell
-route (against the same values: the oracle's two modes agree to rounding) and the cell route with
-extended target gridlets (against the oracle's extended values).
+route and the route with the transform shared by siblings (against the same values: the oracle's
+modes agree to rounding), and the cell route with extended target gridlets (against the oracle's
+extended values).
 
 Tolerances as in the small-case parity tests: FP64 path 1e-10 relative, FP32 path 1e-5 relative
 RMS in potential (acceleration 1e-4, local gridlets 2e-5 of the level's largest value)."""
@@ -32,6 +33,12 @@ def test_plummer2p18_sampled_outputs_match_oracle(ng, prec):
 @pytest.mark.parametrize("ng,extended", [(4, False), (6, False), (4, True), (6, True)])
 def test_plummer2p18_cell_route_matches_oracle(ng, extended, prec):
     _check(ng, prec, "cells", extended)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("ng", [4, 6])
+def test_plummer2p18_shared_route_matches_oracle(ng, prec):
+    _check(ng, prec, "shared", False)
 
 
 def _check(ng, prec, m2l, extended):
