@@ -17,7 +17,7 @@
 // remains per pair is the pointwise product, C^2 (N_g + 1) complex multiply-adds.
 //
 // Kernels:
-//   k_cells_forward   one workgroup per source gridlet (cells of levels >= 2 and virtual cubes):
+//   k_cells_forward   one wave per source gridlet (cells of levels >= 2 and virtual cubes):
 //                     half spectrum [kz < C][ky < C][kx <= N_g] by separable direct sums.
 //   k_cells_accum     one thread per (parent, mode), one launch per parent level. The Green table
 //                     of the level is shared by every parent, so a workgroup stages its chunk of
@@ -85,8 +85,12 @@ struct CellArgs {
   double* m2l_mean;      // [cells]: mean of each target's result, FP32 plans
 };
 
+// one wave per source: a source is a few thousand multiply-adds, so many sources in flight per CU
+// (small workgroups) hide the load and store latency that dominates
+constexpr int kFwdThreads = 64;
+
 template <typename T, int NG, int EXT>
-__global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
+__global__ __launch_bounds__(kFwdThreads) void k_cells_forward(CellArgs<T> a) {
   using S = CellShape<NG, EXT>;
   constexpr int C = S::C, HC = S::HC, K = S::K, KP = S::KP, M = S::M;
   __shared__ cplx<T> tw[C];
@@ -95,14 +99,14 @@ __global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
   __shared__ cplx<T> s_a2[NG * C * HC];   // [z][ky][kx]
   const int src = blockIdx.x, tid = threadIdx.x;
   if (src == a.nsources) {  // the zero row that empty block slots read
-    for (int e = tid; e < KP; e += 256) a.sspec[size_t(src) * KP + e] = {T(0), T(0)};
+    for (int e = tid; e < KP; e += kFwdThreads) a.sspec[size_t(src) * KP + e] = {T(0), T(0)};
     return;
   }
   load_twiddles<T, C>(tw, -1.0);
   const T* g = a.gridlet + size_t(a.first_cell + src) * M;
-  for (int e = tid; e < M; e += 256) s_g[e] = g[e];
+  for (int e = tid; e < M; e += kFwdThreads) s_g[e] = g[e];
   __syncthreads();
-  for (int e = tid; e < NG * NG * HC; e += 256) {
+  for (int e = tid; e < NG * NG * HC; e += kFwdThreads) {
     const int kx = e % HC, row = e / HC;  // row = z * NG + y
     cplx<T> acc = {T(0), T(0)};
     int m = 0;
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
     s_a1[e] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < NG * C * HC; e += 256) {
+  for (int e = tid; e < NG * C * HC; e += kFwdThreads) {
     const int kx = e % HC, ky = (e / HC) % C, z = e / (HC * C);
     cplx<T> acc = {T(0), T(0)};
     int m = 0;
@@ -131,8 +135,8 @@ __global__ __launch_bounds__(256) void k_cells_forward(CellArgs<T> a) {
   }
   __syncthreads();
   cplx<T>* out = a.sspec + size_t(src) * KP;
-  for (int e = K + tid; e < KP; e += 256) out[e] = {T(0), T(0)};
-  for (int e = tid; e < K; e += 256) {
+  for (int e = K + tid; e < KP; e += kFwdThreads) out[e] = {T(0), T(0)};
+  for (int e = tid; e < K; e += kFwdThreads) {
     const int col = e % (C * HC), kz = e / (C * HC);  // col = ky * HC + kx
     cplx<T> acc = {T(0), T(0)};
     int m = 0;
@@ -356,7 +360,7 @@ static void cells_t(Plan& p, hipStream_t s) {
       p.cell_tgt.bytes < size_t(ntargets) * S::KP * sizeof(cplx<T>) ||
       p.local.bytes < size_t(p.ncells) * S::ML * sizeof(T))
     fail(HPM_ERR_DEVICE, "cell spectra buffers too small");
-  k_cells_forward<T, NG, EXT><<<a.nsources + 1, 256, 0, s>>>(a);
+  k_cells_forward<T, NG, EXT><<<a.nsources + 1, kFwdThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
   using A = AccumShape<T>;
   for (int lp = 1; lp + 1 < p.nlevels; ++lp) {
