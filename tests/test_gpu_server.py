@@ -180,3 +180,34 @@ def test_tickets_are_reported_once(mix):
             sv.wait(t)
         with pytest.raises(hpm.HpmError):
             sv.poll(t + 1000)
+
+
+def test_submissions_from_several_host_threads(mix):
+    """Six host threads submit and wait for their own requests on one server at once: every
+    result is the solve alone."""
+    import threading
+    from paper_1906_10734_amd import hpm
+    results, errors = {}, []
+    with hpm.Server(slots=4) as sv:
+        def client(k):
+            try:
+                got = []
+                for j in range(3):
+                    i = (k + 5 * j) % len(mix)
+                    t = sv.submit(mix[i][0], *mix[i][1])
+                    got.append((i, sv.wait(t)))
+                results[k] = got
+            except Exception as e:  # reported below, in the test's thread
+                errors.append(e)
+        threads = [threading.Thread(target=client, args=(k,)) for k in range(6)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=120)
+        st = sv.stats()
+    assert not errors, errors
+    assert len(results) == 6 and st["completed"] == 18 and st["failed"] == 0
+    for got in results.values():
+        for i, (info, out) in got:
+            assert info["status"] == "HPM_OK"
+            assert _same(out, mix[i][2]), MIX[i]
