@@ -169,12 +169,19 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
   using A = AccumShape<T>;
   constexpr int K = S::KP, KM = A::KM, PP = A::PP;  // the stored rows (zero-padded modes)
   static_assert(K % KM == 0, "mode chunks tile the spectrum");
-  __shared__ cplx<T> s_g[S::OFFS * KM];  // [offset][mode]
-  __shared__ int s_src[PP * 216];         // source spectrum rows of the group's blocks
+  // staged offsets: all 7^3 (|d| <= 3), or for the central cubes the 5^3 with |d| <= 2
+  constexpr int OW = CENTRAL ? 5 : 7, OR = OW / 2, NOFF = OW * OW * OW;
+  __shared__ cplx<T> s_g[NOFF * KM];  // [offset][mode], offset (dx+OR) + OW (dy+OR) + OW^2 (dz+OR)
+  __shared__ int s_src[PP * 216];      // source spectrum rows of the group's blocks
   const int tid = threadIdx.x, m = tid % KM, pp = tid / KM;
   const int k0 = blockIdx.x * KM, k = k0 + m;
   const cplx<T>* G = a.gcell + size_t(tlevel - 2) * S::OFFS * K + k0;
-  for (int e = tid; e < S::OFFS * KM; e += 256) s_g[e] = G[size_t(e / KM) * K + e % KM];
+  for (int e = tid; e < NOFF * KM; e += 256) {
+    const int o = e / KM;
+    const int dx = o % OW - OR, dy = (o / OW) % OW - OR, dz = o / (OW * OW) - OR;
+    const int o343 = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);  // the table's layout
+    s_g[e] = G[size_t(o343) * K + e % KM];
+  }
   // every group iteration runs in all threads of the workgroup (uniform trip count)
   for (int grp = blockIdx.y; pbeg + grp * PP < pend; grp += gridDim.y) {
     __syncthreads();  // the previous group's slot rows are consumed
@@ -208,16 +215,17 @@ __global__ __launch_bounds__(256) void k_cells_accum(CellArgs<T> a, int tlevel, 
       }
 #pragma unroll
       for (int cz = 0; cz < 2; ++cz) {
-        const int dz = bz - 2 - cz;  // in [-3, 3]
+        const int dz = bz - 2 - cz;  // in [-3, 3]; in [-2, 2] for the central planes
         const bool zfar = dz < -1 || dz > 1;
-        const cplx<T>* gz = s_g + (49 * (dz + 3)) * KM + m;
+        const cplx<T>* gz = s_g + (OW * OW * (dz + OR)) * KM + m;
 #pragma unroll
         for (int dy = -3; dy <= 3; ++dy) {
 #pragma unroll
           for (int dx = -3; dx <= 3; ++dx) {
             const bool far_xy = dx < -1 || dx > 1 || dy < -1 || dy > 1;
             if (!far_xy && !zfar) continue;  // the 27 offsets of the near zone
-            const cplx<T> gv = gz[((dx + 3) + 7 * (dy + 3)) * KM];
+            if (CENTRAL && (dx < -2 || dx > 2 || dy < -2 || dy > 2)) continue;  // no central source
+            const cplx<T> gv = gz[((dx + OR) + OW * (dy + OR)) * KM];
 #pragma unroll
             for (int cy = 0; cy < 2; ++cy) {
 #pragma unroll
