@@ -181,9 +181,18 @@ void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp,
 
 // The same over the first *dn values (device memory, at most nmax); tmp must already hold the
 // scratch for nmax (no allocation here, so that it can run between kernels still in flight).
+// Up to kScanDnSingleMax the scan is one workgroup that stops at *dn: a level's cell count is
+// usually far below the host's bound, and one launch replaces the three of the tiled scan.
+constexpr int kScanDnSingleMax = 8 * kScanSingleMax;
+
 static void exclusive_scan_i32_dn(const int* in, int* out, int nmax, const int* dn, int* total,
                                   DevBuf& tmp, hipStream_t s) {
   if (nmax <= 0) return;
+  if (nmax <= kScanDnSingleMax) {
+    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, nmax, dn, total);
+    HPM_LAUNCH_CHECK();
+    return;
+  }
   if (tmp.bytes < scan_tmp_ints(nmax) * sizeof(int)) fail(HPM_ERR_DEVICE, "scan scratch too small");
   scan_rec(in, out, nmax, dn, total, tmp.as<int>(), s);
 }
