@@ -172,7 +172,8 @@ hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x,
  *   L2P + P2P  Eq. (7) and its gradient at each particle plus the near-zone direct sum over
  *         the 27 neighbouring cubes (Sec. 1), combined with compensated addition.
  * Outputs phi, ax, ay, az (device, n elements, input order, caller-allocated) are overwritten.
- * Enqueued on "stream" without host synchronisation and without allocation. For n >= 2^16 the
+ * Enqueued on "stream" without host synchronisation, allocation or memory set, so a caller may
+ * capture it in a HIP graph and replay it for new masses on the same tree. For n >= 2^16 the
  * near-zone sums run on a stream the plan owns, forked from "stream" before the source-to-target
  * step and joined back before the leaf pass, so the call is ordered on "stream" as a whole.
  * Errors: HPM_ERR_INVALID_ARG (NULL pointer), HPM_ERR_DEVICE (launch failure).
@@ -359,7 +360,8 @@ hpm_status hpm_server_stats_get(hpm_server* server, hpm_server_stats* stats);
 
 /*
  * Finishes every queued and running request, then stops the workers and releases the plans
- * (NULL is ignored). Tickets not yet reported are released with it.
+ * (NULL is ignored). Tickets not yet reported are released with it. No other call on the same
+ * server may run concurrently with it or follow it (every poll and wait must have returned).
  */
 void hpm_server_destroy(hpm_server* server);
 
