@@ -85,68 +85,87 @@ struct CellArgs {
   double* m2l_mean;      // [cells]: mean of each target's result, FP32 plans
 };
 
-// one wave per source: a source is a few thousand multiply-adds, so many sources in flight per CU
-// (small workgroups) hide the load and store latency that dominates
-constexpr int kFwdThreads = 64;
+// One wave per source (kFwdSources per workgroup; packing four measured slower than one). Each
+// pass gives every
+// lane whole lines: a lane loads the N_g nonzero samples of its line into registers and forms
+// all the line's outputs with compile-time twiddles (exp(-2 pi i jk / C) as immediates), so no
+// output waits on a chain of table loads. Sums run over the samples in order, as the separable
+// definition reads.
+constexpr int kFwdSources = 1;
+constexpr int kFwdThreads = 64 * kFwdSources;
+
+// out[k] = sum_j v[j] w^{jk}, w = exp(-2 pi i / C), for the K outputs of one line
+template <typename T, int NG, int C, int K, bool REAL_IN>
+__device__ __forceinline__ void line_dft(const cplx<T> (&v)[NG], cplx<T>* out, int stride) {
+  static_for<0, K>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    cplx<T> acc = {T(0), T(0)};
+    static_for<0, NG>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      constexpr T wr = T(cis_cos(long(j) * k, C)), wi = T(-cis_sin(long(j) * k, C));
+      if constexpr (REAL_IN) {
+        acc.re += v[j].re * wr;
+        acc.im += v[j].re * wi;
+      } else {
+        acc = cadd(acc, cmul(v[j], cplx<T>{wr, wi}));
+      }
+    });
+    out[k * stride] = acc;
+  });
+}
 
 template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(kFwdThreads) void k_cells_forward(CellArgs<T> a) {
   using S = CellShape<NG, EXT>;
   constexpr int C = S::C, HC = S::HC, K = S::K, KP = S::KP, M = S::M;
-  __shared__ cplx<T> tw[C];
-  __shared__ T s_g[M];
-  __shared__ cplx<T> s_a1[NG * NG * HC];  // [z][y][kx]
-  __shared__ cplx<T> s_a2[NG * C * HC];   // [z][ky][kx]
-  const int src = blockIdx.x, tid = threadIdx.x;
-  if (src == a.nsources) {  // the zero row that empty block slots read
-    for (int e = tid; e < KP; e += kFwdThreads) a.sspec[size_t(src) * KP + e] = {T(0), T(0)};
-    return;
-  }
-  load_twiddles<T, C>(tw, -1.0);
-  const T* g = a.gridlet + size_t(a.first_cell + src) * M;
-  for (int e = tid; e < M; e += kFwdThreads) s_g[e] = g[e];
-  __syncthreads();
-  for (int e = tid; e < NG * NG * HC; e += kFwdThreads) {
-    const int kx = e % HC, row = e / HC;  // row = z * NG + y
-    cplx<T> acc = {T(0), T(0)};
-    int m = 0;
-#pragma unroll
-    for (int x = 0; x < NG; ++x) {
-      const T v = s_g[row * NG + x];
-      acc.re += v * tw[m].re;
-      acc.im += v * tw[m].im;
-      m += kx;
-      if (m >= C) m -= C;
-    }
-    s_a1[e] = acc;
-  }
-  __syncthreads();
-  for (int e = tid; e < NG * C * HC; e += kFwdThreads) {
-    const int kx = e % HC, ky = (e / HC) % C, z = e / (HC * C);
-    cplx<T> acc = {T(0), T(0)};
-    int m = 0;
-#pragma unroll
-    for (int y = 0; y < NG; ++y) {
-      acc = cadd(acc, cmul(s_a1[(z * NG + y) * HC + kx], tw[m]));
-      m += ky;
-      if (m >= C) m -= C;
-    }
-    s_a2[e] = acc;
-  }
-  __syncthreads();
+  __shared__ T s_gw[kFwdSources][M];
+  __shared__ cplx<T> s_a1w[kFwdSources][NG * NG * HC];  // [z][y][kx]
+  __shared__ cplx<T> s_a2w[kFwdSources][NG * C * HC];   // [z][ky][kx]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int src = blockIdx.x * kFwdSources + wave;
+  // every wave passes every barrier; only waves with a source of their own do its work
+  const bool zero_row = src == a.nsources, work = src < a.nsources;
+  T* s_g = s_gw[wave];
+  cplx<T>* s_a1 = s_a1w[wave];
+  cplx<T>* s_a2 = s_a2w[wave];
   cplx<T>* out = a.sspec + size_t(src) * KP;
-  for (int e = K + tid; e < KP; e += kFwdThreads) out[e] = {T(0), T(0)};
-  for (int e = tid; e < K; e += kFwdThreads) {
-    const int col = e % (C * HC), kz = e / (C * HC);  // col = ky * HC + kx
-    cplx<T> acc = {T(0), T(0)};
-    int m = 0;
+  if (zero_row)  // the zero row that empty block slots read
+    for (int e = lane; e < KP; e += 64) out[e] = {T(0), T(0)};
+  if (work) {
+    const T* g = a.gridlet + size_t(a.first_cell + src) * M;
+    for (int e = lane; e < M; e += 64) s_g[e] = g[e];
+  }
+  __syncthreads();
+  // x: one real row (z, y) per lane, its half spectrum kx <= C/2
+  if (work) {
+    for (int r = lane; r < NG * NG; r += 64) {
+      cplx<T> v[NG];
 #pragma unroll
-    for (int z = 0; z < NG; ++z) {
-      acc = cadd(acc, cmul(s_a2[z * C * HC + col], tw[m]));
-      m += kz;
-      if (m >= C) m -= C;
+      for (int x = 0; x < NG; ++x) v[x] = {s_g[r * NG + x], T(0)};
+      line_dft<T, NG, C, HC, true>(v, s_a1 + r * HC, 1);
     }
-    out[e] = acc;
+  }
+  __syncthreads();
+  // y: one column (z, kx) per lane, all C values of ky
+  if (work) {
+    for (int q = lane; q < NG * HC; q += 64) {
+      const int z = q / HC, kx = q % HC;
+      cplx<T> v[NG];
+#pragma unroll
+      for (int y = 0; y < NG; ++y) v[y] = s_a1[(z * NG + y) * HC + kx];
+      line_dft<T, NG, C, C, false>(v, s_a2 + z * C * HC + kx, HC);
+    }
+  }
+  __syncthreads();
+  // z: one column (ky, kx) per lane, all C values of kz, written to the source's spectrum row
+  if (work) {
+    for (int e = K + lane; e < KP; e += 64) out[e] = {T(0), T(0)};
+    for (int col = lane; col < C * HC; col += 64) {
+      cplx<T> v[NG];
+#pragma unroll
+      for (int z = 0; z < NG; ++z) v[z] = s_a2[z * C * HC + col];
+      line_dft<T, NG, C, C, false>(v, out + col, C * HC);
+    }
   }
 }
 
@@ -368,7 +387,7 @@ static void cells_t(Plan& p, hipStream_t s) {
       p.cell_tgt.bytes < size_t(ntargets) * S::KP * sizeof(cplx<T>) ||
       p.local.bytes < size_t(p.ncells) * S::ML * sizeof(T))
     fail(HPM_ERR_DEVICE, "cell spectra buffers too small");
-  k_cells_forward<T, NG, EXT><<<a.nsources + 1, kFwdThreads, 0, s>>>(a);
+  k_cells_forward<T, NG, EXT><<<(a.nsources + kFwdSources) / kFwdSources, kFwdThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
   using A = AccumShape<T>;
   for (int lp = 1; lp + 1 < p.nlevels; ++lp) {
