@@ -13,7 +13,8 @@ this workload). Inputs are seeded and synthetic and resident in device memory be
 Prints ONE JSON line. Two other workloads run on their own flag, each printing its own line:
 
   --batch   512 independent FP32 solves (N log-uniform in [2^10, 2^18], half uniform cube and
-            half Plummer, N_g 4 or 6) through one hpm_server_run_batch call on a warm server;
+            half Plummer, N_g 4 or 6, the shared-transform route unless --batch-m2l says
+            otherwise) through one hpm_server_run_batch call on a warm server;
   --serve   a Poisson stream of solves (N log-uniform in [2^12, 2^20], uniform, Plummer or
             clustered, force tolerance 1e-2 at N_g = 4 or 1e-4 at N_g = 6, extended gridlets on
             the cell route) at 0.5, 0.7 and 0.9 of
@@ -183,7 +184,7 @@ def batch_bench(args):
         p = request_particles(r).astype(np.float32)
         sets.append(_device_set(torch, p, torch.float32))
         probs.append(hpm.Problem(ng=r["ng"], precision="f32", leaf_capacity=64, max_depth=10,
-                                 softening=1e-3))
+                                 softening=1e-3, m2l=args.batch_m2l))
     torch.cuda.synchronize()
     total = sum(r["n"] for r in reqs)
     print(f"[batch] {len(reqs)} solves, {total} particles on the device", file=sys.stderr,
@@ -217,6 +218,7 @@ def batch_bench(args):
            "dtype": "f32", "data": "synthetic (seeded uniform cubes and Plummer spheres)",
            "config": {"workload": f"{len(reqs)} solves, N log-uniform 2^10..2^18, half uniform "
                                   "half Plummer, N_g 4 or 6, leaf<=64, eps=1e-3",
+                      "m2l": args.batch_m2l,
                       "solves": len(reqs), "particles": total, "slots": args.slots,
                       "ng4_solves": sum(r["ng"] == 4 for r in reqs)},
            "checked": {"solves": len(checked), "identical_to_alone": same,
@@ -345,6 +347,8 @@ def main():
                     help="precision of the --profile run")
     ap.add_argument("--batch", action="store_true", help="the batched workload instead")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-m2l", choices=("grid", "cells", "shared"), default="shared",
+                    help="source-to-target route of the batched solves")
     ap.add_argument("--serve", action="store_true", help="the served workload instead")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-pool", type=int, default=64)
