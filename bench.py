@@ -15,6 +15,8 @@ Prints ONE JSON line. Two other workloads run on their own flag, each printing i
   --batch   512 independent FP32 solves (N log-uniform in [2^10, 2^18], half uniform cube and
             half Plummer, N_g 4 or 6, the shared-transform route unless --batch-m2l says
             otherwise) through one hpm_server_run_batch call on a warm server;
+  --large   the 2^24-particle clustered set (N_g = 4, at most 32 per leaf) on each of the three
+            source-to-target routes;
   --serve   a Poisson stream of solves (N log-uniform in [2^12, 2^20], uniform, Plummer or
             clustered, force tolerance 1e-2 at N_g = 4 or 1e-4 at N_g = 6, extended gridlets on
             the cell route) at 0.5, 0.7 and 0.9 of
@@ -327,6 +329,50 @@ def serve_bench(args):
     return rec
 
 
+def large_bench(args):
+    """The large clustered case: 2^24 particles (32 Plummer spheres on a 10% uniform background),
+    at most 32 per leaf, N_g = 4, FP32, on each source-to-target route: rebuild + evaluate timed
+    over `steps` solves after one untimed solve, force error on 1024 sampled particles against the
+    FP64 direct sum over all particles."""
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import random_subset, workload
+    n = 2 ** 24
+    p = workload("clustered2p24_cap32").astype(np.float32)
+    x, y, z, m = _device_set(torch, p, torch.float32)
+    sub = torch.tensor(random_subset(n, 1024, 4004), device="cuda")
+    _, rx, ry, rz = hpm.direct_sum(x.double(), y.double(), z.double(), m.double(), sub, 1.0, 1e-3)
+    ref = torch.stack([rx, ry, rz], 1)
+    routes = {}
+    for route in ("grid", "shared", "cells"):
+        plan = hpm.Plan(hpm.Problem(ng=4, precision="f32", leaf_capacity=32, max_depth=10,
+                                    softening=1e-3, m2l=route), x, y, z)
+        out = [torch.empty_like(m) for _ in range(4)]
+        plan.execute(m, *out)
+        torch.cuda.synchronize()
+        plan.enable_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.rebuild(x, y, z)
+            plan.execute(m, *out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = plan.stage_times()
+        info = plan.info()
+        routes[route] = {"ms_per_step": round(dt * 1e3, 3), "particles_per_s": round(n / dt, 1),
+                         "force_err_rms": _force_err(torch, out, sub, ref),
+                         "m2l_ms": round(st["m2l"] / max(st["n_exec"], 1), 3),
+                         "tree_ms": round(st["tree"] / max(st["n_build"], 1), 3)}
+        print(f"[large] {route}: {routes[route]['ms_per_step']} ms", file=sys.stderr, flush=True)
+        plan.close()
+    return {"mode": "large", "metric": "particles/s of one solve", "unit": "particles/s",
+            "dtype": "f32", "data": "synthetic (seeded clustered set)", "steps": args.steps,
+            "config": {"workload": "2^24 particles, 32 Plummer spheres on a 10% uniform background, "
+                                   "leaf<=32, depth<=10, N_g=4, eps=1e-3",
+                       "levels": info["n_levels"], "targets": info["n_targets"]},
+            "routes": routes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +392,8 @@ def main():
     ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
                     help="precision of the --profile run")
     ap.add_argument("--batch", action="store_true", help="the batched workload instead")
+    ap.add_argument("--large", action="store_true",
+                    help="the 2^24-particle clustered workload on each route instead")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-m2l", choices=("grid", "cells", "shared"), default="shared",
                     help="source-to-target route of the batched solves")
@@ -360,6 +408,9 @@ def main():
         sys.exit(2)
     if args.batch:
         print(json.dumps(batch_bench(args)))
+        return
+    if args.large:
+        print(json.dumps(large_bench(args)))
         return
     if args.serve:
         print(json.dumps(serve_bench(args)))
