@@ -647,13 +647,14 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_parent(M2LArgs<T> a) {
   }
 }
 
-// Which kernel serves (T, N_g): the whole stage in LDS when it fits; else the z-slab kernel (both
-// precisions; in FP64 one workgroup per CU fits); else the full-grid kernel with a global stage
-// slice per workgroup.
+// Which kernel serves (T, N_g): from N_g = 4 on the z-slab kernel where it fits (both
+// precisions; in FP64 one workgroup per CU fits): at N_g = 4 in FP32 the whole-stage kernel
+// would hold 104 KB of LDS per workgroup, one workgroup per CU. Below N_g = 4 the whole stage
+// in LDS; else the full-grid kernel with a global stage slice per workgroup.
 template <typename T, int NG>
 constexpr int m2l_kind() {
-  if constexpr (M2LShape<T, NG>::lds) return 0;
-  else if constexpr (SlabShape<T, NG>::fits) return 1;
+  if constexpr (NG >= 4 && SlabShape<T, NG>::fits) return 1;
+  else if constexpr (M2LShape<T, NG>::lds) return 0;
   else return 2;
 }
 
