@@ -44,6 +44,8 @@ MIX = [
     ("uniform", 2048, 20, 6, "f32", "grid"),
     ("plummer", 30000, 21, 4, "f32", "grid"),
     ("clustered", 4096, 22, 6, "f64", "grid"),
+    ("plummer", 60000, 23, 6, "f32", "shared"),
+    ("uniform", 12000, 24, 4, "f64", "shared"),
 ]
 
 
