@@ -854,6 +854,15 @@ void build_virtual(Plan& p, hipStream_t s) {
   a.pb = p.cpb.as<int>();
   a.pe = p.cpe.as<int>();
   a.keys = p.keys.as<uint32_t>();
+  if (p.prob.uniform_depth > 0) {
+    // a uniform tree splits every occupied cell above its last level: every leaf is on the last
+    // level, and no block cube lies inside a coarser leaf, so there are no virtual cubes and the
+    // leaf counts follow from the level table (no host round trip)
+    p.nleaves = p.level_off[p.nlevels] - p.level_off[p.nlevels - 1];
+    p.nleaves_lt2 = 0;  // nlevels > 2 here
+    build_block_table(p, a, nt, s);
+    return;
+  }
   p.nchild.reserve(size_t(nt) * 4);
   p.childoff.reserve(size_t(nt) * 4);
   a.counts = p.nchild.as<int>();
