@@ -526,6 +526,18 @@ def main():
                              "m2l_ms": round(stage(rsd, "m2l"), 4), "force_err_rms": ferr(osd)[0]},
               "grid_m2l_ms": {"f32": round(stage(r32, "m2l"), 4), "f64": round(stage(r64, "m2l"), 4)},
               "paper_count_ratio_grid_over_cells": round(0.34 * (pg + 3) / (pg + 1), 3)}
+    # the route autotuner on the same tree (one plan built with the cell spectra, every route
+    # timed on it, the fastest kept)
+    for pr in ("f32", "f64"):
+        q = parts.astype(np.float32 if pr == "f32" else np.float64)
+        dq = torch.float32 if pr == "f32" else torch.float64
+        xq, yq, zq, mq = _device_set(torch, q, dq)
+        tplan = hpm.Plan(hpm.Problem(ng=ng, precision=pr, leaf_capacity=64, max_depth=10,
+                                     softening=1e-3, m2l="shared"), xq, yq, zq)
+        best, per = tplan.autotune(mq, reps=3)
+        routes[f"autotuned_{pr}"] = {"route": best,
+                                     "ms_per_evaluation": {k: round(v, 4) for k, v in per.items()}}
+        tplan.close()
     # the extended target gridlet (Sec. 2.5, N_g + 2 nodes per axis) on the cell route, at this
     # order and at N_g = 4: rate and force error beside the standard gridlet's
     for g in sorted({ng, 4}):

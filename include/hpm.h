@@ -200,6 +200,27 @@ hpm_status hpm_plan_rebuild(hpm_plan* plan, int64_t n, const void* x, const void
 hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on);
 hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int64_t* n_build);
 
+/*
+ * Source-to-target route of the plan's later evaluations (an hpm_m2l_mode). All three routes
+ * compute the same sums (Sec. 2.1, Sec. 2.5); they differ in speed. A plan made with
+ * HPM_M2L_GRID can only use that route, since the others need the cell spectra and their Green
+ * tables; a plan made with HPM_M2L_CELLS or HPM_M2L_SHARED can use all three, except with
+ * extended gridlets (HPM_M2L_CELLS only).
+ * Errors: HPM_ERR_INVALID_ARG (NULL plan, unknown mode), HPM_ERR_UNSUPPORTED (route not built).
+ */
+hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode);
+
+/*
+ * Chooses the route by measurement: for every route the plan can use, one untimed evaluation
+ * and then reps (1..1000) timed ones with masses m (device, n elements), outputs overwritten
+ * (device, as hpm_plan_execute), HIP events on "stream"; keeps the fastest for later
+ * evaluations. *mode (host, may be NULL) receives it, ms (host, 3 doubles, may be NULL) the mean
+ * milliseconds per evaluation of HPM_M2L_GRID, _CELLS and _SHARED (-1 for a route the plan
+ * cannot use). Synchronises "stream". On failure the plan keeps its previous route.
+ */
+hpm_status hpm_plan_autotune(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,
+                             void* az, int32_t reps, void* stream, int32_t* mode, double* ms);
+
 /* Releases the plan and all its device memory (NULL is ignored). Synchronises the device. */
 void hpm_plan_destroy(hpm_plan* plan);
 

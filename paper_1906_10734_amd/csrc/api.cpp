@@ -99,6 +99,7 @@ void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const
   p.NL = pr->ng + 2 * p.ext;
   p.ML = p.NL * p.NL * p.NL;
   p.elem = (p.prec == HPM_F32) ? 4 : 8;
+  p.route = pr->m2l_mode;
   HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
                         hipHostMallocMapped | hipHostMallocCoherent));
   HPM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&p.dbox), p.hbox, 0));
@@ -154,8 +155,8 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
     launch_p2p(p, p.side);
     HPM_HIP(hipEventRecord(p.join_ev, p.side));
   }
-  if (p.prob.m2l_mode == HPM_M2L_CELLS) launch_m2l_cells(p, s);
-  else if (p.prob.m2l_mode == HPM_M2L_SHARED) launch_m2l_shared(p, s);
+  if (p.route == HPM_M2L_CELLS) launch_m2l_cells(p, s);
+  else if (p.route == HPM_M2L_SHARED) launch_m2l_shared(p, s);
   else launch_m2l(p, s);
   if (ev) HPM_HIP(hipEventRecord(ev[3], s));
   for (int l = 2; l < p.nlevels; ++l) launch_l2l(p, l, s);  // level 2: re-centring only
@@ -281,6 +282,73 @@ hpm_status hpm_plan_execute(hpm_plan* plan, const void* m, void* phi, void* ax, 
     if (!m || !phi || !ax || !ay || !az) fail(HPM_ERR_INVALID_ARG, "array pointer is NULL");
     if (!plan->p.valid) fail(HPM_ERR_INVALID_ARG, "plan has no valid tree (a rebuild failed)");
     execute_plan(plan->p, m, phi, ax, ay, az, (hipStream_t)stream);
+  });
+}
+
+// routes a plan can evaluate with: its own; all three when it was made with the cell spectra and
+// standard gridlets (the cell route alone builds the extended ones)
+static bool route_allowed(const Plan& p, int32_t mode) {
+  if (mode != HPM_M2L_GRID && mode != HPM_M2L_CELLS && mode != HPM_M2L_SHARED) return false;
+  if (p.prob.m2l_mode == HPM_M2L_GRID) return mode == HPM_M2L_GRID;
+  if (p.ext) return mode == HPM_M2L_CELLS;
+  return true;
+}
+
+hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (m2l_mode != HPM_M2L_GRID && m2l_mode != HPM_M2L_CELLS && m2l_mode != HPM_M2L_SHARED)
+      fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID, HPM_M2L_CELLS or HPM_M2L_SHARED");
+    if (!route_allowed(plan->p, m2l_mode))
+      fail(HPM_ERR_UNSUPPORTED, "the plan was not built for this source-to-target route");
+    plan->p.route = m2l_mode;
+  });
+}
+
+hpm_status hpm_plan_autotune(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,
+                             void* az, int32_t reps, void* stream, int32_t* mode, double* ms) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (!m || !phi || !ax || !ay || !az) fail(HPM_ERR_INVALID_ARG, "array pointer is NULL");
+    if (reps < 1 || reps > 1000) fail(HPM_ERR_INVALID_ARG, "reps must be 1..1000");
+    Plan& p = plan->p;
+    if (!p.valid) fail(HPM_ERR_INVALID_ARG, "plan has no valid tree (a rebuild failed)");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HPM_HIP(hipEventCreate(&e0));
+    HPM_HIP(hipEventCreate(&e1));
+    const int32_t first = p.route;
+    int32_t best = first;
+    double best_ms = -1.0;
+    double per[3] = {-1.0, -1.0, -1.0};
+    hpm_status st = guarded([&] {
+      for (int32_t r = HPM_M2L_GRID; r <= HPM_M2L_SHARED; ++r) {
+        if (!route_allowed(p, r)) continue;
+        p.route = r;
+        execute_plan(p, m, phi, ax, ay, az, s);  // untimed: first use of the route's kernels
+        HPM_HIP(hipEventRecord(e0, s));
+        for (int k = 0; k < reps; ++k) execute_plan(p, m, phi, ax, ay, az, s);
+        HPM_HIP(hipEventRecord(e1, s));
+        HPM_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        HPM_HIP(hipEventElapsedTime(&t, e0, e1));
+        per[r] = double(t) / reps;
+        if (best_ms < 0.0 || per[r] < best_ms) {
+          best_ms = per[r];
+          best = r;
+        }
+      }
+    });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HPM_OK) {
+      p.route = first;
+      fail(st, hpm_last_error());
+    }
+    p.route = best;
+    if (mode) *mode = best;
+    if (ms)
+      for (int r = 0; r < 3; ++r) ms[r] = per[r];
   });
 }
 

@@ -122,6 +122,7 @@ struct Plan {
   int ext = 0;      // 1: extended target gridlets (N_g + 2 nodes per axis)
   int NL = 4;       // target gridlet nodes per axis, N_g + 2 ext
   int ML = 64;      // target gridlet size NL^3 (local potentials)
+  int route = HPM_M2L_GRID;  // source-to-target route of the evaluations (an hpm_m2l_mode)
   int64_t n = 0;
   bool valid = false;  // a tree is built and consistent with the buffers
   int depth = 0;  // Morton key depth D

@@ -88,6 +88,9 @@ SIGNATURES = {
     "hpm_plan_copy_local_offsets": (_i32, [_vp, _i32, _vp]),
     "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _i32, _d, _vp,
                               _vp, _vp, _vp, _vp]),
+    "hpm_plan_set_route": (_i32, [_vp, _i32]),
+    "hpm_plan_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_i32),
+                                 ctypes.POINTER(_d)]),
     "hpm_plan_bytes_estimate": (_i32, [ctypes.POINTER(HpmProblem), _i64,
                                        ctypes.POINTER(_i64)]),
     "hpm_server_create": (_i32, [ctypes.POINTER(HpmServerConfig), ctypes.POINTER(_vp)]),
@@ -231,6 +234,21 @@ class Plan:
         _check(_lib.hpm_plan_execute(self._h, _dev(m, dt, n, "m"), _dev(phi, dt, n, "phi"),
                                      _dev(ax, dt, n, "ax"), _dev(ay, dt, n, "ay"),
                                      _dev(az, dt, n, "az"), _stream(stream)), "hpm_plan_execute")
+
+    def set_route(self, route: str):
+        """Source-to-target route of later evaluations: "grid", "cells" or "shared"."""
+        _check(_lib.hpm_plan_set_route(self._h, HPM_M2L_MODES[route]), "hpm_plan_set_route")
+
+    def autotune(self, m, reps: int = 3, stream=None):
+        """Times every route the plan can use and keeps the fastest: (route, {route: ms})."""
+        dt, n = self.problem.dtype, self.n
+        out = [torch.empty(n, dtype=dt, device=m.device) for _ in range(4)]
+        mode, ms = _i32(), (_d * 3)()
+        _check(_lib.hpm_plan_autotune(self._h, _dev(m, dt, n, "m"), *(o.data_ptr() for o in out),
+                                      int(reps), _stream(stream), ctypes.byref(mode), ms),
+               "hpm_plan_autotune")
+        names = {v: k for k, v in HPM_M2L_MODES.items()}
+        return names[mode.value], {names[r]: ms[r] for r in range(3) if ms[r] >= 0}
 
     def __call__(self, m, stream=None):
         out = [torch.empty(self.n, dtype=self.problem.dtype, device=m.device) for _ in range(4)]

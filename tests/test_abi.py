@@ -93,6 +93,8 @@ def test_null_and_size_checks():
     assert lib.hpm_direct_sum(0, 16, dummy, dummy, dummy, dummy, 1, dummy, 1.0, 0.0, 1, 0.0, dummy,
                               dummy, dummy, dummy, None) == 1
     assert lib.hpm_status_string(2) == b"HPM_ERR_OUT_OF_BOX"
+    assert lib.hpm_plan_set_route(None, 0) == 1
+    assert lib.hpm_plan_autotune(None, dummy, dummy, dummy, dummy, dummy, 1, None, None, None) == 1
     lib.hpm_plan_destroy(None)
 
 

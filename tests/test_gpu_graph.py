@@ -78,3 +78,4 @@ def test_captured_evaluation_replays_equal_eager(kind, n, ng, prec, kw, route):
     log(f"   eager {1e3 * (t1 - t0) / reps:.3f} ms, replay {1e3 * (t2 - t1) / reps:.3f} ms per evaluation")
     del g
     plan.close()
+
