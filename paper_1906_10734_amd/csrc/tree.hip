@@ -613,9 +613,12 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   auto grid = [](int64_t work, int t) {
     return int(std::max<int64_t>(1, std::min<int64_t>((work + t - 1) / t, 4096)));
   };
-  auto enqueue = [&](int from, bool resume_emit) {
+  // levels from..to; the kernels of a level with no cells return at once, but each launch still
+  // costs, so adaptive trees are enqueued to a depth their size suggests first, and the rest
+  // only if the table read back says the tree goes deeper
+  auto enqueue = [&](int from, bool resume_emit, int to) {
     const CellArrays c = cells_of(p);
-    for (int l = from; l <= D; ++l) {
+    for (int l = from; l <= to; ++l) {
       // cells of level l: at most 8^l, n (nonempty) and the capacity
       const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
       if (!(l == from && resume_emit)) {
@@ -632,7 +635,15 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     }
   };
   const int* hl = p.hbox + Plan::kBoxLev;
-  enqueue(0, false);
+  int to = D;
+  if (!uniform) {
+    // log8(n / capacity) levels hold the leaves of an even density; Plummer-like concentration
+    // adds a few (2^18 Plummer particles, 64 per leaf: 8 levels past the root)
+    int est = 0;
+    for (int64_t cells = 1; cells * std::max(1, pr.leaf_capacity) < int64_t(n); cells *= 8) ++est;
+    to = std::min(D, est + 5);
+  }
+  enqueue(0, false, to);
   for (bool first = true;; first = false) {
     HPM_HIP(hipMemcpyAsync(p.hbox + Plan::kBoxLev, lev, kLevWords * sizeof(int),
                            hipMemcpyDeviceToHost, s));
@@ -643,7 +654,15 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
         fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
     }
     const int ov = hl[kLevOverflow];
-    if (ov < 0) break;
+    if (ov < 0) {
+      if (to < D && hl[kLevCnt + to + 1] > 0) {  // the tree goes deeper than enqueued
+        const int from = to + 1;
+        to = D;
+        enqueue(from, false, to);
+        continue;
+      }
+      break;
+    }
     // the children of level ov did not fit: keep the levels up to ov (and ov's split), grow,
     // and emit from level ov on
     const int64_t keep = int64_t(hl[kLevOff + ov]) + hl[kLevCnt + ov];
@@ -652,7 +671,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     level_scratch(hl[kLevCnt + ov]);
     k_lev_resume<<<1, 1, 0, s>>>(lev);
     HPM_LAUNCH_CHECK();
-    enqueue(ov, true);
+    enqueue(ov, true, to);
   }
   p.nlevels = 0;
   for (int l = 0; l <= D; ++l) {
