@@ -107,7 +107,7 @@ def _random_target_setup(ng, level, seed):
     return h
 
 
-@pytest.mark.parametrize("ng", [2, 3, 4])
+@pytest.mark.parametrize("ng", [2, 3, 4, 6, 8])
 def test_fft_source_to_target_equals_direct_gridlet_sum(ng):
     # Sec. 2.1: one (8 N_g)^3 zero-padded FFT with the exact lattice Green function gives the
     # same target potentials as the 189 cube-by-cube sums, to rounding.
