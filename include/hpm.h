@@ -86,10 +86,12 @@ typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1, HPM_M2L_SHARED = 2 } hpm_m2l
 
 /*
  * Problem description.
- *   ng             gridlet points per axis (Sec. 2): 2, 3, 4 or 6 (the FFT edge 8 N_g must
- *                  factor into 2s and 3s). N_g = 8 is built but currently returns
- *                  HPM_ERR_UNSUPPORTED (switched off after a device fault at 2^18 particles).
- *                  Other values give HPM_ERR_UNSUPPORTED.
+ *   ng             gridlet points per axis (Sec. 2): 2, 3, 4, 6 or 8 (the FFT edge 8 N_g must
+ *                  factor into 2s and 3s). N_g = 8 accepts at most 65536 particles (a plan for
+ *                  more, or a rebuild or server request with more, returns HPM_ERR_UNSUPPORTED:
+ *                  a 2^18-particle solve at N_g = 8 faulted in an earlier version of the library
+ *                  and no cause has been shown). The padded-grid route only (the cell-by-cell
+ *                  and shared routes go up to N_g = 6). Other values give HPM_ERR_UNSUPPORTED.
  *   precision      HPM_F32 or HPM_F64: dtype of all particle/output arrays and of the arithmetic
  *                  of the path. Constant tables (fit matrix, child-to-parent matrices, Green
  *                  function transforms) are always built in double and rounded once.

@@ -32,9 +32,6 @@ void check_problem(const hpm_problem* pr) {
   if (ng < 1 || ng > 16) fail(HPM_ERR_INVALID_ARG, "ng out of range");
   if (!(ng == 2 || ng == 3 || ng == 4 || ng == 6 || ng == 8))
     fail(HPM_ERR_UNSUPPORTED, "ng must be one of 2, 3, 4, 6, 8");
-  // N_g = 8 is switched off: a solve of a 2^18-particle Plummer set at N_g = 8 in FP32 ended
-  // with a device memory fault whose cause has not been found yet.
-  if (ng == 8) fail(HPM_ERR_UNSUPPORTED, "ng = 8 is disabled (unresolved device fault)");
   if (!(std::isfinite(pr->box_size) && pr->box_size > 0.0)) fail(HPM_ERR_INVALID_ARG, "box_size must be > 0");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(pr->box_lo[k])) fail(HPM_ERR_INVALID_ARG, "box_lo must be finite");
@@ -48,11 +45,25 @@ void check_problem(const hpm_problem* pr) {
   if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
   if (pr->extended && pr->m2l_mode != HPM_M2L_CELLS)
     fail(HPM_ERR_UNSUPPORTED, "extended gridlets are built on the cell-by-cell route only");
+  if (ng == 8 && pr->m2l_mode != HPM_M2L_GRID)
+    fail(HPM_ERR_UNSUPPORTED, "ng = 8 is built on the padded-grid route only");
   if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
   if (pr->uniform_depth == 0) {
     if (pr->leaf_capacity < 1) fail(HPM_ERR_INVALID_ARG, "leaf_capacity must be >= 1");
     if (pr->max_depth < 1 || pr->max_depth > 10) fail(HPM_ERR_INVALID_ARG, "max_depth must be 1..10");
   }
+}
+
+void check_size(const hpm_problem* pr, int64_t n) {
+  if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+  // N_g = 8 runs on sets of at most kNg8MaxParticles. A 2^18-particle FP32 solve at N_g = 8 ended
+  // in a device memory fault in an earlier version of the library (whose source-to-target kernel
+  // kept its line buffer in device memory); a CPU emulation of that version and of this one on
+  // the same input found every access in bounds, so no cause is shown and the larger sizes stay
+  // off.
+  if (pr->ng == 8 && n > kNg8MaxParticles)
+    fail(HPM_ERR_UNSUPPORTED, "ng = 8 is limited to 65536 particles (a larger solve faulted in an "
+                              "earlier version; cause not shown)");
 }
 
 void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z, hipStream_t s) {
@@ -110,7 +121,6 @@ void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const
   build_tables(p, depth + 1, s);
   size_t slot_bytes = 0;
   p.m2l_slots = m2l_workspace_slots(p.prec, p.ng, &slot_bytes);
-  if (slot_bytes) p.m2l_work.reserve(slot_bytes * p.m2l_slots);
   rebuild_plan(p, n, x, y, z, s);
 }
 
@@ -172,7 +182,7 @@ size_t Plan::device_bytes() const {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
       &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vids, &vtmp, &blocks, &dlevel, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
-      &item_off, &items, &partial, &pairs, &leaf_of, &m2l_work, &cell_src, &cell_tgt, &cell_plist,
+      &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
       &cell_pflag, &cell_ppos, &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
       &tmp_keys, &tmp_vals, &hist, &scan_tmp, &bounds, &nchild, &childoff};
   size_t total = 0;
@@ -208,9 +218,6 @@ size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
     const size_t spec = cell_modes(int(ng), pr.extended) * 2 * s;
     b += (2 * c + 1) * spec + levels * 343 * spec + 3 * 4 * c;
   }
-  size_t slot_bytes = 0;
-  const int slots = m2l_workspace_slots(pr.precision, pr.ng, &slot_bytes);
-  b += slot_bytes * size_t(slots);
   return b + (size_t(1) << 20);
 }
 
@@ -262,7 +269,7 @@ hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x,
   hpm_status st = guarded([&] {
     if (!out) fail(HPM_ERR_INVALID_ARG, "out is NULL");
     check_problem(problem);
-    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    check_size(problem, n);
     if (!x || !y || !z) fail(HPM_ERR_INVALID_ARG, "position pointer is NULL");
     pl = new hpm_plan_s();
     create_plan(pl->p, problem, n, x, y, z, (hipStream_t)stream);
@@ -356,7 +363,7 @@ hpm_status hpm_plan_rebuild(hpm_plan* plan, int64_t n, const void* x, const void
                             const void* z, void* stream) {
   return guarded([&] {
     if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
-    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    check_size(&plan->p.prob, n);
     if (!x || !y || !z) fail(HPM_ERR_INVALID_ARG, "position pointer is NULL");
     rebuild_plan(plan->p, n, x, y, z, (hipStream_t)stream);
   });
@@ -523,7 +530,7 @@ hpm_status hpm_plan_bytes_estimate(const hpm_problem* problem, int64_t n, int64_
   return guarded([&] {
     if (!bytes) fail(HPM_ERR_INVALID_ARG, "bytes is NULL");
     check_problem(problem);
-    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    check_size(problem, n);
     *bytes = int64_t(plan_bytes_estimate(*problem, n));
   });
 }

@@ -164,8 +164,7 @@ struct Plan {
   DevBuf leaf_of;  // [n] leaf list index of each sorted particle
   int64_t n_items = 0;
   int64_t p2p_pairs = 0;
-  DevBuf m2l_work;
-  int m2l_slots = 0;
+  int m2l_slots = 0;  // workgroups of a source-to-target launch
   // cell-by-cell route: source spectra [cells of levels >= 2, then virtual cubes][modes] and the
   // accumulated target spectra [cells of levels >= 2][modes]
   DevBuf cell_src, cell_tgt;
@@ -207,8 +206,10 @@ struct Plan {
 };
 
 // ---- api.cpp ------------------------------------------------------------------------------------
-// host checks of a problem description (throws HpmError)
+// host checks of a problem description and of a particle count for it (throw HpmError)
+constexpr int64_t kNg8MaxParticles = int64_t(1) << 16;
 void check_problem(const hpm_problem* pr);
+void check_size(const hpm_problem* pr, int64_t n);
 // tables, streams and the first tree of a plan; the tree for new positions; one evaluation.
 // Plans are independent of each other: distinct plans may be used from distinct host threads.
 void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const void* y,
@@ -243,6 +244,7 @@ void launch_m2l(Plan& p, hipStream_t s);
 // the transform shared by the children of each split parent (outer cubes of its block); writes
 // each child's (mean, zero-mean gridlet)
 void launch_m2l_parents(Plan& p, hipStream_t s);
+// workgroups of a source-to-target launch (*bytes_per_slot: device workspace per workgroup, 0)
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 
 // ---- m2l_cells.hip -------------------------------------------------------------------------------

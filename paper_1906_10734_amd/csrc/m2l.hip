@@ -17,11 +17,13 @@
 //       inverse z FFT, the N_g target z values kept
 //   y^-1 : columns (kx, z' < N_g), the N_g target y values kept
 //   x^-1 : rows (y', z'), Hermitian half spectrum -> the N_g target x values
-// The line buffer ("stage", layout [z < 6N_g][y < n][kx <= n/2] complex) lives in LDS when it
-// fits, else in a per-workgroup slice of global memory. Cubes of the interaction zone that are
+// The line buffer ("stage", layout [z < 6N_g][y < n][kx <= n/2] complex) lives in LDS; this
+// kernel serves N_g <= 3, the z-slab kernel below the larger orders. Cubes of the interaction zone that are
 // not cells of the tree but lie inside a coarser leaf ("virtual" cubes) have their effective
 // masses fitted once per solve, beside the leaves'; they are found here by their cube id.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "dev_common.h"
 #include "fft.h"
@@ -56,7 +58,6 @@ struct M2LArgs {
   double* m2l_mean;  // z-slab kernel: mean of each target's result (the gridlet part is zero-mean)
   const T* ghat;
   const T* gxy;
-  cplx<T>* work;
   double lo0, lo1, lo2, size;
   // per-parent kernel: the split parents (cell ids) and every cell's 8 children (or -1)
   const int* plist;
@@ -173,19 +174,56 @@ __device__ __forceinline__ void xpass_row(const M2LArgs<T>& a, int yr, int zr, c
   });
 }
 
+// The same half spectrum split over two threads by the parity Q of k (decimation in frequency of
+// the n/2-point transform: its even outputs are the n/4-point transform of z_j + z_{j+n/4}, its odd
+// ones that of (z_j - z_{j+n/4}) e^{-2 pi i j / (n/2)}; X_k needs Z_k and Z_{n/2-k}, both of parity
+// Q). The thread writes X_k for k = Q, Q + 2, ... <= n/2 into row[k].
+template <typename T, int NG, int Q>
+__device__ __forceinline__ void xpass_row_half(const M2LArgs<T>& a, int yr, int zr, const int* s_src,
+                                               cplx<T>* row) {
+  constexpr int n = 8 * NG, h = n / 2, hh = h / 2, M = NG * NG * NG, W = 6 * NG;
+  T x[n];
+#pragma unroll
+  for (int j = 0; j < n; ++j) x[j] = T(0);
+  const int bz = zr / NG, kz = zr % NG, by = yr / NG, jy = yr % NG;
+#pragma unroll
+  for (int bx = 0; bx < 6; ++bx) {
+    const int src = s_src[bx + 6 * (by + 6 * bz)];
+    if (src >= 0) {
+      const T* gsrc = a.gridlet + size_t(src) * M + (kz * NG + jy) * NG;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) x[bx * NG + i] = gsrc[i];
+    }
+  }
+  cplx<T> u[hh], Zq[hh];
+  static_for<0, hh>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const cplx<T> z0 = {x[2 * j], x[2 * j + 1]};
+    const cplx<T> z1 = (2 * j + h < W) ? cplx<T>{x[2 * j + h], x[2 * j + h + 1]} : cplx<T>{T(0), T(0)};
+    if constexpr (Q == 0) u[j] = cadd(z0, z1);
+    else u[j] = twiddle<j, h, -1>(csub(z0, z1));
+  });
+  fft<hh, -1>(u, Zq);  // Zq[kk] = Z[2 kk + Q]
+  static_for<0, hh + 1>([&](auto kc) {
+    constexpr int k = 2 * decltype(kc)::value + Q;
+    if constexpr (k <= h) {
+      const cplx<T> zk = Zq[(k % h) / 2], zc = Zq[((h - k) % h) / 2];
+      const cplx<T> e = {T(0.5) * (zk.re + zc.re), T(0.5) * (zk.im - zc.im)};
+      const cplx<T> o = {T(0.5) * (zk.im + zc.im), T(0.5) * (zc.re - zk.re)};
+      const cplx<T> wo = twiddle<k, n, -1>(o);
+      row[k] = {e.re + wo.re, e.im + wo.im};
+    }
+  });
+}
+
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs<T> a) {
   using S = M2LShape<T, NG>;
   constexpr int n = S::n, H = S::H, W = S::W, M = S::M;
   __shared__ int s_src[216];
   __shared__ int s_off[kMaxLevels + 1];
-  cplx<T>* stage;
-  if constexpr (S::lds) {
-    __shared__ cplx<T> s_stage[S::elems];
-    stage = s_stage;
-  } else {
-    stage = a.work + size_t(blockIdx.x) * S::elems;
-  }
+  static_assert(S::lds, "the whole-grid kernel keeps its stage in LDS");
+  __shared__ cplx<T> stage[S::elems];
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
 
@@ -322,59 +360,128 @@ template <typename T, int NG>
 struct SlabShape {
   static constexpr int n = 8 * NG, H = n / 2 + 1, W = 6 * NG, M = NG * NG * NG;
   static constexpr int NT = kSlabThreads;
-  static constexpr int ZB = kSlabLayers * NG;  // source z rows per slab
+  // At N_g = 8 the inverse y transform is a pruned direct sum in double (FP32 rounding of the
+  // inverse transforms would dominate the gradient of a degree-7 interpolant), and its output
+  // buffer in double leaves room for half a block layer per slab. FP64 at N_g = 8 also cannot
+  // hold the accumulators of all N_g target planes (288 registers per thread): it streams two
+  // source rows per slab, forms the target planes in two passes of N_g / 2, and splits each x
+  // line over two threads and each forward y line over four.
+  static constexpr bool wide = NG >= 8;
+  static constexpr bool narrow = wide && sizeof(T) == 8;
+  static constexpr int ZB = wide ? (narrow ? 2 : NG / 2) : kSlabLayers * NG;  // source rows per slab
+  static constexpr int ZW = narrow ? NG / 2 : NG;           // target z planes per pass
+  static constexpr int YS = narrow ? 4 : 1;                 // threads per forward y line
+  static constexpr int XS = narrow ? 2 : 1;                 // threads per x line
+  static constexpr int ZG = ZB < ZW ? ZB : ZW;              // planes per inverse-y group
+  using RedT = typename std::conditional<wide, double, T>::type;  // inverse-y output
   static constexpr int D = 4 * NG;          // z offsets |Z - z| < 4 N_g
   static constexpr int ENT = n * H;         // (ky, kx) entries of a plane
   static constexpr int PER = (ENT + NT - 1) / NT;
-  static constexpr int NJ = NG + ZB - 1;    // distinct offsets Z - z within one slab
+  static constexpr int NJ = ZW + ZB - 1;    // distinct offsets Z - z within one slab and pass
   static constexpr size_t slab_bytes = size_t(ZB) * n * H * sizeof(cplx<T>);
   static constexpr size_t green_bytes = size_t(D) * H * H * sizeof(T);
-  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<double>) + size_t(M) * 8 +
-                                      size_t(n) * sizeof(cplx<double>);
+  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<RedT>) + size_t(M) * 8 +
+                                      size_t(n) * sizeof(cplx<double>) + 2048;
   static constexpr bool green_lds =
-      kSlabGreenLds && slab_bytes + red_bytes + green_bytes <= 150 * 1024;
-  static constexpr bool fits = slab_bytes + red_bytes <= 150 * 1024;
+      kSlabGreenLds && slab_bytes + red_bytes + green_bytes <= 160 * 1024;
+  static constexpr bool fits = slab_bytes + red_bytes <= 160 * 1024;
 };
 
 // The slab loop of the z-slab scheme: every source z row of the 6 N_g block (the cubes of s_src)
-// through the x and y transforms in LDS and into the real-space z sum (pr, pi) at the N_g target
-// z values Zt .. Zt + N_g - 1. Called by all threads of the workgroup; the accumulators are
-// per thread, entry e = tid + NT r.
+// through the x and y transforms in LDS and into the real-space z sum (pr, pi) at the ZW target
+// z values Zt .. Zt + ZW - 1. Called by all threads of the workgroup; the accumulators are
+// per thread, entry e = tid + NT r. tw holds e^{+2 pi i m / n}, m < n.
 template <typename T, int NG>
 __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, cplx<T>* slab,
-                                         const T* gtab, int Zt,
-                                         T (&pr)[SlabShape<T, NG>::PER][NG],
-                                         T (&pi)[SlabShape<T, NG>::PER][NG]) {
+                                         const T* gtab, int Zt, const cplx<double>* tw,
+                                         T (&pr)[SlabShape<T, NG>::PER][SlabShape<T, NG>::ZW],
+                                         T (&pi)[SlabShape<T, NG>::PER][SlabShape<T, NG>::ZW]) {
   using S = SlabShape<T, NG>;
-  constexpr int n = S::n, H = S::H, W = S::W, NT = S::NT, ZB = S::ZB, PER = S::PER, NJ = S::NJ,
-                ENT = S::ENT;
+  constexpr int n = S::n, H = S::H, W = S::W, NT = S::NT, ZB = S::ZB, ZW = S::ZW, YS = S::YS,
+                PER = S::PER, NJ = S::NJ, ENT = S::ENT;
   const int tid = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < PER; ++r)
 #pragma unroll
-    for (int zz = 0; zz < NG; ++zz) pr[r][zz] = pi[r][zz] = T(0);
+    for (int zz = 0; zz < ZW; ++zz) pr[r][zz] = pi[r][zz] = T(0);
 
   for (int z0 = 0; z0 < W; z0 += ZB) {
-    // x: rows (zb, y) of the slab, y fastest, one real row per thread
-    for (int w = tid; w < ZB * W; w += NT) {
-      const int zb = w / W, yr = w % W;
-      cplx<T> X[H];
-      xpass_row<T, NG>(a, yr, z0 + zb, s_src, X);
-      cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
+    if constexpr (S::XS == 1) {
+      // x: rows (zb, y) of the slab, y fastest, one real row per thread
+      for (int w = tid; w < ZB * W; w += NT) {
+        const int zb = w / W, yr = w % W;
+        cplx<T> X[H];
+        xpass_row<T, NG>(a, yr, z0 + zb, s_src, X);
+        cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
 #pragma unroll
-      for (int k = 0; k < H; ++k) row[k] = X[k];
+        for (int k = 0; k < H; ++k) row[k] = X[k];
+      }
+    } else {
+      // x: two threads per row, one per parity of the output frequency
+      for (int w = tid; w < ZB * W * 2; w += NT) {
+        const int q = w & 1, r = w >> 1;
+        const int zb = r / W, yr = r % W;
+        cplx<T>* row = slab + (size_t(zb) * n + yr) * H;
+        if (q == 0) xpass_row_half<T, NG, 0>(a, yr, z0 + zb, s_src, row);
+        else xpass_row_half<T, NG, 1>(a, yr, z0 + zb, s_src, row);
+      }
     }
     __syncthreads();
-    // y: columns (zb, kx); rows y >= 6 N_g are zero
-    for (int w = tid; w < ZB * H; w += NT) {
-      const int kx = w % H, zb = w / H;
-      cplx<T>* col = slab + size_t(zb) * n * H + kx;
-      cplx<T> in[n], out[n];
+    if constexpr (YS == 1) {
+      // y: columns (zb, kx); rows y >= 6 N_g are zero
+      for (int w = tid; w < ZB * H; w += NT) {
+        const int kx = w % H, zb = w / H;
+        cplx<T>* col = slab + size_t(zb) * n * H + kx;
+        cplx<T> in[n], out[n];
 #pragma unroll
-      for (int y = 0; y < n; ++y) in[y] = (y < W) ? col[size_t(y) * H] : cplx<T>{T(0), T(0)};
-      fft<n, -1>(in, out);
+        for (int y = 0; y < n; ++y) in[y] = (y < W) ? col[size_t(y) * H] : cplx<T>{T(0), T(0)};
+        fft<n, -1>(in, out);
 #pragma unroll
-      for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
+        for (int y = 0; y < n; ++y) col[size_t(y) * H] = out[y];
+      }
+    } else {
+      // y split over YS threads per column (decimation in frequency): thread q transforms
+      //   u_j = e^{-2 pi i q j / n} sum_r x_{j + r m} e^{-2 pi i q r / YS},  j < m = n / YS,
+      // whose m-point transform is the column's outputs ky = YS k + q. All threads read their
+      // inputs before any output is written back in place.
+      static_assert(YS == 4, "forward y split");
+      constexpr int m = n / YS, TASKS = ZB * H * YS;
+      for (int w0 = 0; w0 < TASKS; w0 += NT) {
+        const int w = w0 + tid;
+        const bool live = w < TASKS;
+        const int q = w % YS, c = w / YS;
+        const int kx = c % H, zb = c / H;
+        cplx<T>* col = slab + size_t(zb) * n * H + kx;
+        cplx<T> u[m], out[m];
+        if (live) {
+#pragma unroll
+          for (int j = 0; j < m; ++j) {
+            cplx<T> acc = {T(0), T(0)};
+#pragma unroll
+            for (int r = 0; r < YS; ++r) {
+              if (j + r * m < W) {
+                const cplx<T> v = col[size_t(j + r * m) * H];
+                // times (-i)^(q r)
+                switch ((q * r) & 3) {
+                  case 0: acc = cadd(acc, v); break;
+                  case 1: acc = cadd(acc, cplx<T>{v.im, -v.re}); break;
+                  case 2: acc = csub(acc, v); break;
+                  default: acc = cadd(acc, cplx<T>{-v.im, v.re}); break;
+                }
+              }
+            }
+            const cplx<double> t = tw[(q * j) % n];
+            u[j] = cmul(acc, cplx<T>{T(t.re), T(-t.im)});
+          }
+          fft<m, -1>(u, out);
+        }
+        __syncthreads();
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < m; ++k) col[size_t(YS * k + q) * H] = out[k];
+        }
+        __syncthreads();
+      }
     }
     __syncthreads();
     // z in real space: P(Z) += sum_zb Gxy(|Zt + Z - z0 - zb|) S(zb) for this slab, the slab's
@@ -395,7 +502,7 @@ __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, 
 #pragma unroll
         for (int zb = 0; zb < ZB; ++zb) sv[zb] = slab[(size_t(zb) * n + ky) * H + kx];
 #pragma unroll
-        for (int zz = 0; zz < NG; ++zz) {
+        for (int zz = 0; zz < ZW; ++zz) {
           T ar = g[zz + ZB - 1] * sv[0].re, ai = g[zz + ZB - 1] * sv[0].im;
 #pragma unroll
           for (int zb = 1; zb < ZB; ++zb) {
@@ -415,14 +522,14 @@ __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, 
 template <typename T, int NG>
 __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   using S = SlabShape<T, NG>;
-  constexpr int n = S::n, H = S::H, W = S::W, M = S::M, NT = S::NT, ZB = S::ZB, D = S::D,
-                PER = S::PER, NJ = S::NJ, ENT = S::ENT;
+  constexpr int n = S::n, H = S::H, M = S::M, NT = S::NT, D = S::D, PER = S::PER, ENT = S::ENT,
+                ZW = S::ZW, ZG = S::ZG;
   static_assert(S::fits, "slab buffers exceed the LDS budget");
-  static_assert(W % ZB == 0 && W % 2 == 0, "slab shape");
+  static_assert(S::W % S::ZB == 0 && S::W % 2 == 0 && NG % ZW == 0 && ZW % ZG == 0, "slab shape");
   __shared__ int s_src[216];
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ __align__(16) cplx<T> slab[ZB * n * H];  // [zb][ky (y before the y pass)][kx]
-  __shared__ cplx<double> red[NG * NG * H];            // after y^-1: [Z][Y][kx]
+  __shared__ __align__(16) cplx<T> slab[S::ZB * n * H];  // [zb][ky (y before the y pass)][kx]
+  __shared__ cplx<typename S::RedT> red[NG * NG * H];    // after y^-1: [Z][Y][kx]
   __shared__ double s_out[M];
   __shared__ double s_red[NT / 64];
   __shared__ cplx<double> s_tw[n];  // e^{+2 pi i m / n}
@@ -455,49 +562,75 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     const T* gtab = S::green_lds ? s_green : gtab_g;
     const int Zt = (2 + t.cz) * NG;
 
-    T pr[PER][NG], pi[PER][NG];
-    slab_sum<T, NG>(a, s_src, slab, gtab, Zt, pr, pi);
-
+    // The target z planes in passes of ZW (all N_g at once unless the accumulators would not
+    // fit), each pass's planes through the slab buffer ZG at a time for the inverse y transform.
     // The inverse y transform runs in the plan's precision (the N_g target values of each column
     // kept) and the inverse x transform in double precision as direct sums against a double
     // twiddle table: the last rounding then happens at the magnitude of the potential's variation
     // across the target, not at that of the interaction zone's large smooth potential.
-    static_assert(ZB >= NG, "the slab buffer holds the N_g accumulated planes");
+    for (int zp = 0; zp < NG; zp += ZW) {
+      T pr[PER][ZW], pi[PER][ZW];
+      slab_sum<T, NG>(a, s_src, slab, gtab, Zt + zp, s_tw, pr, pi);
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int e = tid + NT * r;
-      if (e < ENT) {
+      for (int z0 = 0; z0 < ZW; z0 += ZG) {
 #pragma unroll
-        for (int zz = 0; zz < NG; ++zz) slab[size_t(zz) * ENT + e] = {pr[r][zz], pi[r][zz]};
+        for (int r = 0; r < PER; ++r) {
+          const int e = tid + NT * r;
+          if (e < ENT) {
+#pragma unroll
+            for (int zz = 0; zz < ZG; ++zz) slab[size_t(zz) * ENT + e] = {pr[r][z0 + zz], pi[r][z0 + zz]};
+          }
+        }
+        __syncthreads();
+        // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n}, Y = (2 + c_y) N_g + yy
+        if constexpr (!S::wide) {
+          for (int w = tid; w < ZG * H; w += NT) {
+            const int kx = w % H, zz = w / H;
+            const cplx<T>* col = slab + size_t(zz) * ENT + kx;
+            cplx<T> in[n], out[n];
+#pragma unroll
+            for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
+            fft<n, +1>(in, out);
+#pragma unroll
+            for (int yy = 0; yy < NG; ++yy) {
+              const cplx<T> o0 = out[2 * NG + yy], o1 = out[3 * NG + yy];
+              red[(size_t(zp + z0 + zz) * NG + yy) * H + kx] = {t.cy ? o1.re : o0.re, t.cy ? o1.im : o0.im};
+            }
+          }
+        } else {
+          // pruned: only the N_g target values of each column, as direct sums in double
+          for (int w = tid; w < ZG * H * NG; w += NT) {
+            const int kx = w % H, yy = (w / H) % NG, zz = w / (H * NG);
+            const int Y = (2 + t.cy) * NG + yy;
+            const cplx<T>* col = slab + size_t(zz) * ENT + kx;
+            cplx<double> acc = {0.0, 0.0};
+            int mi = 0;
+#pragma unroll 8
+            for (int ky = 0; ky < n; ++ky) {
+              const cplx<double> tv = s_tw[mi];
+              const cplx<T> f = col[size_t(ky) * H];
+              acc.re = fma(double(f.re), tv.re, fma(-double(f.im), tv.im, acc.re));
+              acc.im = fma(double(f.re), tv.im, fma(double(f.im), tv.re, acc.im));
+              mi += Y;
+              if (mi >= n) mi -= n;
+            }
+            red[(size_t(zp + z0 + zz) * NG + yy) * H + kx] = acc;
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
-    // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n}, Y = (2 + c_y) N_g + yy
-    for (int w = tid; w < NG * H; w += NT) {
-      const int kx = w % H, zz = w / H;
-      const cplx<T>* col = slab + size_t(zz) * ENT + kx;
-      cplx<T> in[n], out[n];
-#pragma unroll
-      for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
-      fft<n, +1>(in, out);
-#pragma unroll
-      for (int yy = 0; yy < NG; ++yy) {
-        const cplx<T> o = t.cy ? out[3 * NG + yy] : out[2 * NG + yy];
-        red[(size_t(zz) * NG + yy) * H + kx] = {double(o.re), double(o.im)};
-      }
-    }
-    __syncthreads();
     // x^-1 (Hermitian half spectrum): out = sum_k w_k Re(F_k e^{+2 pi i k X / n}), w_k = 1 at
     // k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g + xx
     const int Xt = (2 + t.cx) * NG;
     for (int q = tid; q < M; q += NT) {
       const int xx = q % NG, row = q / NG;
       const int X = Xt + xx;
-      const cplx<double>* F = red + size_t(row) * H;
+      const cplx<typename S::RedT>* F = red + size_t(row) * H;
       double acc = 0.0;
       int m = 0;
       for (int k = 0; k < H; ++k) {
-        const cplx<double> f = F[k];
+        const cplx<double> f = {double(F[k].re), double(F[k].im)};
         const cplx<double> w = s_tw[m];
         const double v = f.re * w.re - f.im * w.im;
         acc += (k == 0 || k == n / 2) ? v : 2.0 * v;
@@ -536,7 +669,7 @@ struct ParentShape {
   using S = SlabShape<T, NG>;
   static constexpr size_t red_bytes = size_t(NG) * 2 * NG * S::H * sizeof(cplx<T>) +
                                       size_t(S::M) * 8 + size_t(S::n) * sizeof(cplx<double>);
-  static constexpr bool fits = S::slab_bytes + red_bytes + 216 * 4 + 64 <= 150 * 1024;
+  static constexpr bool fits = !S::narrow && S::slab_bytes + red_bytes + 216 * 4 + 64 <= 150 * 1024;
 };
 
 template <typename T, int NG>
@@ -584,7 +717,7 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_parent(M2LArgs<T> a) {
           s_kid[4 * cz + 3] < 0)
         continue;
       T pr[PER][NG], pim[PER][NG];
-      slab_sum<T, NG>(a, s_src, slab, gtab, (2 + cz) * NG, pr, pim);
+      slab_sum<T, NG>(a, s_src, slab, gtab, (2 + cz) * NG, s_tw, pr, pim);
 #pragma unroll
       for (int r = 0; r < PER; ++r) {
         const int e = tid + NT * r;
@@ -647,44 +780,29 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_parent(M2LArgs<T> a) {
   }
 }
 
-// Which kernel serves (T, N_g): from N_g = 4 on the z-slab kernel where it fits (both
-// precisions; in FP64 one workgroup per CU fits): at N_g = 4 in FP32 the whole-stage kernel
-// would hold 104 KB of LDS per workgroup, one workgroup per CU. Below N_g = 4 the whole stage
-// in LDS; else the full-grid kernel with a global stage slice per workgroup.
+// Which kernel serves (T, N_g): from N_g = 4 on the z-slab kernel (both precisions; from N_g = 6
+// in FP64 one workgroup per CU fits); below N_g = 4 the whole-grid kernel with its stage in LDS
+// (at N_g = 4 in FP32 that stage would hold 104 KB, one workgroup per CU).
 template <typename T, int NG>
 constexpr int m2l_kind() {
-  if constexpr (NG >= 4 && SlabShape<T, NG>::fits) return 1;
-  else if constexpr (M2LShape<T, NG>::lds) return 0;
-  else return 2;
+  if constexpr (NG >= 4) {
+    static_assert(SlabShape<T, NG>::fits, "z-slab buffers exceed the LDS budget");
+    return 1;
+  } else {
+    static_assert(M2LShape<T, NG>::lds, "whole-grid stage exceeds the LDS budget");
+    return 0;
+  }
 }
 
 // resident workgroups of the z-slab kernel on 256 CUs
 constexpr int kSlabGrid = 256 * kSlabPerCU;
 
+// Workgroups of a source-to-target launch (the kernels keep every per-target buffer on the CU;
+// there is no workspace in device memory).
 int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot) {
-  size_t b = 0;
-  int kind = 0;
-#define HPM_SHAPE(TT, NN)                      \
-  if (ng == NN) {                              \
-    b = M2LShape<TT, NN>::bytes;               \
-    kind = m2l_kind<TT, NN>();                 \
-  }
-  if (prec == HPM_F32) {
-    HPM_SHAPE(float, 2) HPM_SHAPE(float, 3) HPM_SHAPE(float, 4) HPM_SHAPE(float, 6) HPM_SHAPE(float, 8)
-  } else {
-    HPM_SHAPE(double, 2) HPM_SHAPE(double, 3) HPM_SHAPE(double, 4) HPM_SHAPE(double, 6) HPM_SHAPE(double, 8)
-  }
-#undef HPM_SHAPE
-  if (kind == 0) {
-    *bytes_per_slot = 0;
-    return 8 * 256;
-  }
-  if (kind == 1) {
-    *bytes_per_slot = 0;
-    return kSlabGrid;
-  }
-  *bytes_per_slot = b;
-  return b > (size_t(1) << 20) ? 1024 : 2048;
+  *bytes_per_slot = 0;
+  (void)prec;
+  return ng >= 4 ? kSlabGrid : 8 * 256;
 }
 
 template <typename T, int NG>
@@ -706,13 +824,12 @@ static void m2l_t(Plan& p, hipStream_t s) {
   a.m2l_mean = p.m2l_mean.as<double>();
   a.ghat = p.tab.ghat.as<T>();
   a.gxy = p.tab.gxy.as<T>();
-  a.work = p.m2l_work.as<cplx<T>>();
   a.lo0 = p.prob.box_lo[0];
   a.lo1 = p.prob.box_lo[1];
   a.lo2 = p.prob.box_lo[2];
   a.size = p.prob.box_size;
   int grid = ((a.ntargets + 7) / 8) * 8;
-  if (grid > p.m2l_slots) grid = p.m2l_slots;  // the global stage holds m2l_slots slices
+  if (grid > p.m2l_slots) grid = p.m2l_slots;
   p.m2l_split = m2l_kind<T, NG>() == 1;
   if constexpr (m2l_kind<T, NG>() == 1) k_m2l_slab<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
   else k_m2l<T, NG><<<grid, 256, 0, s>>>(a);

@@ -304,7 +304,7 @@ hpm_status hpm_server_submit(hpm_server* server, const hpm_problem* problem, int
   return guarded([&] {
     if (!server || !ticket) fail(HPM_ERR_INVALID_ARG, "NULL argument");
     check_problem(problem);
-    if (n < 1 || n > (int64_t(1) << 30)) fail(HPM_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    check_size(problem, n);
     if (!x || !y || !z || !m || !phi || !ax || !ay || !az)
       fail(HPM_ERR_INVALID_ARG, "array pointer is NULL");
     auto r = std::make_shared<Request>();

@@ -69,3 +69,16 @@ def rel_rms(a, b) -> float:
 def rel_max(a, b) -> float:
     a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rel_each_max(a, b, floor: float = 1e-3) -> float:
+    """Largest per-particle relative error max_i |a_i - b_i| / max(|b_i|, floor * rms|b|) (rows
+    of a 2-D array are vectors); the floor keeps particles where the field nearly cancels from
+    dividing by a value far below the field's scale."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    if a.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    d = np.linalg.norm(a - b, axis=1)
+    r = np.linalg.norm(b, axis=1)
+    scale = np.sqrt(np.mean(r * r))
+    return float(np.max(d / np.maximum(r, floor * max(scale, 1e-300))))

@@ -7,14 +7,15 @@ route and the route with the transform shared by siblings (against the same valu
 modes agree to rounding), and the cell route with extended target gridlets (against the oracle's
 extended values).
 
-Tolerances as in the small-case parity tests: FP64 path 1e-10 relative, FP32 path 1e-5 relative
-RMS in potential (acceleration 1e-4, local gridlets 2e-5 of the level's largest value)."""
+Tolerances as in the small-case parity tests: FP64 path 1e-10 relative per particle (potential
+and acceleration), FP32 path 1e-5 relative RMS in potential (acceleration 1e-4, local gridlets
+2e-5 of the level's largest value)."""
 import os
 
 import numpy as np
 import pytest
 
-from tests.hpmcase import log, rel_max, rel_rms
+from tests.hpmcase import log, rel_each_max, rel_max, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +74,8 @@ def _check(ng, prec, m2l, extended):
     assert e_acc < tol["acc"]
     if prec == "f64":
         assert rel_max(phi, gold["phi"]) < 1e-10
+        assert rel_each_max(phi, gold["phi"]) < 1e-10
+        assert rel_each_max(acc, gold["acc"]) < 1e-10
 
     worst = 0.0
     for lvl in np.unique(gold["cell_level"]):

@@ -73,3 +73,44 @@ def test_clustered_2p24():
         log(f"[large] cell route {prec}: phi vs padded grid (f64) rel rms {e_c:.2e}")
         assert e_c < tol
         del x, y, z, m, phi, ax, ay, az
+
+
+def test_clustered_2p24_sampled_outputs_match_oracle():
+    # Parity at the largest workload (FP32, its own precision): the oracle's values for 128
+    # sampled particles and 24 sampled target cells (tests/golden/make_clustered2p24.py, oracle
+    # only), same tree; bars as in the small-case parity tests (1e-5 relative RMS in potential,
+    # 1e-4 in acceleration, local gridlets 2e-5 of their largest value).
+    import os
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import clustered_spheres
+    from tests.hpmcase import rel_max, rel_rms
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                "clustered2p24_ng4_f32.npz"))
+    p = clustered_spheres(2 ** 24, 1002).astype(np.float32)
+    x, y, z, m = (torch.tensor(a, dtype=torch.float32, device="cuda") for a in (p.x, p.y, p.z, p.m))
+    plan = hpm.Plan(hpm.Problem(ng=4, precision="f32", leaf_capacity=32, max_depth=10,
+                                softening=1e-3), x, y, z)
+    phi, ax, ay, az = plan(m)
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert list(info["cells_per_level"][:info["n_levels"]]) == list(gold["cells_per_level"])
+    assert info["n_targets"] == int(gold["n_targets"])
+    s = torch.tensor(gold["sample"], device="cuda")
+    e_phi = rel_rms(phi[s].double().cpu().numpy(), gold["phi"])
+    acc = torch.stack([ax[s], ay[s], az[s]], 1).double().cpu().numpy()
+    e_acc = rel_rms(acc, gold["acc"])
+    worst = 0.0
+    for lvl in np.unique(gold["cell_level"]):
+        cells = plan.cells(int(lvl))
+        index = {tuple(c): i for i, c in enumerate(cells["coords"].tolist())}
+        loc = plan.locals(int(lvl))
+        for k in np.nonzero(gold["cell_level"] == lvl)[0]:
+            i = index[tuple(gold["cell_coord"][k].tolist())]
+            worst = max(worst, rel_max(loc[i], gold["cell_local"][k]))
+    log(f"[large] 2^24 vs oracle: phi rel rms {e_phi:.2e} acc rel rms {e_acc:.2e} "
+        f"locals rel max {worst:.2e}")
+    assert e_phi < 1e-5
+    assert e_acc < 1e-4
+    assert worst < 2e-5
+    plan.close()
