@@ -231,6 +231,28 @@ hpm_status hpm_solve(const hpm_problem* problem, int64_t n, const void* x, const
                      const void* z, const void* m, void* phi, void* ax, void* ay, void* az,
                      void* stream);
 
+/*
+ * hpm_solve for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same steps and arguments as hpm_solve, but
+ * every device buffer of the solve (particles in key order, tree, gridlets, local potentials,
+ * near-zone work items, constant tables, the words the tree build reads back) is carved from a
+ * fixed 64 MiB device region of the library, one per device, which each device holds from its
+ * first call until the process ends. The call makes no hipMalloc, hipFree, hipHostMalloc, stream
+ * or event creation; the near-zone sums run in line on "stream".
+ * Limit: the estimate of hpm_plan_bytes_estimate for (problem, n) must fit the 64 MiB region (for
+ * instance 4096 particles at any order, or 2^15 at N_g <= 6 in FP32); a larger problem returns
+ * HPM_ERR_NO_MEMORY before any device work, and so does a tree that outgrows the region while it
+ * is built (the outputs are then unspecified).
+ * Calls on one device share the region and it keeps the last call's contents (every buffer is
+ * written before it is read). Calls from threads of this process are serialised by the library,
+ * and each call synchronises "stream" before it returns; any other overlapping use of the region
+ * races.
+ * Errors: those of hpm_plan_create and hpm_plan_execute.
+ */
+hpm_status hpm_solve_noalloc(const hpm_problem* problem, int64_t n, const void* x, const void* y,
+                             const void* z, const void* m, void* phi, void* ax, void* ay,
+                             void* az, void* stream);
+
 /* Tree and size statistics of a plan (info: host, caller-owned). */
 hpm_status hpm_plan_info_get(const hpm_plan* plan, hpm_plan_info* info);
 

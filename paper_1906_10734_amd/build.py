@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhpm.so")
 SOURCES = ["api.cpp", "server.cpp", "tables.cpp", "tree.hip", "upsweep.hip", "m2l.hip",
-           "m2l_cells.hip", "downsweep.hip"]
+           "m2l_cells.hip", "downsweep.hip", "noalloc.hip"]
 ARCH = os.environ.get("HPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

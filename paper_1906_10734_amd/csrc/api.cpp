@@ -12,6 +12,27 @@
 namespace hpm {
 
 static thread_local std::string g_last_error;
+thread_local Arena* t_arena = nullptr;
+
+void* Arena::take(size_t b) {
+  const size_t off = (used + 255) & ~size_t(255);
+  if (off > size || b > size - off)
+    fail(HPM_ERR_NO_MEMORY, "the no-allocation scratch region is exhausted (" +
+                                std::to_string(size >> 20) + " MiB)");
+  used = off + b;
+  return base + off;
+}
+
+void sync_box(Plan& p, hipStream_t s) {
+  if (p.noalloc)
+    HPM_HIP(hipMemcpyAsync(p.hbox, p.dbox, Plan::kBoxLev * sizeof(int), hipMemcpyDeviceToHost, s));
+  HPM_HIP(hipStreamSynchronize(s));
+}
+
+void clear_box(Plan& p, int w, int count, hipStream_t s) {
+  for (int k = 0; k < count; ++k) p.hbox[w + k] = 0;
+  if (p.noalloc) HPM_HIP(hipMemsetAsync(p.dbox + w, 0, size_t(count) * sizeof(int), s));
+}
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 void fail(hpm_status s, const std::string& msg) { throw HpmError{s, msg}; }
@@ -111,12 +132,17 @@ void create_plan(Plan& p, const hpm_problem* pr, int64_t n, const void* x, const
   p.ML = p.NL * p.NL * p.NL;
   p.elem = (p.prec == HPM_F32) ? 4 : 8;
   p.route = pr->m2l_mode;
-  HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
-                        hipHostMallocMapped | hipHostMallocCoherent));
-  HPM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&p.dbox), p.hbox, 0));
-  HPM_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
-  HPM_HIP(hipEventCreateWithFlags(&p.fork_ev, hipEventDisableTiming));
-  HPM_HIP(hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming));
+  if (p.noalloc) {
+    p.hbox = p.hbox_store;
+    p.dbox = static_cast<int*>(t_arena->take(Plan::kBoxWords * sizeof(int)));
+  } else {
+    HPM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p.hbox), Plan::kBoxWords * sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HPM_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&p.dbox), p.hbox, 0));
+    HPM_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+    HPM_HIP(hipEventCreateWithFlags(&p.fork_ev, hipEventDisableTiming));
+    HPM_HIP(hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming));
+  }
   const int depth = pr->uniform_depth > 0 ? pr->uniform_depth : pr->max_depth;
   build_tables(p, depth + 1, s);
   size_t slot_bytes = 0;
@@ -158,7 +184,7 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
   // the near zone needs only the tree and the sorted masses: for large problems it runs on the
   // side stream beside the source-to-target step (which leaves ALU and memory slots idle) and
   // the leaf pass waits for it; small ones keep it in line, where the fork costs more than it hides
-  const bool fork = p.n >= kForkMinParticles;
+  const bool fork = p.n >= kForkMinParticles && p.side;
   if (fork) {
     HPM_HIP(hipEventRecord(p.fork_ev, s));
     HPM_HIP(hipStreamWaitEvent(p.side, p.fork_ev, 0));
@@ -228,7 +254,7 @@ Plan::~Plan() {
   }
   if (fork_ev) (void)hipEventDestroy(fork_ev);
   if (join_ev) (void)hipEventDestroy(join_ev);
-  if (hbox) (void)hipHostFree(hbox);
+  if (hbox && !noalloc) (void)hipHostFree(hbox);
   if (events_created) {
     for (auto& set : ev)
       for (auto& e : set)

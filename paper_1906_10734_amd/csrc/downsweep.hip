@@ -239,7 +239,7 @@ void build_near_lists(Plan& p, hipStream_t s) {
   HPM_LAUNCH_CHECK();
   exclusive_scan_i32(p.item_cnt.as<int>(), p.item_off.as<int>(), nl, p.dbox + Plan::kBoxTotal,
                      p.scan_tmp, s);
-  HPM_HIP(hipStreamSynchronize(s));
+  sync_box(p, s);
   const int total = p.hbox[Plan::kBoxTotal];
   p.n_items = total;
   p.p2p_pairs = -1;  // read from the device on request

@@ -52,43 +52,74 @@ hpm_status guarded(F&& f) {
 
 #define HPM_LAUNCH_CHECK() HPM_HIP(hipGetLastError())
 
-// A device allocation that frees itself.
+// A fixed region of device memory that buffers are carved from instead of hipMalloc, for the
+// entry point that allocates nothing (bump allocation, 256-byte aligned, nothing is returned until
+// the region is dropped as a whole).
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  void* take(size_t b);
+};
+
+// The arena that DevBuf allocations of the calling thread come from (null: hipMalloc). Set for
+// the duration of a no-allocation call by ArenaScope.
+extern thread_local Arena* t_arena;
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(t_arena) { t_arena = a; }
+  ~ArenaScope() { t_arena = prev; }
+};
+
+// A device allocation that frees itself (from hipMalloc, or from the thread's arena when one is
+// set, in which case release() only forgets it).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool in_arena = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !in_arena) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    in_arena = false;
+  }
+  static void* take(size_t b, bool* from_arena) {
+    void* q = nullptr;
+    *from_arena = t_arena != nullptr;
+    if (t_arena) q = t_arena->take(b);
+    else HPM_HIP(hipMalloc(&q, b));
+    return q;
   }
   // (re)allocate to at least b bytes; contents are not preserved
   void reserve(size_t b) {
     if (b <= bytes && p) return;
     release();
     if (b == 0) b = 16;
-    HPM_HIP(hipMalloc(&p, b));
+    p = take(b, &in_arena);
     bytes = b;
   }
   // grow to at least b bytes, preserving the first "keep" bytes
   void grow(size_t b, size_t keep, hipStream_t s) {
     if (b <= bytes && p) return;
-    void* q = nullptr;
-    HPM_HIP(hipMalloc(&q, b));
+    bool qa = false;
+    void* q = take(b, &qa);
     if (p && keep) HPM_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, s));
     HPM_HIP(hipStreamSynchronize(s));
     release();
     p = q;
     bytes = b;
+    in_arena = qa;
   }
   template <typename U>
   U* as() const { return static_cast<U*>(p); }
   void swap(DevBuf& o) {
     std::swap(p, o.p);
     std::swap(bytes, o.bytes);
+    std::swap(in_arena, o.in_arena);
   }
 };
 
@@ -184,6 +215,11 @@ struct Plan {
   static constexpr int kBoxLev = 24;        // words 24 .. 63: copy of the device level table
   int* hbox = nullptr;
   int* dbox = nullptr;
+  // a plan of the entry point that allocates nothing: its buffers come from an arena, the mailbox
+  // words live in device memory (copied to hbox_store by sync_box), and it has no side stream
+  // and no timing events
+  bool noalloc = false;
+  int hbox_store[kBoxWords] = {0};
   // a second stream (default priority) on which the near-zone sums run beside the far-field
   // chain of an execution, with the events that fork it from and join it to the caller's stream
   hipStream_t side = nullptr;
@@ -220,6 +256,11 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
 // (10 n / leaf capacity + 64 cells, or every cell of a uniform tree; one virtual cube per cell;
 // the near-zone work of four source chunks per cell)
 size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n);
+
+// waits for "s", after copying the mailbox words to the host when they live in device memory
+void sync_box(Plan& p, hipStream_t s);
+// zeroes mailbox words [w, w + count) before kernels set them
+void clear_box(Plan& p, int w, int count, hipStream_t s);
 
 // ---- tables.cpp -------------------------------------------------------------------------------
 // tables for levels 2..max_levels-1 (the Green transforms depend on the level, not on the tree)

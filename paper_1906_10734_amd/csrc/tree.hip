@@ -543,8 +543,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   p.perm.reserve(size_t(n) * 4);
   p.tmp_keys.reserve(size_t(n) * 4);
   p.tmp_vals.reserve(size_t(n) * 4);
-  p.hbox[Plan::kBoxOutOfBox] = 0;
-  p.hbox[Plan::kBoxNonfinite] = 0;
+  clear_box(p, Plan::kBoxOutOfBox, 2, s);
 
   const double scale = double(1 << D) / pr.box_size;
   const double hi0 = pr.box_lo[0] + pr.box_size, hi1 = pr.box_lo[1] + pr.box_size,
@@ -647,7 +646,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   for (bool first = true;; first = false) {
     HPM_HIP(hipMemcpyAsync(p.hbox + Plan::kBoxLev, lev, kLevWords * sizeof(int),
                            hipMemcpyDeviceToHost, s));
-    HPM_HIP(hipStreamSynchronize(s));
+    sync_box(p, s);
     if (first) {
       if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
       if (p.hbox[Plan::kBoxOutOfBox])
@@ -856,7 +855,7 @@ void build_virtual(Plan& p, hipStream_t s) {
   const int first = p.nlevels > 2 ? p.level_off[1] : 0;
   const int nt = p.nlevels > 2 ? p.level_off[p.nlevels - 1] - first : 0;
   if (nt <= 0) {
-    HPM_HIP(hipStreamSynchronize(s));
+    sync_box(p, s);
     read_leaf_counts(p);
     return;
   }
@@ -891,7 +890,7 @@ void build_virtual(Plan& p, hipStream_t s) {
   HPM_LAUNCH_CHECK();
   int* d_total = p.dbox + Plan::kBoxTotal;
   exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
-  HPM_HIP(hipStreamSynchronize(s));
+  sync_box(p, s);
   read_leaf_counts(p);
   const int refs = p.hbox[Plan::kBoxTotal];
   if (refs <= 0) {
@@ -911,7 +910,7 @@ void build_virtual(Plan& p, hipStream_t s) {
   k_unique_flags<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va);
   HPM_LAUNCH_CHECK();
   exclusive_scan_i32(va, vb, refs, d_total, p.scan_tmp, s);
-  HPM_HIP(hipStreamSynchronize(s));
+  sync_box(p, s);
   const int nv = p.hbox[Plan::kBoxTotal];
   p.vkeys.reserve(size_t(std::max(nv, 1)) * 4);
   k_unique_emit<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va, vb,

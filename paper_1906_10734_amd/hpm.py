@@ -80,6 +80,8 @@ SIGNATURES = {
     "hpm_plan_stage_times": (_i32, [_vp, _vp, _vp, _vp]),
     "hpm_solve": (_i32, [ctypes.POINTER(HpmProblem), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                          _vp]),
+    "hpm_solve_noalloc": (_i32, [ctypes.POINTER(HpmProblem), _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp]),
     "hpm_plan_info_get": (_i32, [_vp, ctypes.POINTER(HpmPlanInfo)]),
     "hpm_plan_copy_perm": (_i32, [_vp, _vp]),
     "hpm_plan_copy_cells": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -317,6 +319,20 @@ def solve(problem: Problem, x, y, z, m, stream=None):
     _check(_lib.hpm_solve(ctypes.byref(c), n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
                           _dev(z, dt, n, "z"), _dev(m, dt, n, "m"), *(o.data_ptr() for o in out),
                           _stream(stream)), "hpm_solve")
+    return tuple(out)
+
+
+def solve_noalloc(problem: Problem, x, y, z, m, out=None, stream=None):
+    """One-shot solve without device allocation in the library (hpm_solve_noalloc); ``out``
+    (optional) is the caller's (phi, ax, ay, az). Returns (phi, ax, ay, az) in input order."""
+    n, dt = int(x.numel()), problem.dtype
+    if out is None:
+        out = [torch.empty(n, dtype=dt, device=x.device) for _ in range(4)]
+    c = problem.c()
+    _check(_lib.hpm_solve_noalloc(ctypes.byref(c), n, _dev(x, dt, n, "x"), _dev(y, dt, n, "y"),
+                                  _dev(z, dt, n, "z"), _dev(m, dt, n, "m"),
+                                  *(_dev(o, dt, n, "out") for o in out), _stream(stream)),
+           "hpm_solve_noalloc")
     return tuple(out)
 
 
