@@ -107,7 +107,10 @@ typedef enum { HPM_M2L_GRID = 0, HPM_M2L_CELLS = 1, HPM_M2L_SHARED = 2 } hpm_m2l
  *   extended       0 or 1. 1: target gridlets widened by one node on every side (Sec. 2.5), so
  *                  the source-to-target output, parent-to-child and leaf interpolation use
  *                  (N_g + 2)^3 nodes at the same spacing; sources keep N_g^3 effective masses.
- *                  Built on the cell-by-cell route only: with HPM_M2L_GRID it returns
+ *                  On the padded grid the target window is [(2 + c) N_g - 1, (3 + c) N_g + 1)
+ *                  per axis, still exact with n = 8 N_g. Built on the cell-by-cell route
+ *                  (N_g <= 6) and on the padded-grid route (N_g = 4 and 6); with
+ *                  HPM_M2L_SHARED, or another order on the padded grid, it returns
  *                  HPM_ERR_UNSUPPORTED.
  *   reserved       must be 0.
  */
@@ -207,7 +210,7 @@ hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int
  * compute the same sums (Sec. 2.1, Sec. 2.5); they differ in speed. A plan made with
  * HPM_M2L_GRID can only use that route, since the others need the cell spectra and their Green
  * tables; a plan made with HPM_M2L_CELLS or HPM_M2L_SHARED can use all three, except with
- * extended gridlets (HPM_M2L_CELLS only).
+ * extended gridlets (HPM_M2L_CELLS, and HPM_M2L_GRID at N_g = 4 and 6).
  * Errors: HPM_ERR_INVALID_ARG (NULL plan, unknown mode), HPM_ERR_UNSUPPORTED (route not built).
  */
 hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode);

@@ -64,8 +64,12 @@ void check_problem(const hpm_problem* pr) {
     fail(HPM_ERR_INVALID_ARG, "m2l_mode must be HPM_M2L_GRID, HPM_M2L_CELLS or HPM_M2L_SHARED");
   if (pr->extended != 0 && pr->extended != 1) fail(HPM_ERR_INVALID_ARG, "extended must be 0 or 1");
   if (pr->reserved != 0) fail(HPM_ERR_INVALID_ARG, "problem.reserved must be 0");
-  if (pr->extended && pr->m2l_mode != HPM_M2L_CELLS)
-    fail(HPM_ERR_UNSUPPORTED, "extended gridlets are built on the cell-by-cell route only");
+  if (pr->extended && pr->m2l_mode == HPM_M2L_SHARED)
+    fail(HPM_ERR_UNSUPPORTED, "the shared-transform route has no extended gridlets");
+  if (pr->extended && pr->m2l_mode == HPM_M2L_GRID && ng != 4 && ng != 6)
+    fail(HPM_ERR_UNSUPPORTED, "extended gridlets on the padded-grid route need ng = 4 or 6");
+  if (pr->extended && ng == 8)
+    fail(HPM_ERR_UNSUPPORTED, "no extended gridlets at ng = 8");
   if (ng == 8 && pr->m2l_mode != HPM_M2L_GRID)
     fail(HPM_ERR_UNSUPPORTED, "ng = 8 is built on the padded-grid route only");
   if (pr->uniform_depth < 0 || pr->uniform_depth > 10) fail(HPM_ERR_INVALID_ARG, "uniform_depth must be 0..10");
@@ -239,7 +243,7 @@ size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
                                                               // cubes, locals, fit rows
   b += c * (27 * 8 + 8 + 4 * (16 + 64 * 5 * s));  // near-zone ranges and work items
   const size_t H = 4 * ng + 1, levels = size_t(std::max(depth - 1, 1));
-  b += levels * (H * H * H + 4 * ng * H * H) * s;  // Green transforms
+  b += levels * (H * H * H + (4 * ng + 1) * H * H) * s;  // Green transforms
   if (pr.m2l_mode != HPM_M2L_GRID) {
     const size_t spec = cell_modes(int(ng), pr.extended) * 2 * s;
     b += (2 * c + 1) * spec + levels * 343 * spec + 3 * 4 * c;
@@ -319,11 +323,11 @@ hpm_status hpm_plan_execute(hpm_plan* plan, const void* m, void* phi, void* ax, 
 }
 
 // routes a plan can evaluate with: its own; all three when it was made with the cell spectra and
-// standard gridlets (the cell route alone builds the extended ones)
+// standard gridlets; with extended gridlets the cell route and (N_g = 4, 6) the padded grid
 static bool route_allowed(const Plan& p, int32_t mode) {
   if (mode != HPM_M2L_GRID && mode != HPM_M2L_CELLS && mode != HPM_M2L_SHARED) return false;
   if (p.prob.m2l_mode == HPM_M2L_GRID) return mode == HPM_M2L_GRID;
-  if (p.ext) return mode == HPM_M2L_CELLS;
+  if (p.ext) return mode == HPM_M2L_CELLS || (mode == HPM_M2L_GRID && (p.ng == 4 || p.ng == 6));
   return true;
 }
 

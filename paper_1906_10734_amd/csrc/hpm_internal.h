@@ -136,8 +136,8 @@ struct Tables {
                  // the gridlets are extended)
   DevBuf fitw;   // [Kpad][Mpad]: W[n][p] = B^phi[p][n], Legendre-moment fit matrix, zero padded
   DevBuf ghat;   // [levels 2..L][(n/2+1)^3]: octant of the lattice Green transform / n^3
-  DevBuf gxy;    // [levels 2..L][4 N_g][n/2+1][n/2+1]: Green function transformed along x and y
-                 // only, at z offsets d < 4 N_g, [d][ky][kx], / n^2
+  DevBuf gxy;    // [levels 2..L][4 N_g + 1][n/2+1][n/2+1]: Green function transformed along x
+                 // and y only, at z offsets d <= 4 N_g, [d][ky][kx], / n^2
   DevBuf gcell;  // cell-by-cell and shared-transform routes only: [levels 2..L][343 offsets][(2N_g)^2 (N_g+1)] complex,
                  // transform of the cyclic Green array of each source cube offset, / (2 N_g)^3
   int kpad = 0, mpad = 0;

@@ -356,9 +356,12 @@ constexpr int kSlabLayers = 1;         // block layers (N_g source z rows each) 
 constexpr bool kSlabGreenLds = false;  // Green table of the level in LDS (else read through L2)
 constexpr int kSlabPerCU = 2;          // resident workgroups per CU
 
-template <typename T, int NG>
+// EXT = 1: extended target gridlets (Sec. 2.5), NL = N_g + 2 nodes per axis, the target window
+// [(2 + c) N_g - 1, (3 + c) N_g + 1) per axis.
+template <typename T, int NG, int EXT = 0>
 struct SlabShape {
   static constexpr int n = 8 * NG, H = n / 2 + 1, W = 6 * NG, M = NG * NG * NG;
+  static constexpr int NL = NG + 2 * EXT, ML = NL * NL * NL;  // target gridlet
   static constexpr int NT = kSlabThreads;
   // At N_g = 8 the inverse y transform is a pruned direct sum in double (FP32 rounding of the
   // inverse transforms would dominate the gradient of a degree-7 interpolant), and its output
@@ -369,18 +372,18 @@ struct SlabShape {
   static constexpr bool wide = NG >= 8;
   static constexpr bool narrow = wide && sizeof(T) == 8;
   static constexpr int ZB = wide ? (narrow ? 2 : NG / 2) : kSlabLayers * NG;  // source rows per slab
-  static constexpr int ZW = narrow ? NG / 2 : NG;           // target z planes per pass
+  static constexpr int ZW = narrow ? NG / 2 : NL;           // target z planes per pass
   static constexpr int YS = narrow ? 4 : 1;                 // threads per forward y line
   static constexpr int XS = narrow ? 2 : 1;                 // threads per x line
   static constexpr int ZG = ZB < ZW ? ZB : ZW;              // planes per inverse-y group
   using RedT = typename std::conditional<wide, double, T>::type;  // inverse-y output
-  static constexpr int D = 4 * NG;          // z offsets |Z - z| < 4 N_g
+  static constexpr int D = 4 * NG + 1;      // z offsets |Z - z| <= 4 N_g (table rows)
   static constexpr int ENT = n * H;         // (ky, kx) entries of a plane
   static constexpr int PER = (ENT + NT - 1) / NT;
   static constexpr int NJ = ZW + ZB - 1;    // distinct offsets Z - z within one slab and pass
   static constexpr size_t slab_bytes = size_t(ZB) * n * H * sizeof(cplx<T>);
   static constexpr size_t green_bytes = size_t(D) * H * H * sizeof(T);
-  static constexpr size_t red_bytes = size_t(NG) * NG * H * sizeof(cplx<RedT>) + size_t(M) * 8 +
+  static constexpr size_t red_bytes = size_t(NL) * NL * H * sizeof(cplx<RedT>) + size_t(ML) * 8 +
                                       size_t(n) * sizeof(cplx<double>) + 2048;
   static constexpr bool green_lds =
       kSlabGreenLds && slab_bytes + red_bytes + green_bytes <= 160 * 1024;
@@ -391,12 +394,12 @@ struct SlabShape {
 // through the x and y transforms in LDS and into the real-space z sum (pr, pi) at the ZW target
 // z values Zt .. Zt + ZW - 1. Called by all threads of the workgroup; the accumulators are
 // per thread, entry e = tid + NT r. tw holds e^{+2 pi i m / n}, m < n.
-template <typename T, int NG>
+template <typename T, int NG, int EXT = 0>
 __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, cplx<T>* slab,
                                          const T* gtab, int Zt, const cplx<double>* tw,
-                                         T (&pr)[SlabShape<T, NG>::PER][SlabShape<T, NG>::ZW],
-                                         T (&pi)[SlabShape<T, NG>::PER][SlabShape<T, NG>::ZW]) {
-  using S = SlabShape<T, NG>;
+                                         T (&pr)[SlabShape<T, NG, EXT>::PER][SlabShape<T, NG, EXT>::ZW],
+                                         T (&pi)[SlabShape<T, NG, EXT>::PER][SlabShape<T, NG, EXT>::ZW]) {
+  using S = SlabShape<T, NG, EXT>;
   constexpr int n = S::n, H = S::H, W = S::W, NT = S::NT, ZB = S::ZB, ZW = S::ZW, YS = S::YS,
                 PER = S::PER, NJ = S::NJ, ENT = S::ENT;
   const int tid = threadIdx.x;
@@ -519,18 +522,18 @@ __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, 
   }
 }
 
-template <typename T, int NG>
+template <typename T, int NG, int EXT>
 __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
-  using S = SlabShape<T, NG>;
-  constexpr int n = S::n, H = S::H, M = S::M, NT = S::NT, D = S::D, PER = S::PER, ENT = S::ENT,
-                ZW = S::ZW, ZG = S::ZG;
+  using S = SlabShape<T, NG, EXT>;
+  constexpr int n = S::n, H = S::H, NT = S::NT, D = S::D, PER = S::PER, ENT = S::ENT,
+                ZW = S::ZW, ZG = S::ZG, NL = S::NL, ML = S::ML;
   static_assert(S::fits, "slab buffers exceed the LDS budget");
-  static_assert(S::W % S::ZB == 0 && S::W % 2 == 0 && NG % ZW == 0 && ZW % ZG == 0, "slab shape");
+  static_assert(S::W % S::ZB == 0 && S::W % 2 == 0 && NL % ZW == 0, "slab shape");
   __shared__ int s_src[216];
   __shared__ int s_off[kMaxLevels + 1];
   __shared__ __align__(16) cplx<T> slab[S::ZB * n * H];  // [zb][ky (y before the y pass)][kx]
-  __shared__ cplx<typename S::RedT> red[NG * NG * H];    // after y^-1: [Z][Y][kx]
-  __shared__ double s_out[M];
+  __shared__ cplx<typename S::RedT> red[NL * NL * H];    // after y^-1: [Z][Y][kx]
+  __shared__ double s_out[ML];
   __shared__ double s_red[NT / 64];
   __shared__ cplx<double> s_tw[n];  // e^{+2 pi i m / n}
   __shared__ T s_green[S::green_lds ? D * H * H : 1];  // [d][ky folded][kx]
@@ -560,7 +563,7 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     }
     __syncthreads();
     const T* gtab = S::green_lds ? s_green : gtab_g;
-    const int Zt = (2 + t.cz) * NG;
+    const int Zt = (2 + t.cz) * NG - EXT;
 
     // The target z planes in passes of ZW (all N_g at once unless the accumulators would not
     // fit), each pass's planes through the slab buffer ZG at a time for the inverse y transform.
@@ -568,23 +571,26 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     // kept) and the inverse x transform in double precision as direct sums against a double
     // twiddle table: the last rounding then happens at the magnitude of the potential's variation
     // across the target, not at that of the interaction zone's large smooth potential.
-    for (int zp = 0; zp < NG; zp += ZW) {
+    for (int zp = 0; zp < NL; zp += ZW) {
       T pr[PER][ZW], pi[PER][ZW];
-      slab_sum<T, NG>(a, s_src, slab, gtab, Zt + zp, s_tw, pr, pi);
+      slab_sum<T, NG, EXT>(a, s_src, slab, gtab, Zt + zp, s_tw, pr, pi);
 #pragma unroll
       for (int z0 = 0; z0 < ZW; z0 += ZG) {
+        const int zg = ZW - z0 < ZG ? ZW - z0 : ZG;  // planes in this group
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
           const int e = tid + NT * r;
           if (e < ENT) {
 #pragma unroll
-            for (int zz = 0; zz < ZG; ++zz) slab[size_t(zz) * ENT + e] = {pr[r][z0 + zz], pi[r][z0 + zz]};
+            for (int zz = 0; zz < ZG; ++zz)
+              if (z0 + zz < ZW) slab[size_t(zz) * ENT + e] = {pr[r][z0 + zz], pi[r][z0 + zz]};
           }
         }
         __syncthreads();
-        // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n}, Y = (2 + c_y) N_g + yy
+        // y^-1: red[Z][yy][kx] = sum_ky P(Z, ky, kx) e^{+2 pi i ky Y / n},
+        // Y = (2 + c_y) N_g - EXT + yy
         if constexpr (!S::wide) {
-          for (int w = tid; w < ZG * H; w += NT) {
+          for (int w = tid; w < zg * H; w += NT) {
             const int kx = w % H, zz = w / H;
             const cplx<T>* col = slab + size_t(zz) * ENT + kx;
             cplx<T> in[n], out[n];
@@ -592,16 +598,16 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
             for (int y = 0; y < n; ++y) in[y] = col[size_t(y) * H];
             fft<n, +1>(in, out);
 #pragma unroll
-            for (int yy = 0; yy < NG; ++yy) {
-              const cplx<T> o0 = out[2 * NG + yy], o1 = out[3 * NG + yy];
-              red[(size_t(zp + z0 + zz) * NG + yy) * H + kx] = {t.cy ? o1.re : o0.re, t.cy ? o1.im : o0.im};
+            for (int yy = 0; yy < NL; ++yy) {
+              const cplx<T> o0 = out[2 * NG - EXT + yy], o1 = out[3 * NG - EXT + yy];
+              red[(size_t(zp + z0 + zz) * NL + yy) * H + kx] = {t.cy ? o1.re : o0.re, t.cy ? o1.im : o0.im};
             }
           }
         } else {
           // pruned: only the N_g target values of each column, as direct sums in double
-          for (int w = tid; w < ZG * H * NG; w += NT) {
-            const int kx = w % H, yy = (w / H) % NG, zz = w / (H * NG);
-            const int Y = (2 + t.cy) * NG + yy;
+          for (int w = tid; w < zg * H * NL; w += NT) {
+            const int kx = w % H, yy = (w / H) % NL, zz = w / (H * NL);
+            const int Y = (2 + t.cy) * NG - EXT + yy;
             const cplx<T>* col = slab + size_t(zz) * ENT + kx;
             cplx<double> acc = {0.0, 0.0};
             int mi = 0;
@@ -614,17 +620,17 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
               mi += Y;
               if (mi >= n) mi -= n;
             }
-            red[(size_t(zp + z0 + zz) * NG + yy) * H + kx] = acc;
+            red[(size_t(zp + z0 + zz) * NL + yy) * H + kx] = acc;
           }
         }
         __syncthreads();
       }
     }
     // x^-1 (Hermitian half spectrum): out = sum_k w_k Re(F_k e^{+2 pi i k X / n}), w_k = 1 at
-    // k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g + xx
-    const int Xt = (2 + t.cx) * NG;
-    for (int q = tid; q < M; q += NT) {
-      const int xx = q % NG, row = q / NG;
+    // k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g - EXT + xx
+    const int Xt = (2 + t.cx) * NG - EXT;
+    for (int q = tid; q < ML; q += NT) {
+      const int xx = q % NL, row = q / NL;
       const int X = Xt + xx;
       const cplx<typename S::RedT>* F = red + size_t(row) * H;
       double acc = 0.0;
@@ -642,15 +648,15 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     __syncthreads();
     // result = mean (double, per target) + zero-mean gridlet (T)
     double part = 0.0;
-    for (int e = tid; e < M; e += NT) part += s_out[e];
+    for (int e = tid; e < ML; e += NT) part += s_out[e];
     part = wave_sum(part);
     if ((tid & 63) == 0) s_red[tid >> 6] = part;
     __syncthreads();
     double mean = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) mean += s_red[w];
-    mean *= 1.0 / M;
-    for (int e = tid; e < M; e += NT) a.local[size_t(t.g) * M + e] = T(s_out[e] - mean);
+    mean *= 1.0 / ML;
+    for (int e = tid; e < ML; e += NT) a.local[size_t(t.g) * ML + e] = T(s_out[e] - mean);
     if (tid == 0) a.m2l_mean[t.g] = mean;
   }
 }
@@ -831,8 +837,17 @@ static void m2l_t(Plan& p, hipStream_t s) {
   int grid = ((a.ntargets + 7) / 8) * 8;
   if (grid > p.m2l_slots) grid = p.m2l_slots;
   p.m2l_split = m2l_kind<T, NG>() == 1;
-  if constexpr (m2l_kind<T, NG>() == 1) k_m2l_slab<T, NG><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
-  else k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
+  if constexpr (m2l_kind<T, NG>() == 1) {
+    if (p.ext) {
+      if constexpr (NG == 4 || NG == 6) k_m2l_slab<T, NG, 1><<<grid, SlabShape<T, NG, 1>::NT, 0, s>>>(a);
+      else fail(HPM_ERR_UNSUPPORTED, "no extended padded-grid kernel for this gridlet");
+    } else {
+      k_m2l_slab<T, NG, 0><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
+    }
+  } else {
+    if (p.ext) fail(HPM_ERR_UNSUPPORTED, "no extended padded-grid kernel for this gridlet");
+    k_m2l<T, NG><<<grid, 256, 0, s>>>(a);
+  }
   HPM_LAUNCH_CHECK();
 }
 

@@ -18,9 +18,10 @@
 //                offset. G is real and even along each axis, so its DFT is real, even and a
 //                product of cosine sums; only the octant k in [0, n/2]^3 is stored, divided by
 //                n^3 (the normalisation of the unnormalised inverse FFT). The same function
-//                transformed along x and y only, at the z offsets 0 .. 4 N_g - 1 that separate a
-//                target node from a source node, and divided by n^2, serves the variant of the
-//                source-to-target step that convolves along z in real space.
+//                transformed along x and y only, at the z offsets 0 .. 4 N_g that separate a
+//                target node from a source node (4 N_g = n/2 only with extended target gridlets),
+//                and divided by n^2, serves the variant of the source-to-target step that
+//                convolves along z in real space.
 //   cell-by-cell Green transforms  (only for the cell-by-cell route, Sec. 2.5) per level and
 //                source cube offset d in [-3, 3]^3: the C^3 cyclic array, C = 2 N_g + 2 ext,
 //                whose entry u holds g(h_l |d N_g - u_c|), u_c = u for u < N_g + ext and u - C
@@ -214,7 +215,7 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
   const int n = 8 * ng, H = n / 2 + 1;
   const int nlev = std::max(0, max_levels - 2);
   std::vector<double> ghat(size_t(std::max(nlev, 1)) * H * H * H, 0.0);
-  const int D = 4 * ng;
+  const int D = 4 * ng + 1;
   std::vector<double> gxy(size_t(std::max(nlev, 1)) * D * H * H, 0.0);
   std::vector<double> cs(size_t(H) * n);
   for (int k = 0; k < H; ++k)
@@ -234,10 +235,11 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
           if (x == 0 && y == 0 && z == 0 && eps == 0.0) r2 = h * h;
           // Offsets with max-norm <= N_g join a target node only to nodes of the 27 cubes
           // around the target, which are not sources; every interaction-zone pair is at least
-          // N_g + 1 apart along some axis. Their values never reach a target potential, and
-          // zero keeps the largest (near-origin) kernel values out of the transform, where they
-          // would only add rounding error.
-          const bool unreachable = std::max(pd[x], std::max(pd[y], pd[z])) <= ng;
+          // N_g + 1 apart along some axis (N_g with the extended target gridlet, whose outer
+          // nodes lie one spacing closer to the sources). Their values never reach a target
+          // potential, and zero keeps the largest (near-origin) kernel values out of the
+          // transform, where they would only add rounding error.
+          const bool unreachable = std::max(pd[x], std::max(pd[y], pd[z])) <= ng - p.ext;
           double gv = 0.0;
           if (!unreachable) {
             const double sd = std::sqrt(r2 + eps * eps);
@@ -263,7 +265,7 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
           for (int y = 0; y < n; ++y) acc += a1[(size_t(z) * n + y) * H + kx] * cs[size_t(ky) * n + y];
           a2[(size_t(z) * H + ky) * H + kx] = acc;
         }
-    // x, y only: gxy[d][ky][kx] = a2[d][ky][kx] / n^2, d < 4 N_g
+    // x, y only: gxy[d][ky][kx] = a2[d][ky][kx] / n^2, d <= 4 N_g
     const double inv_n2 = 1.0 / (double(n) * n);
     for (size_t e = 0; e < size_t(D) * H * H; ++e) gxy[size_t(li) * D * H * H + e] = a2[e] * inv_n2;
     // z: ghat[kz][ky][kx] / n^3

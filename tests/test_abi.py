@@ -61,7 +61,8 @@ def _problem(**kw):
     (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
     (dict(kernel="yukawa", screening=float("nan")), 1), (dict(abi=3), 1),
     (dict(abi=4), 1), (dict(m2l_mode=3), 1), (dict(extended=True, m2l="shared"), 6),
-    (dict(extended=True), 6), (dict(extended_id=2, m2l="cells"), 1), (dict(reserved=1), 1),
+    (dict(extended=True, ng=2), 6), (dict(extended=True, ng=3), 6), (dict(extended_id=2, m2l="cells"), 1),
+    (dict(reserved=1), 1),
     (dict(ng=8, m2l="cells"), 6), (dict(ng=8, m2l="shared"), 6),
 ])
 def test_bad_problem_rejected_on_host(kw, status):

@@ -125,10 +125,50 @@ def test_extended_gridlet_matches_oracle(name, ng, kern, prec):
     assert e_acc < tol["acc"]
 
 
-def test_extended_gridlet_needs_the_cell_route():
+def test_extended_gridlet_routes_and_orders():
+    # extended gridlets: cell route at every order, padded grid at N_g = 4 and 6, shared route
+    # never
     import torch
     from paper_1906_10734_amd import hpm
     p, kw = particles("plummer3000_cap16", "f64")
     x, y, z, m = device(p, torch)
-    with pytest.raises(RuntimeError, match="HPM_ERR_UNSUPPORTED"):
-        hpm.Plan(gpu_problem(4, "f64", kw, extended=True), x, y, z)
+    for ng, m2l in ((2, "grid"), (3, "grid"), (4, "shared")):
+        with pytest.raises(RuntimeError, match="HPM_ERR_UNSUPPORTED"):
+            hpm.Plan(gpu_problem(ng, "f64", kw, m2l=m2l, extended=True), x, y, z)
+
+
+# ---- extended target gridlets on the padded (8 N_g)^3 grid: window [(2+c) N_g - 1, (3+c) N_g + 1)
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,ng,kern", [
+    ("plummer3000_cap16", 4, {}),
+    ("clustered5000_cap8", 4, {}),
+    ("uniform4096_d3", 4, {}),
+    ("plummer3000_cap64", 6, {}),
+    ("plummer1000_cap1", 4, {}),
+    ("plummer3000_cap16", 4, dict(kernel="yukawa", screening=0.05)),
+])
+def test_extended_gridlet_on_grid_route_matches_oracle(name, ng, kern, prec):
+    # against the oracle's extended padded-grid mode (pinned to its direct sum), the same bar
+    log(f"[grid ext] {name} ng={ng} {prec} {kern}")
+    h, ophi, oacc = oracle(name, prec, ng, mode="fft", extended=True, **kern)
+    phi, acc, locs = _run(name, ng, prec, "grid", extended=True, **kern)
+    tol = TOL[prec]
+    olocs = h.all_locals()
+    for lvl in range(2, h.tree.max_level + 1):
+        assert locs[lvl].shape == olocs[lvl].shape == (len(olocs[lvl]), (ng + 2) ** 3)
+        assert rel_max(locs[lvl], olocs[lvl]) < tol["local"], ("locals", lvl)
+    e_phi, e_acc = rel_rms(phi, ophi), rel_rms(acc, oacc)
+    log(f"   phi rel rms {e_phi:.2e}  acc rel rms {e_acc:.2e}")
+    assert e_phi < tol["phi"]
+    assert e_acc < tol["acc"]
+
+
+@pytest.mark.parametrize("ng", [4, 6])
+def test_extended_grid_route_equals_extended_cell_route(ng):
+    phi_c, acc_c, loc_c = _run("plummer3000_cap16", ng, "f64", "cells", extended=True)
+    phi_g, acc_g, loc_g = _run("plummer3000_cap16", ng, "f64", "grid", extended=True)
+    for lvl in loc_c:
+        assert rel_max(loc_c[lvl], loc_g[lvl]) < 1e-12, lvl
+    assert rel_rms(phi_c, phi_g) < 1e-12
+    assert rel_rms(acc_c, acc_g) < 1e-11

@@ -4,8 +4,8 @@
 gridlet potentials of 48 target cells at levels >= 2, matched by level and integer coordinates.
 Every source-to-target route the benchmark times is checked: the padded grid, the cell-by-cell
 route and the route with the transform shared by siblings (against the same values: the oracle's
-modes agree to rounding), and the cell route with extended target gridlets (against the oracle's
-extended values).
+modes agree to rounding), and the padded grid and the cell route with extended target gridlets
+(against the oracle's extended values).
 
 Tolerances as in the small-case parity tests: FP64 path 1e-10 relative per particle (potential
 and acceleration), FP32 path 1e-5 relative RMS in potential (acceleration 1e-4, local gridlets
@@ -25,9 +25,9 @@ TOL = {"f64": dict(local=1e-10, phi=1e-10, acc=1e-9),
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("ng", [4, 6])
-def test_plummer2p18_sampled_outputs_match_oracle(ng, prec):
-    _check(ng, prec, "grid", False)
+@pytest.mark.parametrize("ng,extended", [(4, False), (6, False), (4, True), (6, True)])
+def test_plummer2p18_sampled_outputs_match_oracle(ng, extended, prec):
+    _check(ng, prec, "grid", extended)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
