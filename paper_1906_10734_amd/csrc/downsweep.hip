@@ -11,10 +11,11 @@
 //
 // Near zone. Under the cube-complete zones a coarse leaf next to a finely refined cube of its own
 // level sums over every particle in that cube, so the pair count per leaf is very uneven. The
-// near-zone sources of each leaf (27 contiguous sorted ranges) are cut into chunks of kP2PChunk;
-// one wave handles one (leaf, 64-target chunk, source chunk) item and writes partial sums, and a
-// per-leaf pass adds the partials in a fixed order (deterministic), adds the far field and
-// scatters the results to input order.
+// near-zone sources of each leaf (27 contiguous sorted ranges) are cut into chunks of kP2PChunk,
+// and its targets into pieces whose sizes keep a wave's lanes busy (target_pieces); one wave
+// handles one (leaf, target piece, source chunk) item and writes partial sums, and a per-leaf
+// pass adds the partials in a fixed order (deterministic), adds the far field and scatters the
+// results to input order.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
@@ -23,6 +24,31 @@
 namespace hpm {
 
 constexpr int kP2PChunk = 1024;
+
+// The targets of a leaf with K particles in pieces of at most 64: a wave splits its 64 lanes into
+// G = floor(64 / k) groups over the sources of a k-target piece, so k in 33..55 (G = 1, at most
+// 55 lanes busy) is cut as 32 + (k - 32), and 17..27 (G = 2 or 3) as 16 + (k - 16); larger leaves
+// start with pieces of 64. target_piece(K, t) gives the piece of target t: its index, first target
+// and size; target_pieces(K) their number.
+struct Piece {
+  int index, first, size;
+};
+
+__host__ __device__ __forceinline__ Piece target_piece(int K, int t) {
+  const int full = (K - 1) / 64;  // leading pieces of 64
+  if (t < 64 * full) return {t / 64, 64 * (t / 64), 64};
+  const int r = K - 64 * full, u = t - 64 * full;
+  int cut = 0;
+  if (r > 32 && r < 56) cut = 32;
+  else if (r > 16 && r < 28) cut = 16;
+  if (cut == 0) return {full, 64 * full, r};
+  return u < cut ? Piece{full, 64 * full, cut} : Piece{full + 1, 64 * full + cut, r - cut};
+}
+
+__host__ __device__ __forceinline__ int target_pieces(int K) {
+  const int full = (K - 1) / 64, r = K - 64 * full;
+  return full + ((r > 32 && r < 56) || (r > 16 && r < 28) ? 2 : 1);
+}
 
 template <typename T>
 __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
@@ -175,7 +201,7 @@ __global__ void k_near_items(NearArgs a, long long* pairs) {
   for (int k = 0; k < 27; ++k) S += a.near_re[li * 27 + k] - a.near_rb[li * 27 + k];
   const int g = a.leaves[li];
   const int K = a.pe[g] - a.pb[g];
-  const int nt = (K + 63) / 64, ns = (S + kP2PChunk - 1) / kP2PChunk;
+  const int nt = target_pieces(K), ns = (S + kP2PChunk - 1) / kP2PChunk;
   a.items[li] = nt * max(ns, 1);
   atomicAdd(reinterpret_cast<unsigned long long*>(pairs), (unsigned long long)K * S);
 }
@@ -189,10 +215,13 @@ __global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, co
   for (int k = 0; k < 27; ++k) S += near_re[li * 27 + k] - near_rb[li * 27 + k];
   const int g = leaves[li];
   const int K = pe[g] - pb[g];
-  const int nt = (K + 63) / 64, ns = max((S + kP2PChunk - 1) / kP2PChunk, 1);
+  const int ns = max((S + kP2PChunk - 1) / kP2PChunk, 1);
   int it = item_off[li];
-  for (int tc = 0; tc < nt; ++tc)
-    for (int sc = 0; sc < ns; ++sc) items[it++] = make_int4(li, tc * 64, sc * kP2PChunk, S);
+  for (int t = 0; t < K;) {
+    const Piece pc = target_piece(K, t);
+    for (int sc = 0; sc < ns; ++sc) items[it++] = make_int4(li, pc.first, pc.size, sc * kP2PChunk);
+    t = pc.first + pc.size;
+  }
 }
 
 static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
@@ -315,11 +344,12 @@ struct alignas(4 * sizeof(T)) SrcP {
   T x, y, z, m;
 };
 
-// Lanes split as (target tl < K, source group grp < 64/K) when the chunk has K < 64 targets
-// (lanes past the last whole group idle); sources are staged 64 at a time in LDS (position and
-// mass in one 4-vector), and the groups' partial sums are combined in group order through LDS.
-// The self pair is recognised by its place in the source sequence: the target leaf's own cube
-// is entry 13 of its 27 near cubes.
+// Item (leaf, first target t0, piece size kp, first source s0): lanes split as (target tl < kp,
+// source group grp < 64/kp) (lanes past the last whole group idle); sources are staged 64 at a
+// time in LDS (position and mass in one 4-vector). Each lane sums a tile's pair potentials in
+// plain arithmetic and adds the tile's sum to its running total with compensation (Kahan); the
+// groups' partial sums are combined in group order through LDS. The self pair is recognised by
+// its place in the source sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
 template <typename T, int KER>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
@@ -327,10 +357,9 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ T s_part[5][64];
   const int lane = threadIdx.x;
   const int4 it = a.items[blockIdx.x];
-  const int li = it.x, t0 = it.y, s0 = it.z, S = it.w;
+  const int li = it.x, t0 = it.y, kp = it.z, s0 = it.w;
   const int g = a.leaves[li];
   const int pb = a.pb[g];
-  const int K = min(64, a.pe[g] - pb - t0);
   if (lane < 27) s_rb[lane] = a.near_rb[li * 27 + lane];
   {
     const int len = (lane < 27) ? a.near_re[li * 27 + lane] - a.near_rb[li * 27 + lane] : 0;
@@ -343,7 +372,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     if (lane < 28) s_pre[lane] = x - len;  // exclusive prefix; s_pre[27] = total
   }
   __syncthreads();
-  const int kp = K;  // 1 .. 64
+  const int S = s_pre[27];
   const int G = 64 / kp;
   const int tl = lane % kp, grp = lane / kp;
   const int i = pb + t0 + tl;
@@ -357,23 +386,20 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   }
   T ph = T(0), phc = T(0), fx = T(0), fy = T(0), fz = T(0);
   const int s_end = min(S, s0 + kP2PChunk);
-  // the chunk's own targets occupy [self_lo, self_hi) of the source sequence
-  const int self_lo = s_pre[13] + (pb + t0 - s_rb[13]), self_hi = self_lo + K;
+  // the piece's own targets occupy [self_lo, self_hi) of the source sequence
+  const int self_lo = s_pre[13] + (pb + t0 - s_rb[13]), self_hi = self_lo + kp;
+  T pt = T(0);  // potential of the current tile
   auto pair = [&](const SrcP<T>& q, bool skip) {
     const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-    const T r2 = dx * dx + dy * dy + dz * dz + a.eps2;
+    const T r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, a.eps2)));
     const T inv = skip ? T(0) : inv_sqrt(r2);
     T w, c;
     pair_terms<KER>(r2, inv, a.inv_lam, w, c);
-    const T mi = q.m * w;
     const T mi3 = q.m * c;
-    const T yv = -mi - phc;  // Kahan: ph += -m w
-    const T tv = ph + yv;
-    phc = (tv - ph) - yv;
-    ph = tv;
-    fx -= mi3 * dx;
-    fy -= mi3 * dy;
-    fz -= mi3 * dz;
+    pt = fma(-q.m, w, pt);
+    fx = fma(-mi3, dx, fx);
+    fy = fma(-mi3, dy, fy);
+    fz = fma(-mi3, dz, fz);
   };
   for (int tile = s0; tile < s_end; tile += 64) {
     const int sidx = tile + lane;
@@ -391,12 +417,17 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     __syncthreads();
     const int cnt = min(64, s_end - tile);
     if (valid) {
+      pt = T(0);
       if (tile < self_hi && tile + cnt > self_lo) {  // the tile may hold the target itself
         for (int e = grp; e < cnt; e += G) pair(s_src[e], tile + e == self);
       } else {
 #pragma unroll 4
         for (int e = grp; e < cnt; e += G) pair(s_src[e], false);
       }
+      const T yv = pt - phc;  // Kahan: ph += pt
+      const T tv = ph + yv;
+      phc = (tv - ph) - yv;
+      ph = tv;
     }
   }
   if (G > 1) {
@@ -497,10 +528,11 @@ __global__ __launch_bounds__(64) void k_leaf(LeafArgs<T> a) {
   // near zone: partials of this particle's target chunk, source chunks in order
   T ph = T(0), phe = T(0), fx = T(0), fy = T(0), fz = T(0);
   if (valid) {
-    const int t = i - pb, nt = (K + 63) / 64, tc = t / 64;
-    const int ns = a.item_cnt[li] / nt;
+    const int t = i - pb;
+    const Piece pc = target_piece(K, t);
+    const int ns = a.item_cnt[li] / target_pieces(K);
     for (int sc = 0; sc < ns; ++sc) {
-      const T* q = a.partial + (size_t(a.item_off[li] + tc * ns + sc) * 64 + (t % 64)) * 5;
+      const T* q = a.partial + (size_t(a.item_off[li] + pc.index * ns + sc) * 64 + (t - pc.first)) * 5;
       T s, err;
       two_sum(ph, q[0], s, err);
       ph = s;
