@@ -18,10 +18,10 @@ Prints ONE JSON line. Two other workloads run on their own flag, each printing i
   --large   the 2^24-particle clustered set (N_g = 4, at most 32 per leaf) on each of the three
             source-to-target routes;
   --serve   a Poisson stream of solves (N log-uniform in [2^12, 2^20], uniform, Plummer or
-            clustered, force tolerance 1e-2 at N_g = 4 or 1e-4 at N_g = 6, extended gridlets on
-            the cell route) at 0.5, 0.7 and 0.9 of
-            the saturated rate: p50/p99 latency from submission to completion, particles/s, and
-            every result checked against its tolerance and against the same solve alone.
+            clustered, force tolerance 1e-4, N_g = 6 extended on the cell route or N_g = 8 on
+            the padded grid for sets of at most 2^16) at 0.5, 0.7 and 0.9 of the saturated rate:
+            p50/p99 latency from submission to completion, particles/s, and every result checked
+            against its tolerance and against the same solve alone.
 """
 from __future__ import annotations
 
@@ -37,9 +37,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published; counts packed two-wide FP32)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# the vector issue ceiling of code without packed FP32: 256 CUs x 4 SIMDs, one 64-lane
+# instruction per SIMD every 4 cycles, 2.4 GHz
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 78.6
 
 
 def m2l_flops_per_target(ng: int) -> float:
@@ -66,21 +70,35 @@ def source_sha(path: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(ng: int, prec: str):
-    """HBM bytes per M2L launch from committed rocprofv3 counter runs, if they were taken on the
-    current M2L source; else None."""
-    path = os.path.join(ROOT, "profiles", f"m2l_ng{ng}_{prec}_plummer2p18_counters.json")
+def counters_from_profile(name: str, source: str):
+    """Per-launch counter figures of one kernel from a committed rocprofv3 counter summary
+    (profiles/<name>.json), if they were taken on the current source file; else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1906_10734_amd", "csrc", "m2l.hip")
-    if rec.get("m2l_source_sha") != source_sha(src):
+    src = os.path.join(ROOT, "paper_1906_10734_amd", "csrc", source)
+    if rec.get("source_sha") != source_sha(src):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"os_cpu_count": os.cpu_count(), "affinity_cpus": aff, "model": model}
 
 
 def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, kernel="newton",
-             screening=0.0, m2l="grid", extended=False):
+             screening=0.0, m2l="grid", extended=False, overlap=True):
     """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
     p = parts.astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
@@ -88,6 +106,7 @@ def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, ker
     prob = hpm.Problem(ng=ng, precision=prec, leaf_capacity=64, max_depth=10, softening=1e-3,
                        kernel=kernel, screening=screening, m2l=m2l, extended=extended)
     plan = hpm.Plan(prob, x, y, z)
+    plan.set_overlap(overlap)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(warmup):
         plan.rebuild(x, y, z)
@@ -114,54 +133,97 @@ def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, ker
     return res, out, (x, y, z, m)
 
 
-def cpu_baseline(parts, ng: int, budget_s: float):
-    """The FP64 oracle (test infrastructure) on a bounded sample of the same workload, on one
-    host thread: tree + full up-sweep timed whole, source-to-target and parent-to-child timed on
-    a random sample of targets, near zone + interpolation on a random sample of leaves, each
-    scaled to the full counts."""
+_ORACLE = {}  # the oracle's evaluation object, shared with forked workers (copy on write)
+
+
+def _oracle_sample(args):
+    """Times the oracle's per-target (source-to-target + parent-to-child) or per-leaf (near zone
+    + interpolation) work on a random sample until the deadline; returns (items, seconds)."""
+    kind, seed, budget = args
+    from threadpoolctl import threadpool_limits
+    from oracle import hpm as ohpm
+    h, targets, leaves, ng = (_ORACLE[k] for k in ("h", "targets", "leaves", "ng"))
+    t = h.tree
+    rng = np.random.default_rng(seed)
+    n_done, spent = 0, 0.0
+    deadline = time.perf_counter() + budget
+    with threadpool_limits(1):
+        if kind == "m2l":
+            for k in rng.permutation(len(targets)):
+                l, i = targets[k]
+                a = time.perf_counter()
+                phi = h.m2l(l, t.levels[l].coords[i])
+                if l > 2:
+                    ohpm.l2l(phi, int(t.levels[l].keys[i] & 7), ng)
+                spent += time.perf_counter() - a
+                n_done += 1
+                if time.perf_counter() > deadline and n_done >= 4:
+                    break
+        else:
+            for k in rng.permutation(len(leaves)):
+                l, i = leaves[k]
+                lev = t.levels[l]
+                if l >= 2:
+                    h.local(l, i)  # chain of locals (its targets' work is counted by "m2l")
+                a = time.perf_counter()
+                h.leaf_fields(l, i, np.arange(lev.pb[i], lev.pe[i]))
+                spent += time.perf_counter() - a
+                n_done += 1
+                if time.perf_counter() > deadline and n_done >= 4:
+                    break
+    return n_done, spent
+
+
+def cpu_baseline(parts, ng: int, budget_s: float, workers: int):
+    """The FP64 oracle (test infrastructure, as it stands) on a bounded sample of the same
+    workload: tree + full up-sweep timed whole on one thread (the oracle's up-sweep is a serial
+    loop); source-to-target + parent-to-child on random samples of targets and near zone +
+    interpolation on random samples of leaves, run by `workers` forked processes side by side
+    (one thread each), their combined rate taken from the wall clock; scaled to the full solve.
+    Call it before the process touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     from oracle import hpm as ohpm
     p = parts.as_f64()
-    rng = np.random.default_rng(7)
     with threadpool_limits(1):
         prob = ohpm.Problem(ng=ng, softening=1e-3, leaf_capacity=64, max_depth=10)
         t0 = time.perf_counter()
         h = ohpm.HPM(p.x, p.y, p.z, p.m, prob, mode="fft")
         t_up = time.perf_counter() - t0
-        t = h.tree
-        targets = [(l, i) for l in range(2, t.max_level + 1) for i in range(len(t.levels[l]))]
-        leaves = list(t.leaves())
-        deadline = time.perf_counter() + budget_s / 2
-        order = rng.permutation(len(targets))
-        n_m2l, t_m2l = 0, 0.0
-        for k in order:
-            l, i = targets[k]
-            a = time.perf_counter()
-            phi = h.m2l(l, t.levels[l].coords[i])
-            if l > 2:
-                ohpm.l2l(phi, int(t.levels[l].keys[i] & 7), ng)
-            t_m2l += time.perf_counter() - a
-            n_m2l += 1
-            if time.perf_counter() > deadline and n_m2l >= 8:
-                break
-        deadline = time.perf_counter() + budget_s / 2
-        n_leaf, t_leaf = 0, 0.0
-        for k in rng.permutation(len(leaves)):
-            l, i = leaves[k]
-            lev = t.levels[l]
-            if l >= 2:
-                h.local(l, i)  # chain of locals (not timed here; counted above per target)
-            a = time.perf_counter()
-            h.leaf_fields(l, i, np.arange(lev.pb[i], lev.pe[i]))
-            t_leaf += time.perf_counter() - a
-            n_leaf += 1
-            if time.perf_counter() > deadline and n_leaf >= 8:
-                break
-    est = t_up + len(targets) * t_m2l / n_m2l + len(leaves) * t_leaf / n_leaf
-    return {"value": p.n / est, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": (f"tree+P2M+M2M over all {p.n} particles ({t_up:.1f} s); M2L+L2L on "
-                       f"{n_m2l} of {len(targets)} targets; L2P+P2P on {n_leaf} of {len(leaves)} "
-                       f"leaves; scaled to the full solve ({est:.1f} s est.)")}
+    t = h.tree
+    _ORACLE.update(h=h, ng=ng, leaves=list(t.leaves()),
+                   targets=[(l, i) for l in range(2, t.max_level + 1) for i in range(len(t.levels[l]))])
+    rates = {}
+    for kind in ("m2l", "leaf"):
+        jobs = [(kind, 7 + 101 * w, budget_s / 2) for w in range(workers)]
+        t0 = time.perf_counter()
+        if workers == 1:
+            res = [_oracle_sample(jobs[0])]
+        else:
+            with mp.get_context("fork").Pool(workers) as pool:
+                res = pool.map(_oracle_sample, jobs)
+        wall = time.perf_counter() - t0
+        rates[kind] = (sum(r[0] for r in res), wall)
+    n_t, n_l = len(_ORACLE["targets"]), len(_ORACLE["leaves"])
+    est = t_up + n_t * rates["m2l"][1] / rates["m2l"][0] + n_l * rates["leaf"][1] / rates["leaf"][0]
+    _ORACLE.clear()
+    return {"value": round(p.n / est, 2), "unit": "particles/s", "cores": workers, "kind": "oracle",
+            "sample": (f"tree+P2M+M2M over all {p.n} particles on one thread ({t_up:.1f} s); "
+                       f"M2L+L2L on {rates['m2l'][0]} of {n_t} targets and L2P+P2P on "
+                       f"{rates['leaf'][0]} of {n_l} leaves by {workers} process(es) in "
+                       f"{rates['m2l'][1]:.1f} + {rates['leaf'][1]:.1f} s of wall clock; scaled "
+                       f"to the full solve ({est:.1f} s est.)")}
+
+
+def run_info_targets(hpm, torch, parts, ng):
+    """Number of source-to-target targets of a set's tree (one FP32 plan build)."""
+    p = parts.astype(np.float32)
+    x, y, z, _ = _device_set(torch, p, torch.float32)
+    plan = hpm.Plan(hpm.Problem(ng=ng, precision="f32", leaf_capacity=64, max_depth=10,
+                                softening=1e-3), x, y, z)
+    n_t = plan.info()["n_targets"]
+    plan.close()
+    return n_t
 
 
 def _device_set(torch, p, dt):
@@ -241,12 +303,19 @@ def serve_bench(args):
     for i, r in enumerate(pool):
         p = request_particles(r).astype(np.float32)
         dev = _device_set(torch, p, torch.float32)
-        # the order for the request's tolerance: the cheapest form whose force error on the 2^18
-        # Plummer workload is at least 4x below it (the extended gridlet on the cell route: 2.7e-4
-        # at N_g = 4, 1.7e-5 at N_g = 6; the standard N_g = 6 gridlet, 8e-5, leaves no margin)
-        ng = 4 if r["tolerance"] >= 1e-2 else 6
-        prob = hpm.Problem(ng=ng, precision="f32", leaf_capacity=64, max_depth=10, softening=1e-3,
-                           m2l="cells", extended=True)
+        # the form for the request's 1e-4 tolerance: by default the extended N_g = 6 gridlet on
+        # the cell route (1.7e-5 on the 2^18 Plummer workload, 6x below the tolerance; the
+        # standard N_g = 6 gridlet, 8e-5, leaves no margin, and no N_g = 4 form reaches 1e-4);
+        # sets of at most 2^16 particles whose request asks for order 8 take N_g = 8 on the
+        # padded grid (the library's N_g = 8 limit)
+        if r["order8"]:
+            ng = 8
+            prob = hpm.Problem(ng=8, precision="f32", leaf_capacity=64, max_depth=10,
+                               softening=1e-3)
+        else:
+            ng = 6
+            prob = hpm.Problem(ng=6, precision="f32", leaf_capacity=64, max_depth=10,
+                               softening=1e-3, m2l="cells", extended=True)
         sub = torch.tensor(random_subset(r["n"], 256, 6000 + i), device="cuda")
         _, rx, ry, rz = hpm.direct_sum(*dev, sub, 1.0, 1e-3)
         solo = hpm.solve(prob, *dev)
@@ -318,9 +387,12 @@ def serve_bench(args):
     rec = {"mode": "serve", "metric": "solve p50/p99 latency under a Poisson request stream",
            "unit": "ms", "dtype": "f32", "data": "synthetic (seeded uniform, Plummer, clustered)",
            "config": {"workload": "Poisson arrivals, N log-uniform 2^12..2^20, uniform/Plummer/"
-                                  "clustered, tolerance 1e-2 (N_g=4) or 1e-4 (N_g=6), extended "
-                                  "gridlets on the cell route, leaf<=64, eps=1e-3",
+                                  "clustered, relative force tolerance 1e-4 for every request, "
+                                  "N_g = 6 extended on the cell route or (N <= 2^16, seeded coin) "
+                                  "N_g = 8 on the padded grid, leaf<=64, eps=1e-3",
                       "pool": len(pool), "slots": args.slots,
+                      "orders": {"ng6_extended": sum(1 for r in pool if r["ng"] == 6),
+                                 "ng8": sum(1 for r in pool if r["ng"] == 8)},
                       "hbm_budget_gib": args.serve_budget_gib},
            "results": out, "server": stats,
            "pool_over_tolerance": [{k: r[k] for k in ("kind", "n", "ng", "tolerance",
@@ -344,7 +416,7 @@ def large_bench(args):
     _, rx, ry, rz = hpm.direct_sum(x.double(), y.double(), z.double(), m.double(), sub, 1.0, 1e-3)
     ref = torch.stack([rx, ry, rz], 1)
     routes = {}
-    for route in ("grid", "shared", "cells"):
+    for route in getattr(args, "large_routes", "grid,shared,cells").split(","):
         plan = hpm.Plan(hpm.Problem(ng=4, precision="f32", leaf_capacity=32, max_depth=10,
                                     softening=1e-3, m2l=route), x, y, z)
         out = [torch.empty_like(m) for _ in range(4)]
@@ -382,13 +454,17 @@ def main():
     ap.add_argument("--n", type=int, default=2 ** 18)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="most host processes of the all-core CPU baseline")
     ap.add_argument("--sweep-steps", type=int, default=3,
                     help="timed solves per point of the gridlet-order accuracy sweep")
     ap.add_argument("--profile", action="store_true",
                     help="FP32 steps only, then a device copy of 256 MiB (counter calibration)")
     ap.add_argument("--m2l", choices=("grid", "cells", "shared"), default="grid",
                     help="source-to-target route of the --profile run")
+    ap.add_argument("--in-line", action="store_true",
+                    help="--profile: near-zone sums in line after the source-to-target step")
     ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
                     help="precision of the --profile run")
     ap.add_argument("--batch", action="store_true", help="the batched workload instead")
@@ -416,15 +492,25 @@ def main():
         print(json.dumps(serve_bench(args)))
         return
 
-    import torch
-    from paper_1906_10734_amd import hpm
     from synth import plummer_sphere, random_subset
 
     parts = plummer_sphere(args.n, 1001)
     ng = args.ng
+    # the CPU oracle first, before this process touches the GPU (its workers are forked)
+    cpu = None
+    if not args.no_cpu_baseline and not args.profile:
+        host = cpu_info()
+        share = min(host["affinity_cpus"] or host["os_cpu_count"] or 1, args.cpu_workers)
+        cpu = {"all_cores": cpu_baseline(parts, ng, args.cpu_seconds, share),
+               "one_core": cpu_baseline(parts, ng, args.cpu_seconds, 1), "host": host}
+        print(f"[cpu] {cpu['all_cores']['value']} particles/s on {share} cores, "
+              f"{cpu['one_core']['value']} on one", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1906_10734_amd import hpm
     if args.profile:
         r32, _, _ = run_path(hpm, torch, parts, args.precision, ng, args.steps, args.warmup,
-                             m2l=args.m2l)
+                             m2l=args.m2l, overlap=not args.in_line)
         src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -471,23 +557,54 @@ def main():
     phi_f32_vs_f64 = float(((out32[0].double() - out64[0]).norm() / out64[0].norm()))
 
     n_t = r32["info"]["n_targets"]
+    # the M2L stage of the grid route is one launch of the z-slab kernel, bracketed by HIP events on
+    # the stream it is launched on (the near-zone sums run beside it on the plan's second stream)
     m2l_ms = r32["stages"]["m2l"] / max(r32["stages"]["n_exec"], 1)
     flops = m2l_flops_per_target(ng) * n_t
     nbytes = m2l_bytes_per_target(ng, 4) * n_t
     gbs = nbytes / (m2l_ms * 1e-3) / 1e9
     tflops = flops / (m2l_ms * 1e-3) / 1e12
-    kernel = "k_m2l_slab<float,%d>" % ng if ng in (6,) else "k_m2l<float,%d>" % ng
+    kernel = f"k_m2l_slab<float, {ng}, 0>" if ng >= 4 else f"k_m2l<float, {ng}>"
+    ctr = counters_from_profile(f"m2l_ng{ng}_f32_plummer2p18_counters", "m2l.hip")
+    valu = None
+    if ctr and ctr.get("valu_insts_per_launch"):
+        issue_s = ctr["valu_insts_per_launch"] * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ)
+        valu = {"insts_per_launch": ctr["valu_insts_per_launch"],
+                "issue_frac": round(issue_s / (m2l_ms * 1e-3), 4),
+                "source": f"profiles/m2l_ng{ng}_f32_plummer2p18_counters.md"}
     # The FP32 source-to-target kernel keeps its whole transform on chip (LDS and registers); its
     # HBM traffic is the source gridlets and the outputs, so the bound is the vector ALU. The
-    # algorithmic work is the FFT-convention count of one zero-padded transform per target.
+    # algorithmic work is the FFT-convention count of one zero-padded transform per target; the
+    # kernel prunes zero lines and does z in real space, so that count is nominal and the
+    # executed-instruction share of the vector issue ceiling (valu.issue_frac) is the utilisation.
     roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic_from_profile(ng, "f32"), "kernel": kernel,
-                "launch_ms": round(m2l_ms, 4), "targets_per_launch": n_t,
-                "flops_per_target": m2l_flops_per_target(ng),
+                "traffic": ctr.get("bytes_per_launch") if ctr else None, "kernel": kernel,
+                "launch_ms": round(m2l_ms, 4), "launches": r32["stages"]["n_exec"],
+                "targets_per_launch": n_t, "flops_per_target": m2l_flops_per_target(ng),
+                "peak_unpacked_fp32": round(PEAK_FP32_UNPACKED_TFLOPS, 1),
+                "frac_unpacked": round(tflops / PEAK_FP32_UNPACKED_TFLOPS, 4), "valu": valu,
                 "effective_hbm": {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                   "frac": round(gbs / PEAK_HBM_GBS, 4),
                                   "bytes_per_target": m2l_bytes_per_target(ng, 4)}}
+
+    # the near-zone sums (P2P, on the plan's second stream beside M2L): pairs per second and the
+    # 20-flop-per-pair N-body convention against the FP32 peaks
+    pairs = r32["info"]["p2p_pairs"]
+    p2p_ms = r32["stages"]["p2p"] / max(r32["stages"]["n_exec"], 1)
+    p2p_tf = pairs * 20.0 / (p2p_ms * 1e-3) / 1e12
+    pctr = counters_from_profile("p2p_f32_plummer2p18_counters", "downsweep.hip")
+    near_zone = {"kernel": "k_p2p<float, 0>", "pairs": pairs, "launch_ms": round(p2p_ms, 4),
+                 "pairs_per_s": round(pairs / (p2p_ms * 1e-3), 1),
+                 "achieved_tflops_20_per_pair": round(p2p_tf, 3),
+                 "frac": round(p2p_tf / PEAK_FP32_TFLOPS, 4),
+                 "frac_unpacked": round(p2p_tf / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                 "note": "timed on its own stream while the source-to-target kernel runs beside it"}
+    if pctr and pctr.get("valu_insts_per_launch"):
+        near_zone["valu"] = {"insts_per_launch": pctr["valu_insts_per_launch"],
+                             "alone_ms": pctr.get("alone_ms"),
+                             "issue_frac_alone": pctr.get("issue_frac_alone"),
+                             "source": "profiles/p2p_f32_plummer2p18_counters.md"}
 
     value = args.n / (r32["ms_per_step"] * 1e-3)
     v64 = args.n / (r64["ms_per_step"] * 1e-3)
@@ -502,6 +619,28 @@ def main():
                "ms_per_step": round(r4["ms_per_step"], 4), "force_err_rms": e4[0],
                "fp64": {"value": round(args.n / (r4d["ms_per_step"] * 1e-3), 1),
                         "ms_per_step": round(r4d["ms_per_step"], 4), "force_err_rms": e4d[0]}}
+
+    # N_g = 8 (the other order the configuration names), on the 2^16-particle Plummer sphere (the
+    # library limits N_g = 8 to 2^16 particles), beside N_g = 6 on the same set; force errors
+    # against the FP64 direct sum on 4096 sampled particles
+    n8 = 2 ** 16
+    parts8 = plummer_sphere(n8, 1001)
+    sub8 = torch.tensor(random_subset(n8, 4096, 2002), device="cuda")
+    p8 = parts8.as_f64()
+    d8 = _device_set(torch, p8, torch.float64)
+    _, r8x, r8y, r8z = hpm.direct_sum(*d8, sub8, 1.0, 1e-3)
+    ref8 = torch.stack([r8x, r8y, r8z], 1)
+    ng8 = {"workload": f"plummer sphere N={n8} a=0.05 r_t=0.5, leaf<=64, depth<=10, eps=1e-3"}
+    for g in (8, 6):
+        for pr, st in (("f32", args.steps), ("f64", args.fp64_steps)):
+            r8, o8, _ = run_path(hpm, torch, parts8, pr, g, st, 1)
+            ng8[f"ng{g}_{pr}"] = {"value": round(n8 / (r8["ms_per_step"] * 1e-3), 1),
+                                  "ms_per_step": round(r8["ms_per_step"], 4),
+                                  "m2l_ms": round(r8["stages"]["m2l"] / max(r8["stages"]["n_exec"], 1), 4),
+                                  "force_err_rms": _force_err(torch, o8, sub8, ref8)}
+    ng8["m2l_kernel_tflops_fft_convention_f32"] = round(
+        m2l_flops_per_target(8) * run_info_targets(hpm, torch, parts8, 8)
+        / (ng8["ng8_f32"]["m2l_ms"] * 1e-3) / 1e12, 3)
 
     # the cell-by-cell source-to-target route (Sec. 2.5) on the same workload: whole-solve rate,
     # its source-to-target stage time beside the padded grid's, and the force error
@@ -541,12 +680,14 @@ def main():
     # the extended target gridlet (Sec. 2.5, N_g + 2 nodes per axis) on the cell route, at this
     # order and at N_g = 4: rate and force error beside the standard gridlet's
     for g in sorted({ng, 4}):
-        for pr, st in (("f32", args.steps), ("f64", args.fp64_steps)):
-            re_, oe, _ = run_path(hpm, torch, parts, pr, g, st, 1, m2l="cells", extended=True)
-            routes[f"cells_extended_ng{g}_{pr}"] = {
-                "value": round(args.n / (re_["ms_per_step"] * 1e-3), 1),
-                "ms_per_step": round(re_["ms_per_step"], 4), "m2l_ms": round(stage(re_, "m2l"), 4),
-                "leaf_ms": round(stage(re_, "leaf"), 4), "force_err_rms": ferr(oe)[0]}
+        for route in ("cells", "grid"):
+            for pr, st in (("f32", args.steps), ("f64", args.fp64_steps)):
+                re_, oe, _ = run_path(hpm, torch, parts, pr, g, st, 1, m2l=route, extended=True)
+                routes[f"{route}_extended_ng{g}_{pr}"] = {
+                    "value": round(args.n / (re_["ms_per_step"] * 1e-3), 1),
+                    "ms_per_step": round(re_["ms_per_step"], 4),
+                    "m2l_ms": round(stage(re_, "m2l"), 4),
+                    "leaf_ms": round(stage(re_, "leaf"), 4), "force_err_rms": ferr(oe)[0]}
 
     # accuracy sweep over the gridlet order (the paper's accuracy-versus-cost comparison, Sec. 3.2):
     # force error against the direct sum and time per solve, both precisions on the padded grid,
@@ -609,23 +750,28 @@ def main():
         "stage_ms_per_step": {k: round(v / max(r32["stages"]["n_exec"], 1), 4)
                               for k, v in r32["stages"].items() if k not in ("n_exec", "n_build")},
         "roofline": roofline,
+        "near_zone": near_zone,
         "kernels": {"yukawa_f32": yukawa},
-        "other_orders": {"ng4": ng4},
+        "other_orders": {"ng4": ng4, "ng8": ng8},
         "m2l_routes": routes,
         "accuracy_sweep": sweep,
         "small_solve": small,
     }
     rec["stage_ms_per_step"]["tree"] = round(r32["stages"]["tree"] / max(r32["stages"]["n_build"], 1), 4)
-    # the batched and served workloads, shortened (their own flags run them in full)
-    for key, fn, kw in (("batched", batch_bench, dict(steps=2)),
-                        ("served", serve_bench, dict(serve_requests=300))):
+    # the large clustered set (2^24 particles), and the batched and served workloads (the batch
+    # shortened to two timed batches; their own flags run them in full)
+    for key, fn, kw in (("large", large_bench, dict(steps=3, large_routes="grid,shared,cells")),
+                        ("batched", batch_bench, dict(steps=2)),
+                        ("served", serve_bench, dict())):
         try:
             sub_args = argparse.Namespace(**{**vars(args), **kw})
             rec[key] = fn(sub_args)
         except Exception as e:  # a failure here must not hide the main measurement
             rec[key] = {"error": f"{type(e).__name__}: {e}"}
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(parts, ng, args.cpu_seconds)
+    if cpu is not None:
+        rec["cpu_baseline"] = dict(cpu["all_cores"])
+        rec["cpu_baseline"]["one_core"] = cpu["one_core"]
+        rec["cpu_baseline"]["host"] = cpu["host"]
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec))

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HPM_ABI_VERSION 5
+#define HPM_ABI_VERSION 6
 
 typedef enum {
   HPM_OK = 0,
@@ -198,9 +198,12 @@ hpm_status hpm_plan_rebuild(hpm_plan* plan, int64_t n, const void* x, const void
  * Per-stage timing with HIP events recorded on the caller's stream (off by default).
  * hpm_plan_enable_timing(plan, 1) clears the totals and starts recording; 0 stops it.
  * hpm_plan_stage_times waits for every recorded execution and returns accumulated
- * milliseconds in ms[6] (host): [0] tree build (create/rebuild), [1] P2M (moments + fit GEMM,
- * with the mass gather), [2] M2M, [3] M2L, [4] L2L, [5] leaves (L2P + P2P); *n_exec and
- * *n_build (host, may be NULL) receive the number of executions and builds timed.
+ * milliseconds in ms[7] (host): [0] tree build (create/rebuild), [1] P2M (moments + fit GEMM,
+ * with the mass gather), [2] M2M, [3] M2L, [4] L2L, [5] leaves (L2P and the combination with
+ * the near zone, plus the wait for the near-zone sums when they ran on the plan's second
+ * stream), [6] the near-zone sums themselves (P2P, timed on the stream that ran them, beside
+ * [3] and [4] from 2^16 particles on); *n_exec and *n_build (host, may be NULL) receive the
+ * number of executions and builds timed.
  */
 hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on);
 hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int64_t* n_build);
@@ -214,6 +217,16 @@ hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int
  * Errors: HPM_ERR_INVALID_ARG (NULL plan, unknown mode), HPM_ERR_UNSUPPORTED (route not built).
  */
 hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode);
+
+/*
+ * Where the near-zone sums of later evaluations run: on = 1 (the default) puts them on a second
+ * stream of the plan beside the source-to-target step from 2^16 particles on (they need only the
+ * tree and the masses), on = 0 keeps them in line on the caller's stream after it. The results
+ * are the same either way; in line, the near-zone time of hpm_plan_stage_times is that of the
+ * kernel alone.
+ * Errors: HPM_ERR_INVALID_ARG (NULL plan, on not 0 or 1).
+ */
+hpm_status hpm_plan_set_overlap(hpm_plan* plan, int32_t on);
 
 /*
  * Chooses the route by measurement: for every route the plan can use, one untimed evaluation

@@ -163,6 +163,10 @@ static void drain_one(Plan& p) {
     HPM_HIP(hipEventElapsedTime(&ms, p.ev[slot][k], p.ev[slot][k + 1]));
     p.stage_ms[k + 1] += ms;
   }
+  float pm = 0.f;
+  HPM_HIP(hipEventSynchronize(p.p2p_ev[slot][1]));
+  HPM_HIP(hipEventElapsedTime(&pm, p.p2p_ev[slot][0], p.p2p_ev[slot][1]));
+  p.stage_ms[Plan::kStages + 1] += pm;
   p.n_exec += 1;
   p.ring_count -= 1;
 }
@@ -173,9 +177,11 @@ constexpr int64_t kForkMinParticles = int64_t(1) << 16;
 void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* az,
                   hipStream_t s) {
   hipEvent_t* ev = nullptr;
+  hipEvent_t* pev = nullptr;
   if (p.timing) {
     if (p.ring_count == Plan::kRing) drain_one(p);
     ev = p.ev[p.ring_head];
+    pev = p.p2p_ev[p.ring_head];
     p.ring_head = (p.ring_head + 1) % Plan::kRing;
     p.ring_count += 1;
     HPM_HIP(hipEventRecord(ev[0], s));
@@ -188,11 +194,13 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
   // the near zone needs only the tree and the sorted masses: for large problems it runs on the
   // side stream beside the source-to-target step (which leaves ALU and memory slots idle) and
   // the leaf pass waits for it; small ones keep it in line, where the fork costs more than it hides
-  const bool fork = p.n >= kForkMinParticles && p.side;
+  const bool fork = p.overlap && p.n >= kForkMinParticles && p.side;
   if (fork) {
     HPM_HIP(hipEventRecord(p.fork_ev, s));
     HPM_HIP(hipStreamWaitEvent(p.side, p.fork_ev, 0));
+    if (pev) HPM_HIP(hipEventRecord(pev[0], p.side));
     launch_p2p(p, p.side);
+    if (pev) HPM_HIP(hipEventRecord(pev[1], p.side));
     HPM_HIP(hipEventRecord(p.join_ev, p.side));
   }
   if (p.route == HPM_M2L_CELLS) launch_m2l_cells(p, s);
@@ -201,8 +209,13 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
   if (ev) HPM_HIP(hipEventRecord(ev[3], s));
   for (int l = 2; l < p.nlevels; ++l) launch_l2l(p, l, s);  // level 2: re-centring only
   if (ev) HPM_HIP(hipEventRecord(ev[4], s));
-  if (fork) HPM_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
-  else launch_p2p(p, s);
+  if (fork) {
+    HPM_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
+  } else {
+    if (pev) HPM_HIP(hipEventRecord(pev[0], s));
+    launch_p2p(p, s);
+    if (pev) HPM_HIP(hipEventRecord(pev[1], s));
+  }
   launch_leaf(p, phi, ax, ay, az, s);
   if (ev) HPM_HIP(hipEventRecord(ev[5], s));
 }
@@ -210,7 +223,7 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
 size_t Plan::device_bytes() const {
   const DevBuf* bufs[] = {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
-      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vids, &vtmp, &blocks, &dlevel, &dlev, &gridlet,
+      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &blocks, &dlevel, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
       &cell_pflag, &cell_ppos, &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
@@ -261,6 +274,9 @@ Plan::~Plan() {
   if (hbox && !noalloc) (void)hipHostFree(hbox);
   if (events_created) {
     for (auto& set : ev)
+      for (auto& e : set)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& set : p2p_ev)
       for (auto& e : set)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : tree_ev)
@@ -342,6 +358,14 @@ hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode) {
   });
 }
 
+hpm_status hpm_plan_set_overlap(hpm_plan* plan, int32_t on) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (on != 0 && on != 1) fail(HPM_ERR_INVALID_ARG, "on must be 0 or 1");
+    plan->p.overlap = on != 0;
+  });
+}
+
 hpm_status hpm_plan_autotune(hpm_plan* plan, const void* m, void* phi, void* ax, void* ay,
                              void* az, int32_t reps, void* stream, int32_t* mode, double* ms) {
   return guarded([&] {
@@ -406,6 +430,8 @@ hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on) {
     if (on && !p.events_created) {
       for (auto& set : p.ev)
         for (auto& e : set) HPM_HIP(hipEventCreate(&e));
+      for (auto& set : p.p2p_ev)
+        for (auto& e : set) HPM_HIP(hipEventCreate(&e));
       for (auto& e : p.tree_ev) HPM_HIP(hipEventCreate(&e));
       p.events_created = true;
     }
@@ -421,7 +447,7 @@ hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int
     if (!plan || !ms) fail(HPM_ERR_INVALID_ARG, "NULL argument");
     Plan& p = plan->p;
     while (p.ring_count > 0) drain_one(p);
-    for (int k = 0; k <= Plan::kStages; ++k) ms[k] = p.stage_ms[k];
+    for (int k = 0; k <= Plan::kStages + 1; ++k) ms[k] = p.stage_ms[k];
     if (n_exec) *n_exec = p.n_exec;
     if (n_build) *n_build = p.n_build;
   });

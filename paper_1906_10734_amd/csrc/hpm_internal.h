@@ -172,10 +172,13 @@ struct Plan {
   DevBuf leaves;
   // virtual cubes (interaction-zone cubes inside coarser leaves), cell ids ncells .. ncells+nvirt-1
   int64_t nvirt = 0;
-  DevBuf vkeys;   // [nvirt] sorted cube ids (1 << 3l | level-l Morton key)
+  DevBuf vkeys;   // [nvirt] cube ids (1 << 3l | level-l Morton key), in the order found
   DevBuf vlevel;  // [nvirt] level
   DevBuf vlist;   // [nvirt] cell id ncells + v
-  DevBuf vids, vtmp;  // enumeration scratch
+  // the set of virtual cube ids while they are listed: open addressing, 2^vhash_bits slots of
+  // (id, v), grown when a build overflows it
+  DevBuf vhash_keys, vhash_vals;
+  int vhash_bits = 0;
   // source gridlet ids of the 216 block slots of each parent of targets (cells of levels
   // 1 .. L-2, from id blocks_first on)
   DevBuf blocks;
@@ -212,6 +215,8 @@ struct Plan {
   static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
   static constexpr int kBoxCellLevels = 4;  // words 5 .. 4 + L-1: split-parent list bounds
   static constexpr int kBoxLeaves = 16;     // leaf count (read after the first virtual-cube step)
+  static constexpr int kBoxVirt = 17;       // virtual cubes listed
+  static constexpr int kBoxVirtFull = 18;   // the virtual-cube set overflowed
   static constexpr int kBoxLev = 24;        // words 24 .. 63: copy of the device level table
   int* hbox = nullptr;
   int* dbox = nullptr;
@@ -224,6 +229,7 @@ struct Plan {
   // chain of an execution, with the events that fork it from and join it to the caller's stream
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool overlap = true;  // run the near zone on "side" (from kForkMinParticles particles on)
 
   // stage timing with HIP events (off unless enabled): a ring of pending executions
   static constexpr int kStages = 5;   // P2M, M2M, M2L, L2L, leaves
@@ -231,9 +237,10 @@ struct Plan {
   bool timing = false;
   bool events_created = false;
   hipEvent_t ev[kRing][kStages + 1] = {};
+  hipEvent_t p2p_ev[kRing][2] = {};  // around the near-zone sums, on the stream that runs them
   hipEvent_t tree_ev[2] = {};
   int ring_head = 0, ring_count = 0;
-  double stage_ms[kStages + 1] = {0};  // [0] tree build, [1..] execute stages
+  double stage_ms[kStages + 2] = {0};  // [0] tree build, [1..5] execute stages, [6] near zone
   int64_t n_exec = 0, n_build = 0;
   ~Plan();
 

@@ -94,8 +94,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* 
 constexpr int kScanSingleThreads = 1024;
 constexpr int kScanSingleMax = kScanSingleThreads * kScanItems;
 
-__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* in, int* out, int n,
-                                                                    const int* dn, int* total_out) {
+// the body of k_scan_single (one workgroup of kScanSingleThreads threads)
+__device__ __forceinline__ void scan_single(const int* in, int* out, int n, const int* dn,
+                                            int* total_out) {
   __shared__ int s_wave[kScanSingleThreads / 64];
   __shared__ int s_run;
   n = scan_len(n, dn);
@@ -135,6 +136,11 @@ __global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* i
     __syncthreads();
   }
   if (total_out && threadIdx.x == 0) *total_out = s_run;
+}
+
+__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* in, int* out, int n,
+                                                                    const int* dn, int* total_out) {
+  scan_single(in, out, n, dn, total_out);
 }
 
 static size_t scan_tmp_ints(int n) {
@@ -401,9 +407,9 @@ __device__ void level_nbr(int l, int off, int cnt, CellArrays c);
 // (key-sorted) range. Grid-stride over the level's cells (count from the level table). For
 // l >= 1 the same launch first fills the level's 27-cube neighbourhoods (they read only level
 // l-1, which the previous launches completed).
-__global__ void k_level_split(int l, int depth, int uniform, int cap, const int* lev,
-                              const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
-  if (lev[kLevOverflow] >= 0) return;
+__device__ __forceinline__ void level_split(int l, int depth, int uniform, int cap, const int* lev,
+                                            const uint32_t* keys, CellArrays c, int* bounds,
+                                            int* nchild) {
   const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
   if (l >= 1) level_nbr(l, off, cnt, c);
   for (int64_t t0 = int64_t(blockIdx.x) * blockDim.x; t0 < int64_t(cnt) * 8;
@@ -439,12 +445,17 @@ __global__ void k_level_split(int l, int depth, int uniform, int cap, const int*
   }
 }
 
+__global__ void k_level_split(int l, int depth, int uniform, int cap, const int* lev,
+                              const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
+  if (lev[kLevOverflow] >= 0) return;
+  level_split(l, depth, uniform, cap, lev, keys, c, bounds, nchild);
+}
+
 // Children of the cells of level l at ids off_next + childoff[i] + r (the scan of the split
 // counts left the number of level-(l+1) cells in the table); flags the overflow instead when they
 // do not fit in cap cells.
-__global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, const int* childoff,
-                             CellArrays c) {
-  if (lev[kLevOverflow] >= 0) return;
+__device__ __forceinline__ void level_emit(int l, int cap_cells, int* lev, const int* bounds,
+                                           const int* childoff, CellArrays c) {
   const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l], total = lev[kLevCnt + l + 1];
   const int off_next = off + cnt;
   if (int64_t(off_next) + total > cap_cells) {
@@ -473,6 +484,30 @@ __global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, 
       c.child8[g * 8 + k] = id;
     }
   }
+}
+
+__global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, const int* childoff,
+                             CellArrays c) {
+  if (lev[kLevOverflow] >= 0) return;
+  level_emit(l, cap_cells, lev, bounds, childoff, c);
+}
+
+// A level with at most kFusedLevelCells cells in one workgroup: neighbourhoods and split, the scan
+// of the children counts (the next level's size goes to the level table), and the children, with
+// barriers between the phases instead of three launches.
+constexpr int kFusedLevelCells = 32768;
+
+__global__ __launch_bounds__(kScanSingleThreads) void k_level_fused(int l, int depth, int uniform,
+                                                                    int cap, int cap_cells,
+                                                                    int* lev, const uint32_t* keys,
+                                                                    CellArrays c, int* bounds,
+                                                                    int* nchild, int* childoff) {
+  if (lev[kLevOverflow] >= 0) return;  // the same word for every thread of the workgroup
+  level_split(l, depth, uniform, cap, lev, keys, c, bounds, nchild);
+  __syncthreads();
+  scan_single(nchild, childoff, kFusedLevelCells, lev + kLevCnt + l, lev + kLevCnt + l + 1);
+  __syncthreads();
+  level_emit(l, cap_cells, lev, bounds, childoff, c);
 }
 
 // 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
@@ -620,6 +655,15 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     for (int l = from; l <= to; ++l) {
       // cells of level l: at most 8^l, n (nonempty) and the capacity
       const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
+      if (!(l == from && resume_emit) && ub <= kFusedLevelCells) {
+        k_level_fused<<<1, kScanSingleThreads, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
+                                                       int(p.cap_cells), lev,
+                                                       p.keys.as<uint32_t>(), c,
+                                                       p.bounds.as<int>(), p.nchild.as<int>(),
+                                                       p.childoff.as<int>());
+        HPM_LAUNCH_CHECK();
+        continue;
+      }
       if (!(l == from && resume_emit)) {
         k_level_split<<<grid(ub * 27, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
                                                        lev, p.keys.as<uint32_t>(), c,
@@ -708,10 +752,11 @@ static void read_leaf_counts(Plan& p) {
 
 // ---------------------------------------------------------------------------------------------
 // Virtual cubes: interaction-zone cube positions that are not cells of the tree but hold
-// particles of a coarser leaf. Each is listed once (sorted by cube id) and appended to the cell
-// arrays at ids ncells + v with its coordinates and particle range, so that its effective
-// masses are fitted once per solve like a leaf's and the source-to-target kernels read them
-// like any gridlet.
+// particles of a coarser leaf. Each is listed once (a hash set of cube ids, filled by every
+// parent block that sees one) and appended to the cell arrays at ids ncells + v with its
+// coordinates and particle range, so that its effective masses are fitted once per solve like a
+// leaf's and the source-to-target kernels read them like any gridlet. The index v of a cube is
+// the order in which it was first found; nothing computed from it depends on that order.
 // ---------------------------------------------------------------------------------------------
 struct VirtArgs {
   int first_target;
@@ -726,68 +771,57 @@ struct VirtArgs {
   const int* pb;
   const int* pe;
   const uint32_t* keys;  // sorted particle keys at depth D
-  int* counts;           // [targets] (count pass)
-  const int* offs;       // [targets] (emit pass)
-  uint32_t* ids;         // emitted cube ids (emit pass)
+  uint32_t* hkeys;       // hash set: cube id per slot (kNoCube: empty)
+  int* hvals;            // hash set: v per slot
+  uint32_t mask;         // slots - 1
+  int bits;              // slots = 2^bits
 };
 
+constexpr uint32_t kNoCube = 0xffffffffu;  // cube ids are below 2^31
+
+// multiplicative (Fibonacci) hashing: the top "bits" bits of id times 2^32 / golden ratio
+__device__ __forceinline__ uint32_t cube_hash(uint32_t id, int bits) {
+  return (id * 0x9E3779B1u) >> (32 - bits);
+}
+
 // One workgroup per cell of levels 1 .. L-2 (the possible parents of targets), one thread per
-// slot of its 6^3 block: the cube id if the slot is a nonempty virtual cube that lies in the
-// interaction zone of some child (every block cube except the 8 children's own positions). The
-// 8 siblings share the block, so each parent lists it once.
-template <bool EMIT>
-__global__ __launch_bounds__(256) void k_virt_slots(VirtArgs a) {
+// slot of its 6^3 block: a nonempty virtual cube in the interaction zone of some child (every
+// block cube except the 8 children's own positions) joins the set; the thread that adds a new id
+// takes the next index v and records the id at vkeys[v]. A full set raises *full.
+__global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a, int* count, uint32_t* vkeys,
+                                                     int* full) {
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ int s_flag[256];
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
   __syncthreads();
   const int par = a.first_target + blockIdx.x;
+  if (tid >= 216 || !(a.flags[par] & 1)) return;
   const int l = level_of(par, s_off, a.nlevels) + 1;  // level of the block's cubes
-  uint32_t id = 0;
-  int flag = 0;
   const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
-  const bool centre = bx >= 2 && bx <= 3 && by >= 2 && by <= 3 && bz >= 2 && bz <= 3;
-  if (tid < 216 && !centre && (a.flags[par] & 1)) {
-    const int pc = a.coord[par];
-    const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27,
-                                a.flags, a.child8);
-    if (z.coarse >= 0) {
-      const int shift = 3 * (a.depth - l);
-      const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
-      const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
-      const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
-      if (ve > vb) {
-        flag = 1;
-        id = cube_id(l, z.key);
-      }
+  if (bx >= 2 && bx <= 3 && by >= 2 && by <= 3 && bz >= 2 && bz <= 3) return;  // children
+  const int pc = a.coord[par];
+  const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27, a.flags,
+                              a.child8);
+  if (z.coarse < 0) return;
+  const int shift = 3 * (a.depth - l);
+  const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
+  const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
+  const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
+  if (ve <= vb) return;
+  const uint32_t id = cube_id(l, z.key);
+  uint32_t h = cube_hash(id, a.bits);
+  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+    const uint32_t prev = atomicCAS(&a.hkeys[h], kNoCube, id);
+    if (prev == kNoCube) {
+      const int v = atomicAdd(count, 1);
+      a.hvals[h] = v;
+      vkeys[v] = id;
+      return;
     }
+    if (prev == id) return;
+    h = (h + 1) & a.mask;
   }
-  s_flag[tid] = flag;
-  __syncthreads();
-  // inclusive scan of the 256 flags (Hillis-Steele)
-  for (int o = 1; o < 256; o <<= 1) {
-    const int v = tid >= o ? s_flag[tid - o] : 0;
-    __syncthreads();
-    s_flag[tid] += v;
-    __syncthreads();
-  }
-  if (!EMIT) {
-    if (tid == 255) a.counts[blockIdx.x] = s_flag[255];
-  } else if (flag) {
-    a.ids[a.offs[blockIdx.x] + s_flag[tid] - 1] = id;
-  }
-}
-
-__global__ void k_unique_flags(int n, const uint32_t* ids, int* flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = (i == 0 || ids[i] != ids[i - 1]) ? 1 : 0;
-}
-
-__global__ void k_unique_emit(int n, const uint32_t* ids, const int* flags, const int* pos,
-                              uint32_t* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && flags[i]) out[pos[i]] = ids[i];
+  atomicExch(full, 1);
 }
 
 // coordinates, particle range and level of virtual cube v, stored at cell id ncells + v
@@ -815,9 +849,9 @@ __global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, con
 }
 
 // Source gridlet id of every slot of the 6^3 block of each parent of targets: a real cell id,
-// ncells + v for virtual cube v, or -1 (empty position, outside the box, or not a parent).
-__global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, const uint32_t* vkeys,
-                                                     int nvirt, int* table) {
+// ncells + v for virtual cube v (found in the hash set), or -1 (empty position, outside the box,
+// or not a parent).
+__global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, int nvirt, int* table) {
   __shared__ int s_off[kMaxLevels + 1];
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
@@ -832,10 +866,18 @@ __global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, con
                                 a.flags, a.child8);
     if (z.coarse < 0) {
       src = z.real;
-    } else {
+    } else if (nvirt > 0) {
       const uint32_t id = cube_id(l, z.key);
-      const int v = lower_bound_u32(vkeys, 0, nvirt, id);
-      src = (v < nvirt && vkeys[v] == id) ? ncells + v : -1;
+      uint32_t h = cube_hash(id, a.bits);
+      for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+        const uint32_t k = a.hkeys[h];
+        if (k == id) {
+          src = ncells + a.hvals[h];
+          break;
+        }
+        if (k == kNoCube) break;
+        h = (h + 1) & a.mask;
+      }
     }
   }
   table[size_t(blockIdx.x) * 216 + tid] = src;
@@ -844,8 +886,7 @@ __global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, con
 static void build_block_table(Plan& p, const VirtArgs& a, int nt, hipStream_t s) {
   p.blocks.reserve(size_t(nt) * 216 * 4);
   p.blocks_first = a.first_target;
-  k_block_table<<<nt, 256, 0, s>>>(a, int(p.ncells), p.vkeys.as<uint32_t>(), int(p.nvirt),
-                                   p.blocks.as<int>());
+  k_block_table<<<nt, 256, 0, s>>>(a, int(p.ncells), int(p.nvirt), p.blocks.as<int>());
   HPM_LAUNCH_CHECK();
 }
 
@@ -872,6 +913,10 @@ void build_virtual(Plan& p, hipStream_t s) {
   a.pb = p.cpb.as<int>();
   a.pe = p.cpe.as<int>();
   a.keys = p.keys.as<uint32_t>();
+  a.hkeys = nullptr;
+  a.hvals = nullptr;
+  a.mask = 0;
+  a.bits = 0;
   if (p.prob.uniform_depth > 0) {
     // a uniform tree splits every occupied cell above its last level: every leaf is on the last
     // level, and no block cube lies inside a coarser leaf, so there are no virtual cubes and the
@@ -881,54 +926,52 @@ void build_virtual(Plan& p, hipStream_t s) {
     build_block_table(p, a, nt, s);
     return;
   }
-  p.nchild.reserve(size_t(nt) * 4);
-  p.childoff.reserve(size_t(nt) * 4);
-  a.counts = p.nchild.as<int>();
-  a.offs = p.childoff.as<int>();
-  a.ids = nullptr;
-  k_virt_slots<false><<<nt, 256, 0, s>>>(a);
-  HPM_LAUNCH_CHECK();
-  int* d_total = p.dbox + Plan::kBoxTotal;
-  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nt, d_total, p.scan_tmp, s);
-  sync_box(p, s);
-  read_leaf_counts(p);
-  const int refs = p.hbox[Plan::kBoxTotal];
-  if (refs <= 0) {
-    build_block_table(p, a, nt, s);
-    return;
+  // the set starts at 4 slots per cell (at least 2^13) and grows by 4x when a build fills it
+  int bits = 13;
+  while ((int64_t(1) << bits) < 4 * p.ncells && bits < 30) ++bits;
+  p.vhash_bits = std::max(p.vhash_bits, bits);
+  int nv = 0;
+  for (;;) {
+    const size_t slots = size_t(1) << p.vhash_bits;
+    p.vhash_keys.reserve(slots * 4);
+    p.vhash_vals.reserve(slots * 4);
+    p.vkeys.reserve(slots * 4);
+    HPM_HIP(hipMemsetAsync(p.vhash_keys.p, 0xff, slots * 4, s));
+    clear_box(p, Plan::kBoxVirt, 2, s);
+    a.hkeys = p.vhash_keys.as<uint32_t>();
+    a.hvals = p.vhash_vals.as<int>();
+    a.mask = uint32_t(slots - 1);
+    a.bits = p.vhash_bits;
+    k_virt_insert<<<nt, 256, 0, s>>>(a, p.dbox + Plan::kBoxVirt, p.vkeys.as<uint32_t>(),
+                                     p.dbox + Plan::kBoxVirtFull);
+    HPM_LAUNCH_CHECK();
+    sync_box(p, s);
+    if (!p.hbox[Plan::kBoxVirtFull]) {
+      nv = p.hbox[Plan::kBoxVirt];
+      break;
+    }
+    if (p.vhash_bits >= 30) fail(HPM_ERR_NO_MEMORY, "too many virtual cubes");
+    p.vhash_bits += 2;
   }
-  p.vids.reserve(size_t(refs) * 4);
-  p.vtmp.reserve(size_t(refs) * 4 * 4);  // sort scratch (keys, values, values) and flags/pos
-  a.ids = p.vids.as<uint32_t>();
-  k_virt_slots<true><<<nt, 256, 0, s>>>(a);
-  HPM_LAUNCH_CHECK();
-  uint32_t* kb = p.vtmp.as<uint32_t>();
-  int* va = p.vtmp.as<int>() + refs;
-  int* vb = p.vtmp.as<int>() + 2 * size_t(refs);
-  radix_sort(p.vids.as<uint32_t>(), va, kb, vb, refs, 31, p.hist, p.scan_tmp, s);
-  // unique ids: flags in va, positions in vb, compacted into kb
-  k_unique_flags<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va);
-  HPM_LAUNCH_CHECK();
-  exclusive_scan_i32(va, vb, refs, d_total, p.scan_tmp, s);
-  sync_box(p, s);
-  const int nv = p.hbox[Plan::kBoxTotal];
-  p.vkeys.reserve(size_t(std::max(nv, 1)) * 4);
-  k_unique_emit<<<nblk(refs, 256), 256, 0, s>>>(refs, p.vids.as<uint32_t>(), va, vb,
-                                                p.vkeys.as<uint32_t>());
-  HPM_LAUNCH_CHECK();
-  ensure_cells(p, p.ncells + nv, p.ncells, s);
-  p.vlevel.reserve(size_t(std::max(nv, 1)) * 4);
-  p.vlist.reserve(size_t(std::max(nv, 1)) * 4);
-  k_virt_cells<<<nblk(nv, 256), 256, 0, s>>>(nv, p.vkeys.as<uint32_t>(), p.depth, int(p.n),
-                                              p.keys.as<uint32_t>(), int(p.ncells),
-                                              p.ccoord.as<int>(), p.cpb.as<int>(), p.cpe.as<int>(),
-                                              p.vlevel.as<int>(), p.vlist.as<int>());
-  HPM_LAUNCH_CHECK();
-  p.nvirt = nv;
-  a.coord = p.ccoord.as<int>();  // the cell arrays may have moved when they grew
-  a.flags = p.cflags.as<int>();
-  a.child8 = p.child8.as<int>();
-  a.nbr27 = p.nbr27.as<int>();
+  read_leaf_counts(p);
+  if (nv > 0) {
+    ensure_cells(p, p.ncells + nv, p.ncells, s);
+    p.vlevel.reserve(size_t(nv) * 4);
+    p.vlist.reserve(size_t(nv) * 4);
+    k_virt_cells<<<nblk(nv, 256), 256, 0, s>>>(nv, p.vkeys.as<uint32_t>(), p.depth, int(p.n),
+                                                p.keys.as<uint32_t>(), int(p.ncells),
+                                                p.ccoord.as<int>(), p.cpb.as<int>(),
+                                                p.cpe.as<int>(), p.vlevel.as<int>(),
+                                                p.vlist.as<int>());
+    HPM_LAUNCH_CHECK();
+    p.nvirt = nv;
+    a.coord = p.ccoord.as<int>();  // the cell arrays may have moved when they grew
+    a.flags = p.cflags.as<int>();
+    a.child8 = p.child8.as<int>();
+    a.nbr27 = p.nbr27.as<int>();
+    a.pb = p.cpb.as<int>();
+    a.pe = p.cpe.as<int>();
+  }
   build_block_table(p, a, nt, s);
 }
 

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpm.so")
 
-HPM_ABI_VERSION = 5
+HPM_ABI_VERSION = 6
 HPM_F64, HPM_F32 = 0, 1
 HPM_KERNELS = {"newton": 0, "yukawa": 1}
 HPM_M2L_MODES = {"grid": 0, "cells": 1, "shared": 2}
@@ -91,6 +91,7 @@ SIGNATURES = {
     "hpm_direct_sum": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _d, _d, _i32, _d, _vp,
                               _vp, _vp, _vp, _vp]),
     "hpm_plan_set_route": (_i32, [_vp, _i32]),
+    "hpm_plan_set_overlap": (_i32, [_vp, _i32]),
     "hpm_plan_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_i32),
                                  ctypes.POINTER(_d)]),
     "hpm_plan_bytes_estimate": (_i32, [ctypes.POINTER(HpmProblem), _i64,
@@ -211,7 +212,7 @@ class Plan:
                                     _stream(stream), ctypes.byref(h)), "hpm_plan_create")
         self._h = h
 
-    STAGES = ("tree", "p2m", "m2m", "m2l", "l2l", "leaf")
+    STAGES = ("tree", "p2m", "m2m", "m2l", "l2l", "leaf", "p2p")
 
     def rebuild(self, x, y, z, stream=None):
         n, dt = int(x.numel()), self.problem.dtype
@@ -223,7 +224,7 @@ class Plan:
         _check(_lib.hpm_plan_enable_timing(self._h, 1 if on else 0), "hpm_plan_enable_timing")
 
     def stage_times(self) -> dict:
-        ms = (ctypes.c_double * 6)()
+        ms = (ctypes.c_double * 7)()
         ne, nb = ctypes.c_int64(), ctypes.c_int64()
         _check(_lib.hpm_plan_stage_times(self._h, ms, ctypes.byref(ne), ctypes.byref(nb)),
                "hpm_plan_stage_times")
@@ -236,6 +237,11 @@ class Plan:
         _check(_lib.hpm_plan_execute(self._h, _dev(m, dt, n, "m"), _dev(phi, dt, n, "phi"),
                                      _dev(ax, dt, n, "ax"), _dev(ay, dt, n, "ay"),
                                      _dev(az, dt, n, "az"), _stream(stream)), "hpm_plan_execute")
+
+    def set_overlap(self, on: bool):
+        """hpm_plan_set_overlap: near-zone sums beside the source-to-target step (True) or in
+        line after it (False)."""
+        _check(_lib.hpm_plan_set_overlap(self._h, 1 if on else 0), "hpm_plan_set_overlap")
 
     def set_route(self, route: str):
         """Source-to-target route of later evaluations: "grid", "cells" or "shared"."""

@@ -60,7 +60,7 @@ def _problem(**kw):
     (dict(max_depth=11), 1), (dict(leaf_capacity=0), 1), (dict(abi=1), 1), (dict(abi=99), 1),
     (dict(kernel_id=2), 1), (dict(kernel="yukawa", screening=0.0), 1),
     (dict(kernel="yukawa", screening=float("nan")), 1), (dict(abi=3), 1),
-    (dict(abi=4), 1), (dict(m2l_mode=3), 1), (dict(extended=True, m2l="shared"), 6),
+    (dict(abi=4), 1), (dict(abi=5), 1), (dict(m2l_mode=3), 1), (dict(extended=True, m2l="shared"), 6),
     (dict(extended=True, ng=2), 6), (dict(extended=True, ng=3), 6), (dict(extended_id=2, m2l="cells"), 1),
     (dict(reserved=1), 1),
     (dict(ng=8, m2l="cells"), 6), (dict(ng=8, m2l="shared"), 6),

@@ -56,3 +56,25 @@ def test_route_switch_and_autotune(prec):
     assert g.autotune(m, reps=1)[0] == "grid"
     g.close()
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_near_zone_in_line_equals_overlapped(prec):
+    # from 2^16 particles the near-zone sums run on the plan's second stream beside the
+    # source-to-target step; in line (hpm_plan_set_overlap 0) they give the same bits, and the
+    # near-zone stage is timed either way
+    import torch
+    from paper_1906_10734_amd import hpm
+    x, y, z, m = _set("plummer", 1 << 17, prec)
+    plan = hpm.Plan(hpm.Problem(ng=4, precision=prec, softening=1e-3), x, y, z)
+    plan.enable_timing(True)
+    a = [t.clone() for t in plan(m)]
+    plan.set_overlap(False)
+    b = plan(m)
+    torch.cuda.synchronize()
+    assert all(torch.equal(u, v) for u, v in zip(a, b))
+    st = plan.stage_times()
+    log(f"[overlap] {prec}: near zone {st['p2p'] / st['n_exec']:.3f} ms per evaluation")
+    assert st["n_exec"] == 2 and st["p2p"] > 0
+    assert hpm._lib.hpm_plan_set_overlap(plan._h, 2) == 1  # HPM_ERR_INVALID_ARG
+    plan.close()
