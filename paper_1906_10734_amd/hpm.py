@@ -269,7 +269,7 @@ class Plan:
         return dict(n_levels=i.n_levels, ng=i.ng, n_particles=i.n_particles, n_cells=i.n_cells,
                     n_leaves=i.n_leaves, n_targets=i.n_targets,
                     cells_per_level=list(i.cells_per_level)[:i.n_levels],
-                    device_bytes=i.device_bytes)
+                    p2p_pairs=i.p2p_pairs, device_bytes=i.device_bytes)
 
     def perm(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.int32)
