@@ -18,8 +18,8 @@ Prints ONE JSON line. Two other workloads run on their own flag, each printing i
   --large   the 2^24-particle clustered set (N_g = 4, at most 32 per leaf) on each of the three
             source-to-target routes;
   --serve   a Poisson stream of solves (N log-uniform in [2^12, 2^20], uniform, Plummer or
-            clustered, force tolerance 1e-4, N_g = 6 extended on the cell route or N_g = 8 on
-            the padded grid for sets of at most 2^16) at 0.5, 0.7 and 0.9 of the saturated rate:
+            clustered, force tolerance 1e-4, N_g = 6 extended gridlets on the cell route) at
+            0.5, 0.7 and 0.9 of the saturated rate:
             p50/p99 latency from submission to completion, particles/s, and every result checked
             against its tolerance and against the same solve alone.
 """
@@ -303,19 +303,13 @@ def serve_bench(args):
     for i, r in enumerate(pool):
         p = request_particles(r).astype(np.float32)
         dev = _device_set(torch, p, torch.float32)
-        # the form for the request's 1e-4 tolerance: by default the extended N_g = 6 gridlet on
-        # the cell route (1.7e-5 on the 2^18 Plummer workload, 6x below the tolerance; the
-        # standard N_g = 6 gridlet, 8e-5, leaves no margin, and no N_g = 4 form reaches 1e-4);
-        # sets of at most 2^16 particles whose request asks for order 8 take N_g = 8 on the
-        # padded grid (the library's N_g = 8 limit)
-        if r["order8"]:
-            ng = 8
-            prob = hpm.Problem(ng=8, precision="f32", leaf_capacity=64, max_depth=10,
-                               softening=1e-3)
-        else:
-            ng = 6
-            prob = hpm.Problem(ng=6, precision="f32", leaf_capacity=64, max_depth=10,
-                               softening=1e-3, m2l="cells", extended=True)
+        # the form for the request's 1e-4 tolerance: the extended N_g = 6 gridlet on the cell
+        # route (1.7e-5 on the 2^18 Plummer workload, 6x below the tolerance). The standard
+        # N_g = 6 gridlet (8e-5) leaves no margin, no N_g = 4 form reaches 1e-4 (2.7e-4 extended),
+        # and FP32 at N_g = 8 stops at 1.5e-4 (its rounding, not the method: FP64 gives 4.6e-6)
+        ng = 6
+        prob = hpm.Problem(ng=6, precision="f32", leaf_capacity=64, max_depth=10,
+                           softening=1e-3, m2l="cells", extended=True)
         sub = torch.tensor(random_subset(r["n"], 256, 6000 + i), device="cuda")
         _, rx, ry, rz = hpm.direct_sum(*dev, sub, 1.0, 1e-3)
         solo = hpm.solve(prob, *dev)
@@ -388,11 +382,8 @@ def serve_bench(args):
            "unit": "ms", "dtype": "f32", "data": "synthetic (seeded uniform, Plummer, clustered)",
            "config": {"workload": "Poisson arrivals, N log-uniform 2^12..2^20, uniform/Plummer/"
                                   "clustered, relative force tolerance 1e-4 for every request, "
-                                  "N_g = 6 extended on the cell route or (N <= 2^16, seeded coin) "
-                                  "N_g = 8 on the padded grid, leaf<=64, eps=1e-3",
-                      "pool": len(pool), "slots": args.slots,
-                      "orders": {"ng6_extended": sum(1 for r in pool if r["ng"] == 6),
-                                 "ng8": sum(1 for r in pool if r["ng"] == 8)},
+                                  "N_g = 6 extended gridlets on the cell route, leaf<=64, "
+                                  "eps=1e-3", "pool": len(pool), "slots": args.slots,
                       "hbm_budget_gib": args.serve_budget_gib},
            "results": out, "server": stats,
            "pool_over_tolerance": [{k: r[k] for k in ("kind", "n", "ng", "tolerance",

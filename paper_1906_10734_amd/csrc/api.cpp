@@ -223,7 +223,7 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
 size_t Plan::device_bytes() const {
   const DevBuf* bufs[] = {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
-      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &blocks, &dlevel, &dlev, &gridlet,
+      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlevel, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
       &cell_pflag, &cell_ppos, &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,

@@ -177,7 +177,7 @@ struct Plan {
   DevBuf vlist;   // [nvirt] cell id ncells + v
   // the set of virtual cube ids while they are listed: open addressing, 2^vhash_bits slots of
   // (id, v), grown when a build overflows it
-  DevBuf vhash_keys, vhash_vals;
+  DevBuf vhash_keys, vhash_vals, vcount;
   int vhash_bits = 0;
   // source gridlet ids of the 216 block slots of each parent of targets (cells of levels
   // 1 .. L-2, from id blocks_first on)

@@ -492,23 +492,6 @@ __global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, 
   level_emit(l, cap_cells, lev, bounds, childoff, c);
 }
 
-// A level with at most kFusedLevelCells cells in one workgroup: neighbourhoods and split, the scan
-// of the children counts (the next level's size goes to the level table), and the children, with
-// barriers between the phases instead of three launches.
-constexpr int kFusedLevelCells = 32768;
-
-__global__ __launch_bounds__(kScanSingleThreads) void k_level_fused(int l, int depth, int uniform,
-                                                                    int cap, int cap_cells,
-                                                                    int* lev, const uint32_t* keys,
-                                                                    CellArrays c, int* bounds,
-                                                                    int* nchild, int* childoff) {
-  if (lev[kLevOverflow] >= 0) return;  // the same word for every thread of the workgroup
-  level_split(l, depth, uniform, cap, lev, keys, c, bounds, nchild);
-  __syncthreads();
-  scan_single(nchild, childoff, kFusedLevelCells, lev + kLevCnt + l, lev + kLevCnt + l + 1);
-  __syncthreads();
-  level_emit(l, cap_cells, lev, bounds, childoff, c);
-}
 
 // 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
 // thread per (cell, neighbour) entry, grid-stride.
@@ -655,15 +638,6 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     for (int l = from; l <= to; ++l) {
       // cells of level l: at most 8^l, n (nonempty) and the capacity
       const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
-      if (!(l == from && resume_emit) && ub <= kFusedLevelCells) {
-        k_level_fused<<<1, kScanSingleThreads, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
-                                                       int(p.cap_cells), lev,
-                                                       p.keys.as<uint32_t>(), c,
-                                                       p.bounds.as<int>(), p.nchild.as<int>(),
-                                                       p.childoff.as<int>());
-        HPM_LAUNCH_CHECK();
-        continue;
-      }
       if (!(l == from && resume_emit)) {
         k_level_split<<<grid(ub * 27, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
                                                        lev, p.keys.as<uint32_t>(), c,
@@ -824,6 +798,10 @@ __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a, int* count, uin
   atomicExch(full, 1);
 }
 
+__global__ void k_copy_words(const int* src, int* dst, int count) {
+  if (int(threadIdx.x) < count) dst[threadIdx.x] = src[threadIdx.x];
+}
+
 // coordinates, particle range and level of virtual cube v, stored at cell id ncells + v
 __global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, const uint32_t* keys,
                              int ncells, int* coord, int* pb, int* pe, int* vlevel, int* vlist) {
@@ -937,13 +915,18 @@ void build_virtual(Plan& p, hipStream_t s) {
     p.vhash_vals.reserve(slots * 4);
     p.vkeys.reserve(slots * 4);
     HPM_HIP(hipMemsetAsync(p.vhash_keys.p, 0xff, slots * 4, s));
-    clear_box(p, Plan::kBoxVirt, 2, s);
+    // the count and the full flag in device memory (the atomics of the insertion stay on the
+    // device), copied to the mailbox words afterwards
+    p.vcount.reserve(2 * sizeof(int));
+    HPM_HIP(hipMemsetAsync(p.vcount.p, 0, 2 * sizeof(int), s));
     a.hkeys = p.vhash_keys.as<uint32_t>();
     a.hvals = p.vhash_vals.as<int>();
     a.mask = uint32_t(slots - 1);
     a.bits = p.vhash_bits;
-    k_virt_insert<<<nt, 256, 0, s>>>(a, p.dbox + Plan::kBoxVirt, p.vkeys.as<uint32_t>(),
-                                     p.dbox + Plan::kBoxVirtFull);
+    k_virt_insert<<<nt, 256, 0, s>>>(a, p.vcount.as<int>(), p.vkeys.as<uint32_t>(),
+                                     p.vcount.as<int>() + 1);
+    HPM_LAUNCH_CHECK();
+    k_copy_words<<<1, 64, 0, s>>>(p.vcount.as<int>(), p.dbox + Plan::kBoxVirt, 2);
     HPM_LAUNCH_CHECK();
     sync_box(p, s);
     if (!p.hbox[Plan::kBoxVirtFull]) {

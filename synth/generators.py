@@ -201,15 +201,12 @@ def batch_requests(count: int = 512, seed: int = 1003) -> list[dict]:
 def serve_requests(count: int, seed: int = 1004) -> list[dict]:
     """The served workload's request pool: N log-uniform in [2^12, 2^20] (rounded); uniform cube,
     Plummer sphere or clustered set (8 spheres on a 10% background) with equal odds; a relative
-    force tolerance of 1e-4 for every request; and a seeded coin ("order8") that, for sets of at
-    most 2^16 particles, asks for the gridlet order 8 instead of the default form."""
+    force tolerance of 1e-4 for every request."""
     rng = _rng(seed)
     n = np.rint(2.0 ** rng.uniform(12.0, 20.0, count)).astype(np.int64)
     kind = rng.integers(0, 3, count)
-    coin = rng.random(count) < 0.5
     names = ("uniform", "plummer", "clustered")
-    return [dict(n=int(n[i]), kind=names[int(kind[i])], tolerance=1e-4,
-                 order8=bool(coin[i] and n[i] <= 2 ** 16), seed=seed * 1000 + i)
+    return [dict(n=int(n[i]), kind=names[int(kind[i])], tolerance=1e-4, seed=seed * 1000 + i)
             for i in range(count)]
 
 
