@@ -25,7 +25,7 @@ void* Arena::take(size_t b) {
 
 void sync_box(Plan& p, hipStream_t s) {
   if (p.noalloc)
-    HPM_HIP(hipMemcpyAsync(p.hbox, p.dbox, Plan::kBoxLev * sizeof(int), hipMemcpyDeviceToHost, s));
+    HPM_HIP(hipMemcpyAsync(p.hbox, p.dbox, Plan::kBoxWords * sizeof(int), hipMemcpyDeviceToHost, s));
   HPM_HIP(hipStreamSynchronize(s));
 }
 
@@ -96,7 +96,7 @@ void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* 
   if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
   p.n = n;
   build_tree(p, x, y, z, s);
-  build_virtual(p, s);
+  finish_virtual(p, s);
   const size_t cells = size_t(p.ncells);
   p.gridlet.reserve((cells + size_t(p.nvirt)) * p.M * p.elem);
   p.local.reserve(cells * p.ML * p.elem);
@@ -109,10 +109,9 @@ void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* 
     const size_t ntg = cells - size_t(p.level_off[2]);
     p.cell_src.reserve((ntg + size_t(p.nvirt) + 1) * spec);  // + a zero row
     p.cell_tgt.reserve(ntg * spec);
-    build_cell_parents(p, s);  // read after the synchronisation of the near-zone lists
+    read_cell_parents(p);
   }
-  build_near_lists(p, s);
-  if (p.prob.m2l_mode != HPM_M2L_GRID) read_cell_parents(p);
+  finish_near_lists(p, s);
   if (p.timing) {
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));
     HPM_HIP(hipEventSynchronize(p.tree_ev[1]));
@@ -226,8 +225,8 @@ size_t Plan::device_bytes() const {
       &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlevel, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
-      &cell_pflag, &cell_ppos, &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
-      &tmp_keys, &tmp_vals, &hist, &scan_tmp, &bounds, &nchild, &childoff};
+      &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
+      &tmp_keys, &tmp_vals, &hist, &scan_tmp, &tree_blk, &tree_done, &chash_slot, &chash_val};
   size_t total = 0;
   for (const DevBuf* b : bufs) total += b->bytes;
   return total;

@@ -151,11 +151,10 @@ __global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int*
 // Plan-time near-zone lists and the P2P work items
 // ---------------------------------------------------------------------------------------------
 struct NearArgs {
-  int nleaves;
   int depth;
-  int nlevels;
+  const int* lev;  // the tree's level table (leaf count, level offsets)
+  int64_t cap_cells;
   const int* leaves;
-  const int* level_off;
   const int* coord;
   const int* pb;
   const int* pe;
@@ -163,47 +162,111 @@ struct NearArgs {
   const uint32_t* keys;
   int* near_rb;  // [nleaves][27]
   int* near_re;
-  int* items;    // per leaf: number of work items
+  int* item_cnt;  // per leaf: number of work items
+  int* item_off;  // their exclusive prefix sum
+  int* leaf_of;   // leaf list index of each sorted particle
+  unsigned long long* pairs;
+  int* done;      // finish counter (the last workgroup resets it)
+  int* box;
 };
 
-// thread per (leaf, neighbour entry): the sorted range of the particles inside that cube
-__global__ void k_near_ranges(NearArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nleaves * 27) return;
-  const int li = t / 27, k = t % 27;
-  const int g = a.leaves[li];
-  int l = 0;
-  while (l + 1 < a.nlevels && g >= a.level_off[l + 1]) ++l;
-  const int e = a.nbr27[g * 27 + k];
-  int rb = 0, re = 0;
-  if (e >= 0) {
-    rb = a.pb[e];
-    re = a.pe[e];
-  } else if (e <= -2) {
-    const int c = -2 - e;
-    const int pc = a.coord[g];
-    const int qx = coord_x(pc) + k % 3 - 1, qy = coord_y(pc) + (k / 3) % 3 - 1,
-              qz = coord_z(pc) + k / 9 - 1;
-    const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
-    const int shift = 3 * (a.depth - l);
-    rb = lower_bound_u32(a.keys, a.pb[c], a.pe[c], key << shift);
-    re = lower_bound_u32(a.keys, rb, a.pe[c], (key + 1u) << shift);
-  }
-  a.near_rb[t] = rb;
-  a.near_re[t] = re;
-}
+constexpr int kNearThreads = 256;
+using u64 = unsigned long long;
+constexpr int kNearLanes = 32;  // lanes per leaf
 
-// per leaf: source count S, number of (target chunk x source chunk) items, K*S pairs
-__global__ void k_near_items(NearArgs a, long long* pairs) {
-  const int li = blockIdx.x * blockDim.x + threadIdx.x;
-  if (li >= a.nleaves) return;
-  int S = 0;
-  for (int k = 0; k < 27; ++k) S += a.near_re[li * 27 + k] - a.near_rb[li * 27 + k];
-  const int g = a.leaves[li];
-  const int K = a.pe[g] - a.pb[g];
-  const int nt = target_pieces(K), ns = (S + kP2PChunk - 1) / kP2PChunk;
-  a.items[li] = nt * max(ns, 1);
-  atomicAdd(reinterpret_cast<unsigned long long*>(pairs), (unsigned long long)K * S);
+// 32 lanes per leaf, grid-stride over the leaves: lane k < 27 finds the sorted particle range of
+// near cube k (a real cell's range, or the part of a coarser leaf's range with the cube's key
+// prefix); the lanes mark the leaf's particles with its list index; the leaf's targets times
+// sources give its pairs and, cut into pieces and chunks, its work items. The last workgroup to
+// finish turns the item counts into offsets and leaves their total in the mailbox.
+__global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a) {
+  __shared__ int s_off[kMaxLevels + 1];
+  __shared__ int s_w[kNearThreads / 64];
+  __shared__ u64 s_pairs;
+  __shared__ int s_last;
+  const int tid = threadIdx.x, k = tid % kNearLanes;
+  if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
+  const int nl = a.lev[kLevLeaves];
+  if (tid <= kMaxLevels) s_off[tid] = a.lev[kLevOff + tid];
+  if (tid == 0) s_pairs = 0ull;
+  __syncthreads();
+  unsigned long long pairs = 0ull;
+  const int per_group = kNearThreads / kNearLanes;
+  // the trip count is the same for the whole workgroup (the lane shuffles below need every lane)
+  for (int base = blockIdx.x * per_group; base < nl; base += gridDim.x * per_group) {
+    const int li = base + tid / kNearLanes;
+    const bool live = li < nl;
+    const int g = live ? a.leaves[li] : 0;
+    const int l = live ? level_of(g, s_off, kMaxLevels) : 0;
+    int rb = 0, re = 0;
+    if (live && k < 27) {
+      const int e = a.nbr27[size_t(g) * 27 + k];
+      if (e >= 0) {
+        rb = a.pb[e];
+        re = a.pe[e];
+      } else if (e <= -2) {
+        const int c = -2 - e;
+        const int pc = a.coord[g];
+        const int qx = coord_x(pc) + k % 3 - 1, qy = coord_y(pc) + (k / 3) % 3 - 1,
+                  qz = coord_z(pc) + k / 9 - 1;
+        const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
+        const int shift = 3 * (a.depth - l);
+        rb = lower_bound_u32(a.keys, a.pb[c], a.pe[c], key << shift);
+        re = lower_bound_u32(a.keys, rb, a.pe[c], (key + 1u) << shift);
+      }
+      a.near_rb[size_t(li) * 27 + k] = rb;
+      a.near_re[size_t(li) * 27 + k] = re;
+    }
+    int S = re - rb;
+#pragma unroll
+    for (int o = kNearLanes / 2; o > 0; o >>= 1) S += __shfl_xor(S, o, kNearLanes);
+    if (!live) continue;
+    const int b = a.pb[g], e = a.pe[g];
+    for (int j = b + k; j < e; j += kNearLanes) a.leaf_of[j] = li;
+    if (k == 0) {
+      const int K = e - b;
+      const int ns = (S + kP2PChunk - 1) / kP2PChunk;
+      a.item_cnt[li] = target_pieces(K) * max(ns, 1);
+      pairs += (unsigned long long)K * (unsigned long long)S;
+    }
+  }
+  if (k == 0 && pairs) atomicAdd(&s_pairs, pairs);
+  __syncthreads();
+  if (tid == 0 && s_pairs) atomicAdd(a.pairs, s_pairs);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(a.done, 1) == int(gridDim.x) - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // the last workgroup: exclusive scan of the item counts (thread t takes a chunk)
+  const int per = (nl + kNearThreads - 1) / kNearThreads;
+  const int i0 = min(nl, tid * per), i1 = min(nl, i0 + per);
+  int sum = 0;
+  for (int i = i0; i < i1; ++i) sum += a.item_cnt[i];
+  const int lane = tid & 63, wave = tid >> 6;
+  int x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int run = x - sum, total = 0;
+#pragma unroll
+  for (int w = 0; w < kNearThreads / 64; ++w) {
+    if (w < wave) run += s_w[w];
+    total += s_w[w];
+  }
+  for (int i = i0; i < i1; ++i) {
+    a.item_off[i] = run;
+    run += a.item_cnt[i];
+  }
+  if (tid == 0) {
+    a.box[Plan::kBoxTotal] = total;
+    *a.done = 0;
+  }
 }
 
 __global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, const int* pe,
@@ -226,34 +289,18 @@ __global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, co
 
 static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
 
-// leaf list index of every sorted particle (a leaf's particles are one contiguous range)
-__global__ void k_leaf_of(const int* leaves, const int* pb, const int* pe, int* leaf_of) {
-  const int li = blockIdx.x;
-  const int g = leaves[li];
-  for (int j = pb[g] + threadIdx.x; j < pe[g]; j += blockDim.x) leaf_of[j] = li;
-}
-
-void build_near_lists(Plan& p, hipStream_t s) {
-  const int nl = int(p.nleaves);
-  p.near_rb.reserve(size_t(nl) * 27 * 4);
-  p.near_re.reserve(size_t(nl) * 27 * 4);
-  p.item_cnt.reserve(size_t(nl) * 4);
-  p.item_off.reserve(size_t(nl) * 4);
-  p.pairs.reserve(16);
-  HPM_HIP(hipMemsetAsync(p.pairs.p, 0, 8, s));
+void enqueue_near_lists(Plan& p, hipStream_t s) {
+  const size_t cap = size_t(p.cap_cells);  // leaves <= cells <= capacity
+  p.near_rb.reserve(cap * 27 * 4);
+  p.near_re.reserve(cap * 27 * 4);
+  p.item_cnt.reserve(cap * 4);
+  p.item_off.reserve(cap * 4);
   p.leaf_of.reserve(size_t(std::max<int64_t>(p.n, 1)) * 4);
-  HPM_HIP(hipMemsetAsync(p.leaf_of.p, 0xff, size_t(p.n) * 4, s));
-  if (nl > 0) {
-    k_leaf_of<<<nl, 64, 0, s>>>(p.leaves.as<int>(), p.cpb.as<int>(), p.cpe.as<int>(),
-                                p.leaf_of.as<int>());
-    HPM_LAUNCH_CHECK();
-  }
   NearArgs a;
-  a.nleaves = nl;
   a.depth = p.depth;
-  a.nlevels = p.nlevels;
+  a.lev = p.dlev.as<int>();
+  a.cap_cells = p.cap_cells;
   a.leaves = p.leaves.as<int>();
-  a.level_off = p.dlevel.as<int>();
   a.coord = p.ccoord.as<int>();
   a.pb = p.cpb.as<int>();
   a.pe = p.cpe.as<int>();
@@ -261,19 +308,24 @@ void build_near_lists(Plan& p, hipStream_t s) {
   a.keys = p.keys.as<uint32_t>();
   a.near_rb = p.near_rb.as<int>();
   a.near_re = p.near_re.as<int>();
-  a.items = p.item_cnt.as<int>();
-  k_near_ranges<<<nblk(int64_t(nl) * 27, 256), 256, 0, s>>>(a);
+  a.item_cnt = p.item_cnt.as<int>();
+  a.item_off = p.item_off.as<int>();
+  a.leaf_of = p.leaf_of.as<int>();
+  a.pairs = p.pairs.as<unsigned long long>();
+  a.done = p.vcount.as<int>() + 3;
+  a.box = p.dbox;
+  const int groups = std::max(1, std::min(nblk(int64_t(cap), kNearThreads / kNearLanes), 2048));
+  k_near_lists<<<groups, kNearThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
-  k_near_items<<<nblk(nl, 256), 256, 0, s>>>(a, p.pairs.as<long long>());
-  HPM_LAUNCH_CHECK();
-  exclusive_scan_i32(p.item_cnt.as<int>(), p.item_off.as<int>(), nl, p.dbox + Plan::kBoxTotal,
-                     p.scan_tmp, s);
-  sync_box(p, s);
-  const int total = p.hbox[Plan::kBoxTotal];
-  p.n_items = total;
+}
+
+void finish_near_lists(Plan& p, hipStream_t s) {
+  const int nl = int(p.nleaves);
+  const int total = int(p.n_items);
   p.p2p_pairs = -1;  // read from the device on request
   p.items.reserve(size_t(std::max(total, 1)) * sizeof(int4));
   p.partial.reserve(size_t(std::max(total, 1)) * 64 * 5 * p.elem);
+  if (nl <= 0) return;
   k_fill_items<<<nblk(nl, 256), 256, 0, s>>>(nl, p.item_off.as<int>(), p.cpb.as<int>(),
                                              p.cpe.as<int>(), p.leaves.as<int>(),
                                              p.near_rb.as<int>(), p.near_re.as<int>(),

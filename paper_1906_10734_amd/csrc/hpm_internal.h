@@ -15,6 +15,13 @@ namespace hpm {
 
 constexpr int kMaxLevelsHost = 11;  // levels 0..10
 
+// The tree build's level table (device memory; also copied to the mailbox words from
+// Plan::kBoxLev on): first cell id and cell count of each level (offsets past the last level are
+// the cell total), the cell and leaf totals, the leaves of levels 0 and 1, the first leaf-list
+// index of each level, and where each level starts in the list of split cells of levels >= 1.
+constexpr int kLevOff = 0, kLevCnt = 16, kLevCells = 32, kLevLeaves = 33, kLevLeavesLt2 = 34,
+              kLevLeafOff = 40, kLevSplitOff = 52, kLevWords = 64;
+
 struct HpmError {
   hpm_status status;
   std::string msg;
@@ -176,7 +183,8 @@ struct Plan {
   DevBuf vlevel;  // [nvirt] level
   DevBuf vlist;   // [nvirt] cell id ncells + v
   // the set of virtual cube ids while they are listed: open addressing, 2^vhash_bits slots of
-  // (id, v), grown when a build overflows it
+  // (generation << 32 | id, v), grown when a build overflows it; vcount: cubes listed, the set
+  // is full, finish counter of the listing kernel
   DevBuf vhash_keys, vhash_vals, vcount;
   int vhash_bits = 0;
   // source gridlet ids of the 216 block slots of each parent of targets (cells of levels
@@ -204,20 +212,24 @@ struct Plan {
   DevBuf cell_src, cell_tgt;
   // the split parents (cells of levels 1 .. L-2 with children) in id order, and where each
   // parent level starts in that list (cell_pbeg[L-1] is its length)
-  DevBuf cell_plist, cell_pflag, cell_ppos;
+  DevBuf cell_plist;
   int cell_pbeg[kMaxLevelsHost + 1] = {0};
   Tables tab;
-  // scratch for the tree build
-  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, bounds, nchild, childoff;
+  // scratch for the tree build: sort buffers, per-workgroup level counts and the count kernel's
+  // finish counter, and the hash of cube id -> cell id (slots tagged with the build's generation,
+  // so that a new build needs no clearing)
+  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, tree_blk, tree_done, chash_slot, chash_val;
+  int chash_bits = 0;
+  uint32_t tree_gen = 0;
   // pinned, device-mapped words that kernels write and the host reads after a stream
   // synchronisation (counts that size the next step of the build, input error flags)
-  static constexpr int kBoxWords = 64;
+  static constexpr int kBoxWords = 128;
   static constexpr int kBoxOutOfBox = 0, kBoxNonfinite = 1, kBoxTotal = 2, kBoxLeavesLt2 = 3;
   static constexpr int kBoxCellLevels = 4;  // words 5 .. 4 + L-1: split-parent list bounds
   static constexpr int kBoxLeaves = 16;     // leaf count (read after the first virtual-cube step)
   static constexpr int kBoxVirt = 17;       // virtual cubes listed
   static constexpr int kBoxVirtFull = 18;   // the virtual-cube set overflowed
-  static constexpr int kBoxLev = 24;        // words 24 .. 63: copy of the device level table
+  static constexpr int kBoxLev = 24;        // words 24 .. 87: copy of the tree's level table
   int* hbox = nullptr;
   int* dbox = nullptr;
   // a plan of the entry point that allocates nothing: its buffers come from an arena, the mailbox
@@ -274,12 +286,13 @@ void clear_box(Plan& p, int w, int count, hipStream_t s);
 void build_tables(Plan& p, int max_levels, hipStream_t s);
 
 // ---- tree.hip -----------------------------------------------------------------------------------
-// Leaves the leaf list's counts in the mailbox; build_virtual reads them.
+// The tree of the current positions: sorted particles, cells, leaf list, neighbourhoods, the set
+// of virtual cubes and the near-zone lists, with one host synchronisation (the counts that size
+// the rest: levels, cells, leaves, virtual cubes, near-zone work items). Then finish_virtual
+// appends the virtual cubes to the cell arrays and builds the per-parent table of block sources.
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
+void finish_virtual(Plan& p, hipStream_t s);
 void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
-// lists the virtual cubes of the current tree, appends them to the cell arrays and builds the
-// per-parent table of block sources; sets p.nleaves and p.nleaves_lt2 from the mailbox
-void build_virtual(Plan& p, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------
 void launch_gather_masses(Plan& p, const void* m, hipStream_t s);
@@ -299,10 +312,8 @@ int m2l_workspace_slots(int prec, int ng, size_t* bytes_per_slot);
 // modes of one cell spectrum as stored: C^2 (C/2 + 1) with C = 2 N_g + 2 ext, rounded up to a
 // multiple of 16
 size_t cell_modes(int ng, int ext);
-// the list of split parents that the cell-by-cell route visits (with the tree build): the
-// kernels are enqueued by build_cell_parents, the per-level bounds are read from the mailbox by
-// read_cell_parents after the stream has been synchronised
-void build_cell_parents(Plan& p, hipStream_t s);
+// the list of split parents that the cell-by-cell route visits is written by the tree build;
+// read_cell_parents takes its per-level bounds from the mailbox
 void read_cell_parents(Plan& p);
 void launch_m2l_cells(Plan& p, hipStream_t s);
 // the shared-transform route: the central cubes cell by cell, the outer cubes by
@@ -310,7 +321,10 @@ void launch_m2l_cells(Plan& p, hipStream_t s);
 void launch_m2l_shared(Plan& p, hipStream_t s);
 
 // ---- downsweep.hip -------------------------------------------------------------------------------
-void build_near_lists(Plan& p, hipStream_t s);
+// near-zone ranges, work-item counts and offsets of every leaf (enqueued by the tree build before
+// its synchronisation: the leaf count is read on the device), then the work items themselves
+void enqueue_near_lists(Plan& p, hipStream_t s);
+void finish_near_lists(Plan& p, hipStream_t s);
 void launch_l2l(Plan& p, int level, hipStream_t s);
 // near-zone partial sums (independent of the far-field chain), then the per-leaf combination
 void launch_p2p(Plan& p, hipStream_t s);

@@ -409,45 +409,8 @@ size_t cell_modes(int ng, int ext) {
 }
 
 // ---- list of split parents (cells of levels 1 .. L-2 with children), by level ----------------
-__global__ void k_split_flags(int first, int n, const int* cflags, int* flag) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flag[i] = cflags[first + i] & 1;
-}
-
-__global__ void k_split_emit(int first, int n, const int* flag, const int* pos, int* list) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && flag[i]) list[pos[i]] = first + i;
-}
-
-// start of each parent level in the list (levels 1 .. L-2), and its end, into the mailbox
-__global__ void k_split_bounds(int nlevels, const int* level_off, int first, int n,
-                               const int* flag, const int* pos, int* box) {
-  const int l = threadIdx.x;
-  if (l < 1 || l > nlevels - 1) return;
-  const int i = level_off[l] - first;  // first cell of level l, relative to the list's range
-  box[Plan::kBoxCellLevels + l] = i < n ? pos[i] : pos[n - 1] + flag[n - 1];
-}
-
-void build_cell_parents(Plan& p, hipStream_t s) {
-  for (int l = 0; l <= kMaxLevelsHost; ++l) p.cell_pbeg[l] = 0;
-  if (p.nlevels <= 2) return;
-  const int first = p.level_off[1], n = p.level_off[p.nlevels - 1] - first;
-  if (n <= 0) return;
-  p.cell_pflag.reserve(size_t(n) * 4);
-  p.cell_ppos.reserve(size_t(n) * 4);
-  p.cell_plist.reserve(size_t(n) * 4);
-  const int nb = (n + 255) / 256;
-  k_split_flags<<<nb, 256, 0, s>>>(first, n, p.cflags.as<int>(), p.cell_pflag.as<int>());
-  HPM_LAUNCH_CHECK();
-  exclusive_scan_i32(p.cell_pflag.as<int>(), p.cell_ppos.as<int>(), n, nullptr, p.scan_tmp, s);
-  k_split_emit<<<nb, 256, 0, s>>>(first, n, p.cell_pflag.as<int>(), p.cell_ppos.as<int>(),
-                                  p.cell_plist.as<int>());
-  HPM_LAUNCH_CHECK();
-  k_split_bounds<<<1, 64, 0, s>>>(p.nlevels, p.dlevel.as<int>(), first, n, p.cell_pflag.as<int>(),
-                                  p.cell_ppos.as<int>(), p.dbox);
-  HPM_LAUNCH_CHECK();
-}
-
+// The list itself is written by the tree build; the start of each parent level in it is in the
+// mailbox.
 void read_cell_parents(Plan& p) {
   for (int l = 0; l <= kMaxLevelsHost; ++l) p.cell_pbeg[l] = 0;
   if (p.nlevels <= 2 || p.level_off[p.nlevels - 1] <= p.level_off[1]) return;

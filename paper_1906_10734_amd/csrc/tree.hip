@@ -185,24 +185,6 @@ void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp,
   scan_rec(in, out, n, nullptr, total, t, s);
 }
 
-// The same over the first *dn values (device memory, at most nmax); tmp must already hold the
-// scratch for nmax (no allocation here, so that it can run between kernels still in flight).
-// Up to kScanDnSingleMax the scan is one workgroup that stops at *dn: a level's cell count is
-// usually far below the host's bound, and one launch replaces the three of the tiled scan.
-constexpr int kScanDnSingleMax = 8 * kScanSingleMax;
-
-static void exclusive_scan_i32_dn(const int* in, int* out, int nmax, const int* dn, int* total,
-                                  DevBuf& tmp, hipStream_t s) {
-  if (nmax <= 0) return;
-  if (nmax <= kScanDnSingleMax) {
-    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, nmax, dn, total);
-    HPM_LAUNCH_CHECK();
-    return;
-  }
-  if (tmp.bytes < scan_tmp_ints(nmax) * sizeof(int)) fail(HPM_ERR_DEVICE, "scan scratch too small");
-  scan_rec(in, out, nmax, dn, total, tmp.as<int>(), s);
-}
-
 // ---------------------------------------------------------------------------------------------
 // Morton keys
 // ---------------------------------------------------------------------------------------------
@@ -363,6 +345,20 @@ __global__ void k_gather3(int n, const int* perm, const T* x, const T* y, const 
 // ---------------------------------------------------------------------------------------------
 // Levels
 // ---------------------------------------------------------------------------------------------
+// The cells follow from the sorted keys alone. A cell of level l is a run of equal level-l key
+// prefixes whose parent run (level l - 1) was split, and a run is split when it holds more than
+// leaf_capacity particles and l < D (uniform trees: when l < D). Particle counts only shrink
+// from a run to its sub-runs, so the cells that contain particle i are its runs of levels
+// 0 .. L(i), L(i) being the level of its leaf, and the cells that start at particle i are those
+// of levels d(i) .. L(i), d(i) being the first level at which its key prefix differs from that of
+// particle i - 1. Three launches build every level at once:
+//   count: per workgroup of particles, the cells and leaves that start in it on each level; the
+//          last workgroup to finish turns them into id bases (levels contiguous, each level in
+//          key order, which is Morton order) and writes the level table;
+//   emit:  the cells (key, coordinates, particle range, split flag), the leaf list, and a hash of
+//          cube id -> cell id;
+//   link:  parent and child tables and the 27-cube neighbourhoods, by hash lookups.
+// ---------------------------------------------------------------------------------------------
 struct CellArrays {
   uint32_t* key;
   int* coord;
@@ -379,159 +375,356 @@ static CellArrays cells_of(Plan& p) {
           p.cparent.as<int>(),   p.cflags.as<int>(),  p.child8.as<int>(), p.nbr27.as<int>()};
 }
 
-// Level table in device memory, written by the level kernels as the tree grows, so that the
-// level loop runs without host round trips: first cell id and cell count of each level, and the
-// level whose children did not fit the cell arrays (-1: none; every later level kernel then
-// returns, and the host grows the arrays and resumes there).
-constexpr int kLevOff = 0, kLevCnt = 16, kLevOverflow = 32, kLevWords = 40;
+constexpr int kTreeThreads = 256;
+constexpr int kTreeSeq = 2 * kMaxLevels;  // per workgroup: cells of each level, leaves of each
+constexpr int kTreeMaxGroups = 2048;      // the count kernel's workgroups (rounds absorb the rest)
 
-__global__ void k_root(int n, CellArrays c, int* lev) {
-  const int t = threadIdx.x;
-  if (t < 27) c.nbr27[t] = (t == 13) ? 0 : -1;
-  if (t < kLevWords) lev[t] = (t == kLevCnt) ? 1 : (t == kLevOverflow ? -1 : 0);
-  if (t == 0) {
-    c.key[0] = 0;
-    c.coord[0] = 0;
-    c.pb[0] = 0;
-    c.pe[0] = n;
-    c.parent[0] = -1;
+struct TreeArgs {
+  const uint32_t* keys;  // sorted keys at depth D
+  int n;
+  int depth;
+  int cap;
+  int uniform;
+  int rounds;           // particles per thread: workgroup b takes [b rounds 256, (b+1) rounds 256)
+  int* blk;             // [workgroups][kTreeSeq]: counts, then id bases
+  int* done;            // workgroups of the count kernel finished (its last one resets it)
+  int* lev;             // level table
+  int* box;             // mailbox words
+  int* zero_words;      // cleared by the count kernel for the later steps of the build (4 ints)
+  unsigned long long* zero_pairs;  // near-zone pair count, likewise
+  int64_t cap_cells;    // capacity of the cell arrays (emit and link do nothing above it)
+  // emit / link
+  CellArrays c;
+  int* leaves;
+  int* splits;          // cells with children of levels >= 1, in id order
+  uint64_t* hslot;      // cube hash: (generation << 32 | cube id) per slot
+  int* hval;            // cell id per slot
+  uint32_t hmask;
+  int hbits;
+  uint32_t gen;         // this build's generation: slots of other generations are empty
+};
+
+// first j in (i, hi] with keys[j] >= v (hi if none below hi); keys[i] < v
+__device__ __forceinline__ int gallop_fwd(const uint32_t* keys, int i, int hi, uint32_t v) {
+  int lo = i + 1, step = 1, j = i + 1;
+  while (j < hi && keys[j] < v) {
+    lo = j + 1;
+    step <<= 1;
+    j = i + step;
   }
+  return lower_bound_u32(keys, lo, min(j, hi), v);
 }
 
-__global__ void k_lev_resume(int* lev) { lev[kLevOverflow] = -1; }
+// first j in [0, i] with keys[j] >= v; keys[i] >= v
+__device__ __forceinline__ int gallop_back(const uint32_t* keys, int i, uint32_t v) {
+  int hi = i, step = 1, j = i - 1;
+  while (j >= 0 && keys[j] >= v) {
+    hi = j;
+    step <<= 1;
+    j = i - step;
+  }
+  return lower_bound_u32(keys, max(j + 1, 0), hi, v);
+}
 
-__device__ void level_nbr(int l, int off, int cnt, CellArrays c);
+// The runs that start at one particle, walked level by level.
+struct Walk {
+  uint32_t key;
+  int i;
+  int lo;    // first level at which a cell starts here
+  int end;   // end of the run of the previous level
+  bool live; // cells start here at the levels still to come (until the leaf)
+};
 
-// Split decision and the 9 boundaries of the child ranges of each cell of level l: eight lanes
-// per cell, lane k finds the first particle of child octant k by binary search in the cell's
-// (key-sorted) range. Grid-stride over the level's cells (count from the level table). For
-// l >= 1 the same launch first fills the level's 27-cube neighbourhoods (they read only level
-// l-1, which the previous launches completed).
-__device__ __forceinline__ void level_split(int l, int depth, int uniform, int cap, const int* lev,
-                                            const uint32_t* keys, CellArrays c, int* bounds,
-                                            int* nchild) {
-  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l];
-  if (l >= 1) level_nbr(l, off, cnt, c);
-  for (int64_t t0 = int64_t(blockIdx.x) * blockDim.x; t0 < int64_t(cnt) * 8;
-       t0 += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t t = t0 + threadIdx.x;
-    const int i = int(t >> 3), k = int(t & 7);
-    const bool live = i < cnt;
-    int b = 0, nonempty = 0;
-    bool split = false;
-    int pe = 0;
-    if (live) {
-      const int g = off + i;
-      const int pb = c.pb[g];
-      pe = c.pe[g];
-      split = uniform ? (l < depth) : ((pe - pb) > cap && l < depth);
-      if (k == 0) c.flags[g] = split ? 1 : 0;
-      if (split) {
-        const int shift = 3 * (depth - l - 1);
-        const uint32_t base = c.key[g] << 3;
-        b = (k == 0) ? pb : lower_bound_u32(keys, pb, pe, (base + uint32_t(k)) << shift);
-        bounds[i * 9 + k] = b;
-        if (k == 7) bounds[i * 9 + 8] = pe;
-      }
+__device__ __forceinline__ Walk walk_init(const TreeArgs& a, int i) {
+  Walk w{0u, i, kMaxLevels, 0, false};
+  if (i >= a.n) return w;
+  const uint32_t k = a.keys[i];
+  w.key = k;
+  int d = 0;
+  if (i > 0) {
+    const uint32_t x = k ^ a.keys[i - 1];
+    if (x == 0u) return w;  // same cube as the previous particle at every level
+    d = a.depth - (31 - __clz(int(x))) / 3;
+  }
+  int end = a.n;
+  if (d >= 1 && !a.uniform) {
+    // the parent run (level d - 1) must be split: more than cap particles
+    const int sh = 3 * (a.depth - d + 1);
+    const uint32_t pre = k >> sh;
+    const int e = gallop_fwd(a.keys, i, a.n, (pre + 1u) << sh);
+    const int b = gallop_back(a.keys, i, pre << sh);
+    if (e - b <= a.cap) return w;
+    end = e;
+  }
+  w.lo = d;
+  w.end = end;
+  w.live = true;
+  return w;
+}
+
+// level l of the walk (called for l = 0, 1, ... in order): a cell starts here (cell), it is a
+// leaf (leaf), with cnt particles
+__device__ __forceinline__ void walk_step(const TreeArgs& a, Walk& w, int l, bool& cell, bool& leaf,
+                                          int& cnt) {
+  cell = leaf = false;
+  cnt = 0;
+  if (!w.live || l < w.lo) return;
+  const int sh = 3 * (a.depth - l);
+  const int e = (l == 0) ? a.n : gallop_fwd(a.keys, w.i, w.end, ((w.key >> sh) + 1u) << sh);
+  cnt = e - w.i;
+  cell = true;
+  leaf = a.uniform ? (l >= a.depth) : (cnt <= a.cap || l >= a.depth);
+  w.end = e;
+  if (leaf) w.live = false;
+}
+
+// exclusive scan of one value per thread over the workgroup (kTreeThreads), and the total
+__device__ __forceinline__ int group_scan(int v, int* s_w, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int pre = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kTreeThreads / 64; ++w) {
+    if (w < wave) pre += s_w[w];
+    all += s_w[w];
+  }
+  __syncthreads();
+  total = all;
+  return pre + x - v;
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_tree_count(TreeArgs a) {
+  __shared__ int s_cnt[kTreeSeq];
+  __shared__ int s_w[kTreeThreads / 64];
+  __shared__ int s_last;
+  __shared__ int s_tot[kTreeSeq];
+  __shared__ int s_off[kTreeSeq];
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < kTreeSeq) s_cnt[tid] = 0;
+  __syncthreads();
+  for (int r = 0; r < a.rounds; ++r) {
+    const int i = (blockIdx.x * a.rounds + r) * kTreeThreads + tid;
+    Walk w = walk_init(a, i);
+    for (int l = 0; l < kMaxLevels; ++l) {
+      bool cell, leaf;
+      int cnt;
+      walk_step(a, w, l, cell, leaf, cnt);
+      const uint64_t mc = __ballot(cell), ml = __ballot(leaf);
+      if (lane == 0 && mc) atomicAdd(&s_cnt[l], __popcll(mc));
+      if (lane == 0 && ml) atomicAdd(&s_cnt[kMaxLevels + l], __popcll(ml));
     }
-    // child k is nonempty if the next boundary is past this one (lanes k+1 of the same cell)
-    const int next = __shfl_down(b, 1, 8);
-    if (live && split) nonempty = ((k == 7) ? pe : next) > b ? 1 : 0;
-    int nc = nonempty;
-    nc += __shfl_xor(nc, 1, 8);
-    nc += __shfl_xor(nc, 2, 8);
-    nc += __shfl_xor(nc, 4, 8);
-    if (live && k == 0) nchild[i] = split ? nc : 0;
+  }
+  __syncthreads();
+  if (tid < kTreeSeq) a.blk[size_t(blockIdx.x) * kTreeSeq + tid] = s_cnt[tid];
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(a.done, 1) == int(gridDim.x) - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // the last workgroup: bases of every workgroup, level-major (thread t takes a chunk of them)
+  const int nb = gridDim.x, per = (nb + kTreeThreads - 1) / kTreeThreads;
+  const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+  for (int q = 0; q < kTreeSeq; ++q) {
+    int sum = 0;
+    for (int b = b0; b < b1; ++b) sum += a.blk[size_t(b) * kTreeSeq + q];
+    int tot;
+    int run = group_scan(sum, s_w, tot);
+    if (tid == 0) s_tot[q] = tot;
+    for (int b = b0; b < b1; ++b) {
+      const int c = a.blk[size_t(b) * kTreeSeq + q];
+      a.blk[size_t(b) * kTreeSeq + q] = run;  // within the level; the level offset is added below
+      run += c;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int oc = 0, ol = 0;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      s_off[l] = oc;
+      s_off[kMaxLevels + l] = ol;
+      oc += s_tot[l];
+      ol += s_tot[kMaxLevels + l];
+    }
+    int* lev = a.lev;
+    for (int l = 0; l < 16; ++l) {
+      lev[kLevOff + l] = l < kMaxLevels ? s_off[l] : oc;
+      lev[kLevCnt + l] = l < kMaxLevels ? s_tot[l] : 0;
+    }
+    lev[kLevCells] = oc;
+    lev[kLevLeaves] = ol;
+    lev[kLevLeavesLt2] = s_tot[kMaxLevels] + s_tot[kMaxLevels + 1];
+    int nlev = 0, ps = 0;
+    for (int l = 0; l < 12; ++l) {
+      lev[kLevLeafOff + l] = l < kMaxLevels ? s_off[kMaxLevels + l] : ol;
+      lev[kLevSplitOff + l] = ps;  // split cells of levels 1 .. l-1
+      if (l >= 1 && l < kMaxLevels) ps += s_tot[l] - s_tot[kMaxLevels + l];
+      if (l < kMaxLevels && s_tot[l] > 0) nlev = l + 1;
+    }
+    for (int w = 0; w < kLevWords; ++w) a.box[Plan::kBoxLev + w] = lev[w];
+    a.box[Plan::kBoxLeaves] = ol;
+    a.box[Plan::kBoxLeavesLt2] = lev[kLevLeavesLt2];
+    for (int l = 1; l < nlev; ++l) a.box[Plan::kBoxCellLevels + l] = lev[kLevSplitOff + l];
+    for (int w = 0; w < 4; ++w) a.zero_words[w] = 0;
+    *a.zero_pairs = 0ull;
+    *a.done = 0;
+  }
+  __syncthreads();
+  for (int b = b0; b < b1; ++b)
+    for (int q = 0; q < kTreeSeq; ++q) a.blk[size_t(b) * kTreeSeq + q] += s_off[q];
+}
+
+// multiplicative (Fibonacci) hashing: the top "bits" bits of id times 2^32 / golden ratio
+__device__ __forceinline__ uint32_t cube_hash(uint32_t id, int bits) {
+  return (id * 0x9E3779B1u) >> (32 - bits);
+}
+
+__device__ __forceinline__ void chash_insert(const TreeArgs& a, uint32_t id, int v) {
+  const uint64_t mine = (uint64_t(a.gen) << 32) | id;
+  uint32_t h = cube_hash(id, a.hbits);
+  for (uint32_t probe = 0; probe <= a.hmask;) {
+    const uint64_t cur = __hip_atomic_load(&a.hslot[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uint32_t(cur >> 32) == a.gen) {  // taken in this build
+      h = (h + 1) & a.hmask;
+      ++probe;
+      continue;
+    }
+    if (atomicCAS(reinterpret_cast<unsigned long long*>(&a.hslot[h]), (unsigned long long)cur,
+                  (unsigned long long)mine) == cur) {
+      a.hval[h] = v;
+      return;
+    }
+    // another insertion of this build took the slot first: look at it again
   }
 }
 
-__global__ void k_level_split(int l, int depth, int uniform, int cap, const int* lev,
-                              const uint32_t* keys, CellArrays c, int* bounds, int* nchild) {
-  if (lev[kLevOverflow] >= 0) return;
-  level_split(l, depth, uniform, cap, lev, keys, c, bounds, nchild);
+__device__ __forceinline__ int chash_find(const TreeArgs& a, uint32_t id) {
+  uint32_t h = cube_hash(id, a.hbits);
+  for (uint32_t probe = 0; probe <= a.hmask; ++probe) {
+    const uint64_t s = a.hslot[h];
+    if (uint32_t(s >> 32) != a.gen) return -1;
+    if (uint32_t(s) == id) return a.hval[h];
+    h = (h + 1) & a.hmask;
+  }
+  return -1;
 }
 
-// Children of the cells of level l at ids off_next + childoff[i] + r (the scan of the split
-// counts left the number of level-(l+1) cells in the table); flags the overflow instead when they
-// do not fit in cap cells.
-__device__ __forceinline__ void level_emit(int l, int cap_cells, int* lev, const int* bounds,
-                                           const int* childoff, CellArrays c) {
-  const int off = lev[kLevOff + l], cnt = lev[kLevCnt + l], total = lev[kLevCnt + l + 1];
-  const int off_next = off + cnt;
-  if (int64_t(off_next) + total > cap_cells) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) lev[kLevOverflow] = l;
-    return;
+__global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
+  __shared__ int s_run[kTreeSeq];
+  __shared__ int s_w[2][kTreeThreads / 64];
+  __shared__ int s_lev[kLevWords];
+  if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;  // the host grows the arrays and re-runs
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < kTreeSeq) s_run[tid] = a.blk[size_t(blockIdx.x) * kTreeSeq + tid];
+  if (tid < kLevWords) s_lev[tid] = a.lev[tid];
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  __syncthreads();
+  for (int r = 0; r < a.rounds; ++r) {
+    const int i = (blockIdx.x * a.rounds + r) * kTreeThreads + tid;
+    Walk w = walk_init(a, i);
+    for (int l = 0; l < kMaxLevels; ++l) {
+      bool cell, leaf;
+      int cnt;
+      walk_step(a, w, l, cell, leaf, cnt);
+      const uint64_t mc = __ballot(cell), ml = __ballot(leaf);
+      if (lane == 0) {
+        s_w[0][wave] = __popcll(mc);
+        s_w[1][wave] = __popcll(ml);
+      }
+      __syncthreads();
+      int pc = s_run[l], pl = s_run[kMaxLevels + l], tc = 0, tl = 0;
+#pragma unroll
+      for (int q = 0; q < kTreeThreads / 64; ++q) {
+        if (q < wave) {
+          pc += s_w[0][q];
+          pl += s_w[1][q];
+        }
+        tc += s_w[0][q];
+        tl += s_w[1][q];
+      }
+      if (cell) {
+        const int id = pc + __popcll(mc & lt);
+        const int sh = 3 * (a.depth - l);
+        const uint32_t key = w.key >> sh;
+        int x = 0, y = 0, z = 0;
+        for (int b = 0; b < l; ++b) {
+          x |= int((key >> (3 * b)) & 1u) << b;
+          y |= int((key >> (3 * b + 1)) & 1u) << b;
+          z |= int((key >> (3 * b + 2)) & 1u) << b;
+        }
+        a.c.key[id] = key;
+        a.c.coord[id] = pack_coord(x, y, z);
+        a.c.pb[id] = w.i;
+        a.c.pe[id] = w.i + cnt;
+        a.c.flags[id] = leaf ? 0 : 1;
+        int4* ch = reinterpret_cast<int4*>(a.c.child8 + size_t(id) * 8);
+        ch[0] = make_int4(-1, -1, -1, -1);
+        ch[1] = make_int4(-1, -1, -1, -1);
+        const int lrank = pl + __popcll(ml & lt);  // leaves before this cell in id order
+        if (leaf) a.leaves[lrank] = id;
+        else if (l >= 1)
+          a.splits[s_lev[kLevSplitOff + l] + (id - s_lev[kLevOff + l]) -
+                   (lrank - s_lev[kLevLeafOff + l])] = id;
+        chash_insert(a, cube_id(l, key), id);
+      }
+      __syncthreads();  // every thread has read s_run and s_w
+      if (tid == 0) {
+        s_run[l] += tc;
+        s_run[kMaxLevels + l] += tl;
+      }
+      __syncthreads();
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) lev[kLevOff + l + 1] = off_next;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-    const int g = off + i;
-    const bool split = c.flags[g] & 1;
-    const int cx = coord_x(c.coord[g]), cy = coord_y(c.coord[g]), cz = coord_z(c.coord[g]);
-    int r = 0;
-    for (int k = 0; k < 8; ++k) {
-      int id = -1;
-      if (split) {
-        const int b0 = bounds[i * 9 + k], b1 = bounds[i * 9 + k + 1];
-        if (b1 > b0) {
-          id = off_next + childoff[i] + r++;
-          c.key[id] = (c.key[g] << 3) | uint32_t(k);
-          c.coord[id] = pack_coord(2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + ((k >> 2) & 1));
-          c.pb[id] = b0;
-          c.pe[id] = b1;
-          c.parent[id] = g;
+}
+
+// thread per (cell, neighbour entry): the neighbour entry of the 27-cube neighbourhood (x
+// fastest); entry 13 also links the cell to its parent. The entry of position q on level l is
+// the cell there, or else the deepest cell that contains q: -2 - id if that is a leaf (q lies
+// inside it), -1 if it has children (the level-l cube at q is empty), and -1 outside the box.
+__global__ __launch_bounds__(256) void k_tree_link(TreeArgs a) {
+  __shared__ int s_off[kMaxLevels + 1];
+  const int ncells = a.lev[kLevCells];
+  if (int64_t(ncells) > a.cap_cells) return;
+  if (threadIdx.x <= kMaxLevels) s_off[threadIdx.x] = a.lev[kLevOff + threadIdx.x];
+  __syncthreads();
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(ncells) * 27;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int g = int(t / 27), j = int(t % 27);
+    const int l = level_of(g, s_off, kMaxLevels);
+    const uint32_t key = a.c.key[g];
+    int v = -1;
+    if (j == 13) {
+      v = g;
+      int par = -1;
+      if (l > 0) {
+        par = chash_find(a, cube_id(l - 1, key >> 3));
+        if (par >= 0) a.c.child8[size_t(par) * 8 + (key & 7u)] = g;
+      }
+      a.c.parent[g] = par;
+    } else {
+      const int pc = a.c.coord[g];
+      const int qx = coord_x(pc) + j % 3 - 1, qy = coord_y(pc) + (j / 3) % 3 - 1,
+                qz = coord_z(pc) + j / 9 - 1;
+      const int side = 1 << l;
+      if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
+        const uint32_t q = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
+        for (int k = l; k >= 0; --k) {
+          const int id = chash_find(a, cube_id(k, q >> (3 * (l - k))));
+          if (id < 0) continue;
+          v = (k == l) ? id : ((a.c.flags[id] & 1) ? -1 : -2 - id);
+          break;
         }
       }
-      c.child8[g * 8 + k] = id;
     }
+    a.c.nbr27[size_t(g) * 27 + j] = v;
   }
-}
-
-__global__ void k_level_emit(int l, int cap_cells, int* lev, const int* bounds, const int* childoff,
-                             CellArrays c) {
-  if (lev[kLevOverflow] >= 0) return;
-  level_emit(l, cap_cells, lev, bounds, childoff, c);
-}
-
-
-// 27-cube neighbourhood of the cells of level l (>= 1) from the parent's neighbourhood: one
-// thread per (cell, neighbour) entry, grid-stride.
-__device__ void level_nbr(int l, int off, int cnt, CellArrays c) {
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(cnt) * 27;
-       t += int64_t(gridDim.x) * blockDim.x) {
-    const int i = int(t / 27), j = int(t % 27);
-    const int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
-    const int g = off + i;
-    const int pc = c.coord[g];
-    const int x = coord_x(pc), y = coord_y(pc), z = coord_z(pc);
-    const int par = c.parent[g];
-    const int side = 1 << l;
-    const int qx = x + dx, qy = y + dy, qz = z + dz;
-    int v = -1;
-    if (qx >= 0 && qy >= 0 && qz >= 0 && qx < side && qy < side && qz < side) {
-      const int ox = (qx >> 1) - (x >> 1), oy = (qy >> 1) - (y >> 1), oz = (qz >> 1) - (z >> 1);
-      const int e = c.nbr27[par * 27 + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
-      if (e >= 0) {
-        if (c.flags[e] & 1) v = c.child8[e * 8 + ((qx & 1) | ((qy & 1) << 1) | ((qz & 1) << 2))];
-        else v = -2 - e;
-      } else {
-        v = e;
-      }
-    }
-    c.nbr27[g * 27 + j] = v;
-  }
-}
-
-__global__ void k_leaf_flags(int ncells, const int* flags, int* isleaf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncells) isleaf[i] = (flags[i] & 1) ? 0 : 1;
-}
-
-// leaf list; the cell with id first2 (the first of level 2) reports how many leaves precede it
-__global__ void k_leaf_compact(int ncells, const int* flags, const int* pos, int* leaves,
-                               int first2, int* lt2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncells && i == first2) *lt2 = pos[i];
-  if (i < ncells && !(flags[i] & 1)) leaves[pos[i]] = i;
 }
 
 static void ensure_cells(Plan& p, int64_t need, int64_t keep, hipStream_t s) {
@@ -549,7 +742,31 @@ static void ensure_cells(Plan& p, int64_t need, int64_t keep, hipStream_t s) {
   p.cap_cells = cap;
 }
 
+// (re)allocates b and clears it when the allocation changes; true if it did
+static bool reserve_cleared(DevBuf& b, size_t bytes, hipStream_t s) {
+  if (bytes <= b.bytes && b.p) return false;
+  b.reserve(bytes);
+  HPM_HIP(hipMemsetAsync(b.p, 0, b.bytes, s));
+  return true;
+}
+
+// the cube hash for the cell arrays' capacity (at least twice as many slots)
+static void reserve_cube_hash(Plan& p, hipStream_t s) {
+  int bits = 12;
+  while ((int64_t(1) << bits) < 2 * p.cap_cells && bits < 31) ++bits;
+  if (bits > p.chash_bits || !p.chash_slot.p) {
+    p.chash_bits = std::max(bits, p.chash_bits);
+    const size_t slots = size_t(1) << p.chash_bits;
+    p.chash_slot.release();
+    reserve_cleared(p.chash_slot, slots * 8, s);
+    p.chash_val.reserve(slots * 4);
+  }
+}
+
 static inline int nblk(int64_t n, int t) { return int((n + t - 1) / t); }
+
+static void reserve_virt_set(Plan& p, int min_bits, hipStream_t s);
+static void enqueue_virt_insert(Plan& p, hipStream_t s);
 
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s) {
   const hpm_problem& pr = p.prob;
@@ -581,7 +798,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   }
   HPM_LAUNCH_CHECK();
   // invalid positions got key 0, so the build below stays well defined; the flags are checked
-  // at the first synchronisation of the level loop
+  // at the synchronisation after the levels
 
   radix_sort_pairs(p, 3 * D, s);
 
@@ -601,8 +818,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
                                                    p.zs.as<double>());
   HPM_LAUNCH_CHECK();
 
-  // levels, all enqueued back to back: every level kernel reads its level's cell range from the
-  // device table, and the host waits once, at the end (or where the cells outgrew the arrays)
+  // capacity of the cell arrays: the cells a tree of this kind usually has (grown and the emit
+  // and link launches repeated when the count says more)
   int64_t est = 64;
   if (uniform) {
     int64_t lvl = 1;
@@ -615,80 +832,71 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     est = std::max<int64_t>(1024, 6 * int64_t(n) / std::max(1, pr.leaf_capacity) + 64);
   }
   ensure_cells(p, est, 0, s);
+
+  TreeArgs a;
+  a.keys = p.keys.as<uint32_t>();
+  a.n = n;
+  a.depth = D;
+  a.cap = pr.leaf_capacity;
+  a.uniform = uniform ? 1 : 0;
+  a.rounds = std::max(1, nblk(nblk(n, kTreeThreads), kTreeMaxGroups));
+  const int groups = std::max(1, nblk(n, kTreeThreads * a.rounds));
+  p.tree_blk.reserve(size_t(groups) * kTreeSeq * 4);
+  reserve_cleared(p.tree_done, 16, s);
   p.dlev.reserve(kLevWords * sizeof(int));
-  int* lev = p.dlev.as<int>();
-  auto level_scratch = [&](int64_t keep) {
-    const size_t c = size_t(p.cap_cells);
-    p.bounds.grow(c * 9 * 4, size_t(keep) * 9 * 4, s);
-    p.childoff.grow(c * 4, size_t(keep) * 4, s);
-    p.nchild.grow(c * 4, 0, s);
-    p.scan_tmp.reserve(scan_tmp_ints(int(std::min<int64_t>(c, n))) * sizeof(int));
-  };
-  level_scratch(0);
-  k_root<<<1, 64, 0, s>>>(n, cells_of(p), lev);
+  a.blk = p.tree_blk.as<int>();
+  a.done = p.tree_done.as<int>();
+  a.lev = p.dlev.as<int>();
+  a.box = p.dbox;
+  p.vcount.reserve(4 * sizeof(int));  // cleared by the count kernel
+  p.pairs.reserve(16);
+  a.zero_words = p.vcount.as<int>();
+  a.zero_pairs = p.pairs.as<unsigned long long>();
+  k_tree_count<<<groups, kTreeThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
-  auto grid = [](int64_t work, int t) {
-    return int(std::max<int64_t>(1, std::min<int64_t>((work + t - 1) / t, 4096)));
-  };
-  // levels from..to; the kernels of a level with no cells return at once, but each launch still
-  // costs, so adaptive trees are enqueued to a depth their size suggests first, and the rest
-  // only if the table read back says the tree goes deeper
-  auto enqueue = [&](int from, bool resume_emit, int to) {
-    const CellArrays c = cells_of(p);
-    for (int l = from; l <= to; ++l) {
-      // cells of level l: at most 8^l, n (nonempty) and the capacity
-      const int64_t ub = std::min<int64_t>({int64_t(1) << (3 * l), int64_t(n), p.cap_cells});
-      if (!(l == from && resume_emit)) {
-        k_level_split<<<grid(ub * 27, 256), 256, 0, s>>>(l, D, uniform ? 1 : 0, pr.leaf_capacity,
-                                                       lev, p.keys.as<uint32_t>(), c,
-                                                       p.bounds.as<int>(), p.nchild.as<int>());
-        HPM_LAUNCH_CHECK();
-        exclusive_scan_i32_dn(p.nchild.as<int>(), p.childoff.as<int>(), int(ub),
-                              lev + kLevCnt + l, lev + kLevCnt + l + 1, p.scan_tmp, s);
-      }
-      k_level_emit<<<grid(ub, 128), 128, 0, s>>>(l, int(p.cap_cells), lev, p.bounds.as<int>(),
-                                                 p.childoff.as<int>(), c);
-      HPM_LAUNCH_CHECK();
-    }
-  };
   const int* hl = p.hbox + Plan::kBoxLev;
-  int to = D;
-  if (!uniform) {
-    // log8(n / capacity) levels hold the leaves of an even density; Plummer-like concentration
-    // adds a few (2^18 Plummer particles, 64 per leaf: 8 levels past the root)
-    int est = 0;
-    for (int64_t cells = 1; cells * std::max(1, pr.leaf_capacity) < int64_t(n); cells *= 8) ++est;
-    to = std::min(D, est + 5);
-  }
-  enqueue(0, false, to);
-  for (bool first = true;; first = false) {
-    HPM_HIP(hipMemcpyAsync(p.hbox + Plan::kBoxLev, lev, kLevWords * sizeof(int),
-                           hipMemcpyDeviceToHost, s));
+  for (int attempt = 0;; ++attempt) {
+    reserve_cube_hash(p, s);
+    p.leaves.reserve(size_t(p.cap_cells) * 4);      // at most one leaf per cell
+    p.cell_plist.reserve(size_t(p.cap_cells) * 4);  // and one split cell
+    p.tree_gen = (p.tree_gen + 1u) ? p.tree_gen + 1u : 1u;  // 0 never names a build
+    a.cap_cells = p.cap_cells;
+    a.c = cells_of(p);
+    a.leaves = p.leaves.as<int>();
+    a.splits = p.cell_plist.as<int>();
+    a.hslot = p.chash_slot.as<uint64_t>();
+    a.hval = p.chash_val.as<int>();
+    a.hbits = p.chash_bits;
+    a.hmask = uint32_t((size_t(1) << p.chash_bits) - 1);
+    a.gen = p.tree_gen;
+    k_tree_emit<<<groups, kTreeThreads, 0, s>>>(a);
+    HPM_LAUNCH_CHECK();
+    k_tree_link<<<std::max(1, std::min(nblk(p.cap_cells * 27, 256), 8192)), 256, 0, s>>>(a);
+    HPM_LAUNCH_CHECK();
+    if (!uniform) {
+      reserve_virt_set(p, 0, s);
+      enqueue_virt_insert(p, s);
+    }
+    enqueue_near_lists(p, s);
     sync_box(p, s);
-    if (first) {
+    if (attempt == 0) {
       if (p.hbox[Plan::kBoxNonfinite]) fail(HPM_ERR_NONFINITE, "a particle position is not finite");
       if (p.hbox[Plan::kBoxOutOfBox])
         fail(HPM_ERR_OUT_OF_BOX, "a particle position is outside the box");
     }
-    const int ov = hl[kLevOverflow];
-    if (ov < 0) {
-      if (to < D && hl[kLevCnt + to + 1] > 0) {  // the tree goes deeper than enqueued
-        const int from = to + 1;
-        to = D;
-        enqueue(from, false, to);
-        continue;
-      }
-      break;
-    }
-    // the children of level ov did not fit: keep the levels up to ov (and ov's split), grow,
-    // and emit from level ov on
-    const int64_t keep = int64_t(hl[kLevOff + ov]) + hl[kLevCnt + ov];
-    const int64_t need = keep + hl[kLevCnt + ov + 1];
-    ensure_cells(p, need + need / 2 + 64, keep, s);
-    level_scratch(hl[kLevCnt + ov]);
-    k_lev_resume<<<1, 1, 0, s>>>(lev);
-    HPM_LAUNCH_CHECK();
-    enqueue(ov, true, to);
+    const int64_t total = hl[kLevCells];
+    if (total <= p.cap_cells) break;
+    if (attempt > 0) fail(HPM_ERR_DEVICE, "tree build: cell count changed between launches");
+    // every launch after the count returned at once: grow and run them again
+    ensure_cells(p, total + total / 4 + 64, 0, s);
+  }
+  // a virtual-cube set that filled up: a larger one, listed again
+  while (!uniform && p.hbox[Plan::kBoxVirtFull]) {
+    if (p.vhash_bits >= 30) fail(HPM_ERR_NO_MEMORY, "too many virtual cubes");
+    reserve_virt_set(p, p.vhash_bits + 2, s);
+    HPM_HIP(hipMemsetAsync(p.vcount.p, 0, 3 * sizeof(int), s));
+    enqueue_virt_insert(p, s);
+    sync_box(p, s);
   }
   p.nlevels = 0;
   for (int l = 0; l <= D; ++l) {
@@ -696,32 +904,16 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     p.level_off[l] = hl[kLevOff + l];
     p.nlevels = l + 1;
   }
-  p.ncells = int64_t(p.level_off[p.nlevels - 1]) + hl[kLevCnt + p.nlevels - 1];
+  p.ncells = hl[kLevCells];
   for (int l = p.nlevels; l <= kMaxLevelsHost; ++l) p.level_off[l] = int(p.ncells);
   p.dlevel.reserve(sizeof(p.level_off));
   HPM_HIP(hipMemcpyAsync(p.dlevel.p, p.level_off, sizeof(p.level_off), hipMemcpyHostToDevice, s));
-
-  // leaf list (global-id order, so leaves of levels 0 and 1 come first)
-  const int nc = int(p.ncells);
-  p.nchild.reserve(size_t(nc) * 4);
-  p.childoff.reserve(size_t(nc) * 4);
-  k_leaf_flags<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.nchild.as<int>());
-  HPM_LAUNCH_CHECK();
-  exclusive_scan_i32(p.nchild.as<int>(), p.childoff.as<int>(), nc, p.dbox + Plan::kBoxLeaves,
-                     p.scan_tmp, s);
-  p.leaves.reserve(size_t(nc) * 4);  // at most one leaf per cell
-  const int first2 = p.nlevels > 2 ? p.level_off[2] : -1;
-  k_leaf_compact<<<nblk(nc, 256), 256, 0, s>>>(nc, p.cflags.as<int>(), p.childoff.as<int>(),
-                                               p.leaves.as<int>(), first2,
-                                               p.dbox + Plan::kBoxLeavesLt2);
-  HPM_LAUNCH_CHECK();
-  // the counts are read by build_virtual after its first synchronisation
-}
-
-static void read_leaf_counts(Plan& p) {
   p.nleaves = p.hbox[Plan::kBoxLeaves];
   p.nleaves_lt2 = (p.nlevels > 2) ? p.hbox[Plan::kBoxLeavesLt2] : p.nleaves;
+  p.nvirt = uniform ? 0 : p.hbox[Plan::kBoxVirt];
+  p.n_items = p.hbox[Plan::kBoxTotal];
 }
+
 
 
 // ---------------------------------------------------------------------------------------------
@@ -733,10 +925,9 @@ static void read_leaf_counts(Plan& p) {
 // the order in which it was first found; nothing computed from it depends on that order.
 // ---------------------------------------------------------------------------------------------
 struct VirtArgs {
-  int first_target;
   int depth;
-  int nlevels;
-  const int* level_off;
+  const int* lev;        // the tree's level table
+  int64_t cap_cells;     // nothing to do while the cells outgrow the arrays
   const int* coord;
   const int* parent;
   const int* flags;
@@ -745,100 +936,129 @@ struct VirtArgs {
   const int* pb;
   const int* pe;
   const uint32_t* keys;  // sorted particle keys at depth D
-  uint32_t* hkeys;       // hash set: cube id per slot (kNoCube: empty)
-  int* hvals;            // hash set: v per slot
+  uint64_t* hslot;       // hash set: (generation << 32 | cube id) per slot
+  int* hval;             // hash set: v per slot
   uint32_t mask;         // slots - 1
   int bits;              // slots = 2^bits
+  uint32_t gen;
+  int* count;            // [0] cubes listed, [1] the set is full, [2] finish counter
+  uint32_t* vkeys;       // cube id of each v
+  int* box;
 };
 
-constexpr uint32_t kNoCube = 0xffffffffu;  // cube ids are below 2^31
-
-// multiplicative (Fibonacci) hashing: the top "bits" bits of id times 2^32 / golden ratio
-__device__ __forceinline__ uint32_t cube_hash(uint32_t id, int bits) {
-  return (id * 0x9E3779B1u) >> (32 - bits);
+// parents of targets: the cells of levels 1 .. L-2, [first, end) in id order
+__device__ __forceinline__ void parent_range(const int* lev, int& first, int& end) {
+  int nlev = 0;
+  for (int l = 0; l < kMaxLevels; ++l)
+    if (lev[kLevCnt + l] > 0) nlev = l + 1;
+  first = lev[kLevOff + 1];
+  end = nlev > 2 ? lev[kLevOff + nlev - 1] : first;
 }
 
-// One workgroup per cell of levels 1 .. L-2 (the possible parents of targets), one thread per
-// slot of its 6^3 block: a nonempty virtual cube in the interaction zone of some child (every
-// block cube except the 8 children's own positions) joins the set; the thread that adds a new id
-// takes the next index v and records the id at vkeys[v]. A full set raises *full.
-__global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a, int* count, uint32_t* vkeys,
-                                                     int* full) {
+// One workgroup per parent of targets (grid-stride), one thread per slot of its 6^3 block: a
+// nonempty virtual cube in the interaction zone of some child (every block cube except the 8
+// children's own positions) joins the set; the thread that adds a new id takes the next index v
+// and records the id at vkeys[v]. A full set raises count[1]. The last workgroup to finish copies
+// the two words to the mailbox.
+__global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
   __shared__ int s_off[kMaxLevels + 1];
+  __shared__ int s_last;
   const int tid = threadIdx.x;
-  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
+  if (tid <= kMaxLevels) s_off[tid] = a.lev[kLevOff + tid];
   __syncthreads();
-  const int par = a.first_target + blockIdx.x;
-  if (tid >= 216 || !(a.flags[par] & 1)) return;
-  const int l = level_of(par, s_off, a.nlevels) + 1;  // level of the block's cubes
-  const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
-  if (bx >= 2 && bx <= 3 && by >= 2 && by <= 3 && bz >= 2 && bz <= 3) return;  // children
-  const int pc = a.coord[par];
-  const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27, a.flags,
-                              a.child8);
-  if (z.coarse < 0) return;
-  const int shift = 3 * (a.depth - l);
-  const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
-  const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
-  const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
-  if (ve <= vb) return;
-  const uint32_t id = cube_id(l, z.key);
-  uint32_t h = cube_hash(id, a.bits);
-  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
-    const uint32_t prev = atomicCAS(&a.hkeys[h], kNoCube, id);
-    if (prev == kNoCube) {
-      const int v = atomicAdd(count, 1);
-      a.hvals[h] = v;
-      vkeys[v] = id;
-      return;
+  int first, end;
+  parent_range(a.lev, first, end);
+  for (int par = first + blockIdx.x; par < end; par += gridDim.x) {
+    if (tid >= 216 || !(a.flags[par] & 1)) continue;
+    const int l = level_of(par, s_off, kMaxLevels) + 1;  // level of the block's cubes
+    const int bx = tid % 6, by = (tid / 6) % 6, bz = tid / 36;
+    if (bx >= 2 && bx <= 3 && by >= 2 && by <= 3 && bz >= 2 && bz <= 3) continue;  // children
+    const int pc = a.coord[par];
+    const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27,
+                                a.flags, a.child8);
+    if (z.coarse < 0) continue;
+    const int shift = 3 * (a.depth - l);
+    const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
+    const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
+    const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
+    if (ve <= vb) continue;
+    const uint32_t id = cube_id(l, z.key);
+    const uint64_t mine = (uint64_t(a.gen) << 32) | id;
+    uint32_t h = cube_hash(id, a.bits);
+    bool placed = false;
+    for (uint32_t probe = 0; probe <= a.mask;) {
+      const uint64_t cur = __hip_atomic_load(&a.hslot[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (uint32_t(cur >> 32) == a.gen) {
+        if (uint32_t(cur) == id) {  // listed already
+          placed = true;
+          break;
+        }
+        h = (h + 1) & a.mask;
+        ++probe;
+        continue;
+      }
+      if (atomicCAS(reinterpret_cast<unsigned long long*>(&a.hslot[h]), (unsigned long long)cur,
+                    (unsigned long long)mine) == cur) {
+        const int v = atomicAdd(&a.count[0], 1);
+        a.hval[h] = v;
+        a.vkeys[v] = id;
+        placed = true;
+        break;
+      }
+      // the slot changed under us (another insertion of this build): look at it again
     }
-    if (prev == id) return;
-    h = (h + 1) & a.mask;
+    if (!placed) atomicExch(&a.count[1], 1);
   }
-  atomicExch(full, 1);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(&a.count[2], 1) == int(gridDim.x) - 1);
+  __syncthreads();
+  if (!s_last || tid != 0) return;
+  __threadfence();
+  a.box[Plan::kBoxVirt] = __hip_atomic_load(&a.count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  a.box[Plan::kBoxVirtFull] = __hip_atomic_load(&a.count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  a.count[2] = 0;
 }
 
-__global__ void k_copy_words(const int* src, int* dst, int count) {
-  if (int(threadIdx.x) < count) dst[threadIdx.x] = src[threadIdx.x];
-}
-
-// coordinates, particle range and level of virtual cube v, stored at cell id ncells + v
-__global__ void k_virt_cells(int nv, const uint32_t* vids, int depth, int n, const uint32_t* keys,
-                             int ncells, int* coord, int* pb, int* pe, int* vlevel, int* vlist) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  const uint32_t id = vids[v];
-  const int l = cube_id_level(id);
-  const uint32_t key = id ^ (1u << (3 * l));
-  int x = 0, y = 0, z = 0;
-  for (int b = 0; b < l; ++b) {
-    x |= int((key >> (3 * b)) & 1u) << b;
-    y |= int((key >> (3 * b + 1)) & 1u) << b;
-    z |= int((key >> (3 * b + 2)) & 1u) << b;
-  }
-  const int shift = 3 * (depth - l);
-  const int b0 = lower_bound_u32(keys, 0, n, key << shift);
-  const int e0 = lower_bound_u32(keys, b0, n, (key + 1u) << shift);
-  coord[ncells + v] = pack_coord(x, y, z);
-  pb[ncells + v] = b0;
-  pe[ncells + v] = e0;
-  vlevel[v] = l;
-  vlist[v] = ncells + v;
-}
-
-// Source gridlet id of every slot of the 6^3 block of each parent of targets: a real cell id,
-// ncells + v for virtual cube v (found in the hash set), or -1 (empty position, outside the box,
-// or not a parent).
-__global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, int nvirt, int* table) {
+// Workgroups [0, nt): the source gridlet id of every slot of the 6^3 block of each parent of
+// targets: a real cell id, ncells + v for virtual cube v (found in the hash set), or -1 (empty
+// position, outside the box, or not a parent). Workgroups from nt on: coordinates, particle range
+// and level of virtual cube v, stored at cell id ncells + v.
+__global__ __launch_bounds__(256) void k_virt_finish(VirtArgs a, int first, int nt, int ncells,
+                                                     int nvirt, int* table, int* coord, int* pb,
+                                                     int* pe, int* vlevel, int* vlist, int n) {
   __shared__ int s_off[kMaxLevels + 1];
   const int tid = threadIdx.x;
-  if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
+  if (int(blockIdx.x) >= nt) {
+    const int v = (blockIdx.x - nt) * 256 + tid;
+    if (v >= nvirt) return;
+    const uint32_t id = a.vkeys[v];
+    const int l = cube_id_level(id);
+    const uint32_t key = id ^ (1u << (3 * l));
+    int x = 0, y = 0, z = 0;
+    for (int b = 0; b < l; ++b) {
+      x |= int((key >> (3 * b)) & 1u) << b;
+      y |= int((key >> (3 * b + 1)) & 1u) << b;
+      z |= int((key >> (3 * b + 2)) & 1u) << b;
+    }
+    const int shift = 3 * (a.depth - l);
+    const int b0 = lower_bound_u32(a.keys, 0, n, key << shift);
+    const int e0 = lower_bound_u32(a.keys, b0, n, (key + 1u) << shift);
+    coord[ncells + v] = pack_coord(x, y, z);
+    pb[ncells + v] = b0;
+    pe[ncells + v] = e0;
+    vlevel[v] = l;
+    vlist[v] = ncells + v;
+    return;
+  }
+  if (tid <= kMaxLevels) s_off[tid] = a.lev[kLevOff + tid];
   __syncthreads();
   if (tid >= 216) return;
-  const int par = a.first_target + blockIdx.x;
+  const int par = first + blockIdx.x;
   int src = -1;
   if (a.flags[par] & 1) {
-    const int l = level_of(par, s_off, a.nlevels) + 1;
+    const int l = level_of(par, s_off, kMaxLevels) + 1;
     const int pc = a.coord[par];
     const IzSlot z = block_cube(coord_x(pc), coord_y(pc), coord_z(pc), l, par, tid, a.nbr27,
                                 a.flags, a.child8);
@@ -848,12 +1068,12 @@ __global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, int
       const uint32_t id = cube_id(l, z.key);
       uint32_t h = cube_hash(id, a.bits);
       for (uint32_t probe = 0; probe <= a.mask; ++probe) {
-        const uint32_t k = a.hkeys[h];
-        if (k == id) {
-          src = ncells + a.hvals[h];
+        const uint64_t k = a.hslot[h];
+        if (uint32_t(k >> 32) != a.gen) break;
+        if (uint32_t(k) == id) {
+          src = ncells + a.hval[h];
           break;
         }
-        if (k == kNoCube) break;
         h = (h + 1) & a.mask;
       }
     }
@@ -861,28 +1081,11 @@ __global__ __launch_bounds__(256) void k_block_table(VirtArgs a, int ncells, int
   table[size_t(blockIdx.x) * 216 + tid] = src;
 }
 
-static void build_block_table(Plan& p, const VirtArgs& a, int nt, hipStream_t s) {
-  p.blocks.reserve(size_t(nt) * 216 * 4);
-  p.blocks_first = a.first_target;
-  k_block_table<<<nt, 256, 0, s>>>(a, int(p.ncells), int(p.nvirt), p.blocks.as<int>());
-  HPM_LAUNCH_CHECK();
-}
-
-void build_virtual(Plan& p, hipStream_t s) {
-  p.nvirt = 0;
-  // parents of targets: cells of levels 1 .. nlevels-2
-  const int first = p.nlevels > 2 ? p.level_off[1] : 0;
-  const int nt = p.nlevels > 2 ? p.level_off[p.nlevels - 1] - first : 0;
-  if (nt <= 0) {
-    sync_box(p, s);
-    read_leaf_counts(p);
-    return;
-  }
+static VirtArgs virt_args(Plan& p) {
   VirtArgs a;
-  a.first_target = first;
   a.depth = p.depth;
-  a.nlevels = p.nlevels;
-  a.level_off = p.dlevel.as<int>();
+  a.lev = p.dlev.as<int>();
+  a.cap_cells = p.cap_cells;
   a.coord = p.ccoord.as<int>();
   a.parent = p.cparent.as<int>();
   a.flags = p.cflags.as<int>();
@@ -891,71 +1094,53 @@ void build_virtual(Plan& p, hipStream_t s) {
   a.pb = p.cpb.as<int>();
   a.pe = p.cpe.as<int>();
   a.keys = p.keys.as<uint32_t>();
-  a.hkeys = nullptr;
-  a.hvals = nullptr;
-  a.mask = 0;
-  a.bits = 0;
-  if (p.prob.uniform_depth > 0) {
-    // a uniform tree splits every occupied cell above its last level: every leaf is on the last
-    // level, and no block cube lies inside a coarser leaf, so there are no virtual cubes and the
-    // leaf counts follow from the level table (no host round trip)
-    p.nleaves = p.level_off[p.nlevels] - p.level_off[p.nlevels - 1];
-    p.nleaves_lt2 = 0;  // nlevels > 2 here
-    build_block_table(p, a, nt, s);
-    return;
-  }
-  // the set starts at 4 slots per cell (at least 2^13) and grows by 4x when a build fills it
-  int bits = 13;
-  while ((int64_t(1) << bits) < 4 * p.ncells && bits < 30) ++bits;
-  p.vhash_bits = std::max(p.vhash_bits, bits);
-  int nv = 0;
-  for (;;) {
-    const size_t slots = size_t(1) << p.vhash_bits;
-    p.vhash_keys.reserve(slots * 4);
-    p.vhash_vals.reserve(slots * 4);
-    p.vkeys.reserve(slots * 4);
-    HPM_HIP(hipMemsetAsync(p.vhash_keys.p, 0xff, slots * 4, s));
-    // the count and the full flag in device memory (the atomics of the insertion stay on the
-    // device), copied to the mailbox words afterwards
-    p.vcount.reserve(2 * sizeof(int));
-    HPM_HIP(hipMemsetAsync(p.vcount.p, 0, 2 * sizeof(int), s));
-    a.hkeys = p.vhash_keys.as<uint32_t>();
-    a.hvals = p.vhash_vals.as<int>();
-    a.mask = uint32_t(slots - 1);
-    a.bits = p.vhash_bits;
-    k_virt_insert<<<nt, 256, 0, s>>>(a, p.vcount.as<int>(), p.vkeys.as<uint32_t>(),
-                                     p.vcount.as<int>() + 1);
-    HPM_LAUNCH_CHECK();
-    k_copy_words<<<1, 64, 0, s>>>(p.vcount.as<int>(), p.dbox + Plan::kBoxVirt, 2);
-    HPM_LAUNCH_CHECK();
-    sync_box(p, s);
-    if (!p.hbox[Plan::kBoxVirtFull]) {
-      nv = p.hbox[Plan::kBoxVirt];
-      break;
-    }
-    if (p.vhash_bits >= 30) fail(HPM_ERR_NO_MEMORY, "too many virtual cubes");
-    p.vhash_bits += 2;
-  }
-  read_leaf_counts(p);
+  a.hslot = p.vhash_keys.as<uint64_t>();
+  a.hval = p.vhash_vals.as<int>();
+  a.bits = p.vhash_bits;
+  a.mask = uint32_t((size_t(1) << p.vhash_bits) - 1);
+  a.gen = p.tree_gen;
+  a.count = p.vcount.as<int>();
+  a.vkeys = p.vkeys.as<uint32_t>();
+  a.box = p.dbox;
+  return a;
+}
+
+// the virtual-cube set for the cell arrays' capacity (4 slots per cell, at least 2^13), cleared
+// when it is (re)allocated
+static void reserve_virt_set(Plan& p, int min_bits, hipStream_t s) {
+  int bits = std::max(13, min_bits);
+  while ((int64_t(1) << bits) < 4 * p.cap_cells && bits < 30) ++bits;
+  if (bits <= p.vhash_bits && p.vhash_keys.p) return;
+  p.vhash_bits = bits;
+  const size_t slots = size_t(1) << bits;
+  p.vhash_keys.release();
+  p.vhash_keys.reserve(slots * 8);
+  HPM_HIP(hipMemsetAsync(p.vhash_keys.p, 0, slots * 8, s));
+  p.vhash_vals.reserve(slots * 4);
+  p.vkeys.reserve(slots * 4);
+}
+
+static void enqueue_virt_insert(Plan& p, hipStream_t s) {
+  k_virt_insert<<<std::max(1, std::min<int>(int(p.cap_cells), 2048)), 256, 0, s>>>(virt_args(p));
+  HPM_LAUNCH_CHECK();
+}
+
+void finish_virtual(Plan& p, hipStream_t s) {
+  const int first = p.nlevels > 2 ? p.level_off[1] : 0;
+  const int nt = p.nlevels > 2 ? p.level_off[p.nlevels - 1] - first : 0;
+  const int nv = int(p.nvirt);
   if (nv > 0) {
     ensure_cells(p, p.ncells + nv, p.ncells, s);
     p.vlevel.reserve(size_t(nv) * 4);
     p.vlist.reserve(size_t(nv) * 4);
-    k_virt_cells<<<nblk(nv, 256), 256, 0, s>>>(nv, p.vkeys.as<uint32_t>(), p.depth, int(p.n),
-                                                p.keys.as<uint32_t>(), int(p.ncells),
-                                                p.ccoord.as<int>(), p.cpb.as<int>(),
-                                                p.cpe.as<int>(), p.vlevel.as<int>(),
-                                                p.vlist.as<int>());
-    HPM_LAUNCH_CHECK();
-    p.nvirt = nv;
-    a.coord = p.ccoord.as<int>();  // the cell arrays may have moved when they grew
-    a.flags = p.cflags.as<int>();
-    a.child8 = p.child8.as<int>();
-    a.nbr27 = p.nbr27.as<int>();
-    a.pb = p.cpb.as<int>();
-    a.pe = p.cpe.as<int>();
   }
-  build_block_table(p, a, nt, s);
+  p.blocks_first = first;
+  if (nt <= 0) return;
+  p.blocks.reserve(size_t(nt) * 216 * 4);
+  k_virt_finish<<<nt + nblk(nv, 256), 256, 0, s>>>(
+      virt_args(p), first, nt, int(p.ncells), nv, p.blocks.as<int>(), p.ccoord.as<int>(),
+      p.cpb.as<int>(), p.cpe.as<int>(), p.vlevel.as<int>(), p.vlist.as<int>(), int(p.n));
+  HPM_LAUNCH_CHECK();
 }
 
 }  // namespace hpm
