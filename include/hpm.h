@@ -154,13 +154,16 @@ int32_t hpm_abi_version(void);
 /*
  * Tree construction (Sec. 1): Morton keys of the n positions, a stable key sort (ties by input
  * index), the levels of real cells by the tree rule, each cell's 27 cube neighbours, and the
- * leaf list. All of it runs on the device; the host reads back one count per level. Positions
+ * leaf list. All of it runs on the device; the host reads back the counts per level. Positions
  * are copied into the plan in sorted order, so the caller may reuse x, y, z afterwards. The
  * plan holds every buffer hpm_plan_execute needs, sized for this tree.
  *   problem  host; n >= 1; x, y, z device arrays of n elements.
  *   *out     receives the plan (NULL on failure).
  * Errors: HPM_ERR_INVALID_ARG, HPM_ERR_UNSUPPORTED, HPM_ERR_OUT_OF_BOX, HPM_ERR_NONFINITE,
- * HPM_ERR_NO_MEMORY, HPM_ERR_DEVICE. The call synchronises "stream".
+ * HPM_ERR_NO_MEMORY, HPM_ERR_DEVICE. The call synchronises "stream" once, when the counts that
+ * size the tree are read back (x, y, z are no longer read after that); the last few kernels of
+ * the build are enqueued after it, so work that uses the plan on another stream must wait for
+ * "stream".
  */
 hpm_status hpm_plan_create(const hpm_problem* problem, int64_t n, const void* x, const void* y,
                            const void* z, void* stream, hpm_plan** out);

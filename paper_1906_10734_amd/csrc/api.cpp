@@ -91,8 +91,20 @@ void check_size(const hpm_problem* pr, int64_t n) {
                               "earlier version; cause not shown)");
 }
 
+// Adds the elapsed time of a timed tree build still pending to the totals.
+static void drain_tree(Plan& p) {
+  if (!p.tree_pending) return;
+  HPM_HIP(hipEventSynchronize(p.tree_ev[1]));
+  float ms = 0.f;
+  HPM_HIP(hipEventElapsedTime(&ms, p.tree_ev[0], p.tree_ev[1]));
+  p.stage_ms[0] += ms;
+  p.n_build += 1;
+  p.tree_pending = false;
+}
+
 void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z, hipStream_t s) {
   p.valid = false;
+  drain_tree(p);
   if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
   p.n = n;
   build_tree(p, x, y, z, s);
@@ -112,15 +124,10 @@ void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* 
     read_cell_parents(p);
   }
   finish_near_lists(p, s);
-  if (p.timing) {
+  if (p.timing) {  // read when the next build starts or the times are asked for
     HPM_HIP(hipEventRecord(p.tree_ev[1], s));
-    HPM_HIP(hipEventSynchronize(p.tree_ev[1]));
-    float ms = 0.f;
-    HPM_HIP(hipEventElapsedTime(&ms, p.tree_ev[0], p.tree_ev[1]));
-    p.stage_ms[0] += ms;
-    p.n_build += 1;
+    p.tree_pending = true;
   }
-  HPM_HIP(hipStreamSynchronize(s));
   p.valid = true;
 }
 
@@ -222,11 +229,11 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
 size_t Plan::device_bytes() const {
   const DevBuf* bufs[] = {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
-      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlevel, &dlev, &gridlet,
+      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
       &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
-      &tmp_keys, &tmp_vals, &hist, &scan_tmp, &tree_blk, &tree_done, &chash_slot, &chash_val};
+      &tmp_keys, &tmp_vals, &sort_ctr, &sort_status, &tree_blk, &chash_slot, &chash_val};
   size_t total = 0;
   for (const DevBuf* b : bufs) total += b->bytes;
   return total;
@@ -435,6 +442,7 @@ hpm_status hpm_plan_enable_timing(hpm_plan* plan, int32_t on) {
       p.events_created = true;
     }
     while (p.ring_count > 0) drain_one(p);
+    drain_tree(p);
     for (double& v : p.stage_ms) v = 0.0;
     p.n_exec = p.n_build = 0;
     p.timing = on != 0;
@@ -446,6 +454,7 @@ hpm_status hpm_plan_stage_times(hpm_plan* plan, double* ms, int64_t* n_exec, int
     if (!plan || !ms) fail(HPM_ERR_INVALID_ARG, "NULL argument");
     Plan& p = plan->p;
     while (p.ring_count > 0) drain_one(p);
+    drain_tree(p);
     for (int k = 0; k <= Plan::kStages + 1; ++k) ms[k] = p.stage_ms[k];
     if (n_exec) *n_exec = p.n_exec;
     if (n_build) *n_build = p.n_build;

@@ -166,7 +166,7 @@ struct NearArgs {
   int* item_off;  // their exclusive prefix sum
   int* leaf_of;   // leaf list index of each sorted particle
   unsigned long long* pairs;
-  int* done;      // finish counter (the last workgroup resets it)
+  const int* vcount;  // the virtual-cube listing's words (count, full)
   int* box;
 };
 
@@ -177,13 +177,10 @@ constexpr int kNearLanes = 32;  // lanes per leaf
 // 32 lanes per leaf, grid-stride over the leaves: lane k < 27 finds the sorted particle range of
 // near cube k (a real cell's range, or the part of a coarser leaf's range with the cube's key
 // prefix); the lanes mark the leaf's particles with its list index; the leaf's targets times
-// sources give its pairs and, cut into pieces and chunks, its work items. The last workgroup to
-// finish turns the item counts into offsets and leaves their total in the mailbox.
+// sources give its pairs and, cut into pieces and chunks, its work items.
 __global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a) {
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ int s_w[kNearThreads / 64];
   __shared__ u64 s_pairs;
-  __shared__ int s_last;
   const int tid = threadIdx.x, k = tid % kNearLanes;
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
   const int nl = a.lev[kLevLeaves];
@@ -233,39 +230,53 @@ __global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a) {
   if (k == 0 && pairs) atomicAdd(&s_pairs, pairs);
   __syncthreads();
   if (tid == 0 && s_pairs) atomicAdd(a.pairs, s_pairs);
-  __threadfence();
+}
+
+// One workgroup: exclusive scan of the item counts into offsets (chunks of 4096, four
+// consecutive counts per thread), their total into the mailbox, with the two words of the
+// virtual-cube listing that ran before.
+constexpr int kNearScanThreads = 1024;
+__global__ __launch_bounds__(kNearScanThreads) void k_near_scan(NearArgs a) {
+  __shared__ int s_w[kNearScanThreads / 64];
+  __shared__ int s_run;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
+  const int nl = a.lev[kLevLeaves];
+  if (tid == 0) s_run = 0;
   __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(a.done, 1) == int(gridDim.x) - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // the last workgroup: exclusive scan of the item counts (thread t takes a chunk)
-  const int per = (nl + kNearThreads - 1) / kNearThreads;
-  const int i0 = min(nl, tid * per), i1 = min(nl, i0 + per);
-  int sum = 0;
-  for (int i = i0; i < i1; ++i) sum += a.item_cnt[i];
-  const int lane = tid & 63, wave = tid >> 6;
-  int x = sum;
+  for (int c0 = 0; c0 < nl; c0 += 4 * kNearScanThreads) {
+    const int i = c0 + 4 * tid;
+    int v[4];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) s_w[wave] = x;
-  __syncthreads();
-  int run = x - sum, total = 0;
+    for (int k = 0; k < 4; ++k) v[k] = (i + k < nl) ? a.item_cnt[i + k] : 0;
+    const int sum = (v[0] + v[1]) + (v[2] + v[3]);
+    int x = sum;
 #pragma unroll
-  for (int w = 0; w < kNearThreads / 64; ++w) {
-    if (w < wave) run += s_w[w];
-    total += s_w[w];
-  }
-  for (int i = i0; i < i1; ++i) {
-    a.item_off[i] = run;
-    run += a.item_cnt[i];
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    int run = s_run + x - sum, all = 0;
+#pragma unroll
+    for (int w = 0; w < kNearScanThreads / 64; ++w) {
+      if (w < wave) run += s_w[w];
+      all += s_w[w];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k < nl) a.item_off[i + k] = run;
+      run += v[k];
+    }
+    __syncthreads();  // every thread has read s_run and s_w
+    if (tid == 0) s_run += all;
+    __syncthreads();
   }
   if (tid == 0) {
-    a.box[Plan::kBoxTotal] = total;
-    *a.done = 0;
+    a.box[Plan::kBoxTotal] = s_run;
+    a.box[Plan::kBoxVirt] = a.vcount[0];
+    a.box[Plan::kBoxVirtFull] = a.vcount[1];
   }
 }
 
@@ -312,10 +323,12 @@ void enqueue_near_lists(Plan& p, hipStream_t s) {
   a.item_off = p.item_off.as<int>();
   a.leaf_of = p.leaf_of.as<int>();
   a.pairs = p.pairs.as<unsigned long long>();
-  a.done = p.vcount.as<int>() + 3;
+  a.vcount = p.vcount.as<int>();
   a.box = p.dbox;
   const int groups = std::max(1, std::min(nblk(int64_t(cap), kNearThreads / kNearLanes), 2048));
   k_near_lists<<<groups, kNearThreads, 0, s>>>(a);
+  HPM_LAUNCH_CHECK();
+  k_near_scan<<<1, kNearScanThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
 }
 
@@ -738,7 +751,7 @@ static void leaf_t(Plan& p, void* phi, void* ax, void* ay, void* az, hipStream_t
   LeafArgs<T> a;
   a.n = int(p.n);
   a.leaves = p.leaves.as<int>();
-  a.level_off = p.dlevel.as<int>();
+  a.level_off = p.dlev.as<int>() + kLevOff;
   a.nlevels = p.nlevels;
   a.coord = p.ccoord.as<int>();
   a.pb = p.cpb.as<int>();

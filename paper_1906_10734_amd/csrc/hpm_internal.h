@@ -184,15 +184,15 @@ struct Plan {
   DevBuf vlist;   // [nvirt] cell id ncells + v
   // the set of virtual cube ids while they are listed: open addressing, 2^vhash_bits slots of
   // (generation << 32 | id, v), grown when a build overflows it; vcount: cubes listed, the set
-  // is full, finish counter of the listing kernel
+  // is full
   DevBuf vhash_keys, vhash_vals, vcount;
   int vhash_bits = 0;
   // source gridlet ids of the 216 block slots of each parent of targets (cells of levels
   // 1 .. L-2, from id blocks_first on)
   DevBuf blocks;
   int blocks_first = 0;
-  DevBuf dlevel;  // level offsets on the device (kMaxLevelsHost + 1 ints)
-  DevBuf dlev;    // the tree build's level table (cell ranges per level, overflow flag)
+  DevBuf dlev;    // the tree build's level table (kLevOff + l: first cell id of level l, the cell
+                  // total past the last level)
   // gridlets
   DevBuf gridlet, local, moments;  // gridlet [cells + virtual][M], local [cells][ML]
   // rows of the P2M fit: leaves of levels >= 2, then the virtual cubes (cell ids, levels)
@@ -215,10 +215,11 @@ struct Plan {
   DevBuf cell_plist;
   int cell_pbeg[kMaxLevelsHost + 1] = {0};
   Tables tab;
-  // scratch for the tree build: sort buffers, per-workgroup level counts and the count kernel's
-  // finish counter, and the hash of cube id -> cell id (slots tagged with the build's generation,
-  // so that a new build needs no clearing)
-  DevBuf tmp_keys, tmp_vals, hist, scan_tmp, tree_blk, tree_done, chash_slot, chash_val;
+  // scratch for the tree build: sort buffers and state, per-workgroup level counts, and the hash of cube
+  // id -> cell id (slots tagged with the build's generation, so that a new build needs no
+  // clearing)
+  DevBuf tmp_keys, tmp_vals, sort_ctr, sort_status, tree_blk, chash_slot, chash_val;
+  bool sort_clean = false;  // the sort state is all zero (false: clear it before the next sort)
   int chash_bits = 0;
   uint32_t tree_gen = 0;
   // pinned, device-mapped words that kernels write and the host reads after a stream
@@ -251,6 +252,7 @@ struct Plan {
   hipEvent_t ev[kRing][kStages + 1] = {};
   hipEvent_t p2p_ev[kRing][2] = {};  // around the near-zone sums, on the stream that runs them
   hipEvent_t tree_ev[2] = {};
+  bool tree_pending = false;  // tree_ev holds a timed build not yet added to stage_ms[0]
   int ring_head = 0, ring_count = 0;
   double stage_ms[kStages + 2] = {0};  // [0] tree build, [1..5] execute stages, [6] near zone
   int64_t n_exec = 0, n_build = 0;
@@ -292,7 +294,6 @@ void build_tables(Plan& p, int max_levels, hipStream_t s);
 // appends the virtual cubes to the cell arrays and builds the per-parent table of block sources.
 void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_t s);
 void finish_virtual(Plan& p, hipStream_t s);
-void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s);
 
 // ---- upsweep.hip --------------------------------------------------------------------------------
 void launch_gather_masses(Plan& p, const void* m, hipStream_t s);

@@ -820,7 +820,7 @@ static void m2l_t(Plan& p, hipStream_t s) {
   if (a.ntargets <= 0) return;
   a.nlevels = p.nlevels;
   a.depth = p.depth;
-  a.level_off = p.dlevel.as<int>();
+  a.level_off = p.dlev.as<int>() + kLevOff;
   a.coord = p.ccoord.as<int>();
   a.parent = p.cparent.as<int>();
   a.blocks = p.blocks.as<int>();
@@ -871,7 +871,7 @@ static void parents_t(Plan& p, hipStream_t s) {
       fail(HPM_ERR_DEVICE, "shared-transform buffers inconsistent with the tree");
     a.nlevels = p.nlevels;
     a.depth = p.depth;
-    a.level_off = p.dlevel.as<int>();
+    a.level_off = p.dlev.as<int>() + kLevOff;
     a.blocks = p.blocks.as<int>();
     a.first_parent = p.blocks_first;
     a.gridlet = p.gridlet.as<T>();

@@ -373,7 +373,7 @@ static void cells_t(Plan& p, hipStream_t s) {
   a.nsources = ntargets + int(p.nvirt);
   a.first_parent = p.blocks_first;
   a.nlevels = p.nlevels;
-  a.level_off = p.dlevel.as<int>();
+  a.level_off = p.dlev.as<int>() + kLevOff;
   a.child8 = p.child8.as<int>();
   a.blocks = p.blocks.as<int>();
   a.gridlet = p.gridlet.as<T>();

@@ -1,10 +1,11 @@
 // Oct-tree construction on the device (Sec. 1): Morton keys, a stable LSD radix sort of
 // (key, input index), levels of real cells by the split rule, child tables, the 27-cube
-// neighbourhood of every cell, and the leaf list.
+// neighbourhood of every cell, the leaf list, the virtual cubes of the interaction zones, and
+// the list of split cells; about a dozen launches and one host synchronisation per build.
 //
-// Cells live in one id space with the levels contiguous and each level in Morton order. A cell
-// is built from its parent's particle range by binary search for the 8 child key prefixes, so a
-// level costs O(cells log n), not O(n). Neighbour entry encoding (27 per cell, x fastest):
+// Cells live in one id space with the levels contiguous and each level in Morton order. Every
+// level is built at once from the sorted keys (see "Levels"). Neighbour entry encoding (27 per
+// cell, x fastest):
 //   >= 0        the real cell at that position (same level)
 //   -1          no particle there, or outside the box
 //   <= -2       the position lies inside the coarser leaf with id (-2 - entry); its particles are
@@ -21,13 +22,11 @@
 namespace hpm {
 
 // ---------------------------------------------------------------------------------------------
-// Exclusive prefix sum of int32 (block tiles of 2048, recursive over block totals)
+// Workgroup scan
 // ---------------------------------------------------------------------------------------------
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;
-
-__device__ __forceinline__ int block_exclusive_scan(int v, int* s_wave, int* total) {
+// exclusive scan of one value per thread over a workgroup of NT threads, and the total
+template <int NT>
+__device__ __forceinline__ int group_scan(int v, int* s_w, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int x = v;
 #pragma unroll
@@ -35,228 +34,165 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* s_wave, int* tot
     const int y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
-  if (lane == 63) s_wave[wave] = x;
+  if (lane == 63) s_w[wave] = x;
   __syncthreads();
-  int wave_pre = 0, all = 0;
-  for (int w = 0; w < kScanThreads / 64; ++w) {
-    if (w < wave) wave_pre += s_wave[w];
-    all += s_wave[w];
+  int pre = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wave) pre += s_w[w];
+    all += s_w[w];
   }
   __syncthreads();
-  *total = all;
-  return wave_pre + x - v;
-}
-
-// n is the length, or its upper bound when dn (the length in device memory) is given.
-__device__ __forceinline__ int scan_len(int n, const int* dn) { return dn ? min(*dn, n) : n; }
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, int n, const int* dn,
-                                                              int* sums) {
-  __shared__ int s_wave[kScanThreads / 64];
-  n = scan_len(n, dn);
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) v += in[base + k];
-  int total;
-  (void)block_exclusive_scan(v, s_wave, &total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int* in, int* out, int n,
-                                                            const int* dn, const int* block_off,
-                                                            int* total_out) {
-  __shared__ int s_wave[kScanThreads / 64];
-  n = scan_len(n, dn);
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int sum = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0;
-    sum += v[k];
-  }
-  int total;
-  int run = block_exclusive_scan(sum, s_wave, &total);
-  if (block_off) run += block_off[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
-  if (total_out && threadIdx.x == 0) *total_out = (block_off ? block_off[blockIdx.x] : 0) + total;
-}
-
-// One workgroup scans up to kScanSingleMax values in chunks of 1024 x 8 with a running offset
-// (one launch instead of three for the medium sizes of the tree build; larger inputs scan faster
-// on many workgroups).
-constexpr int kScanSingleThreads = 1024;
-constexpr int kScanSingleMax = kScanSingleThreads * kScanItems;
-
-// the body of k_scan_single (one workgroup of kScanSingleThreads threads)
-__device__ __forceinline__ void scan_single(const int* in, int* out, int n, const int* dn,
-                                            int* total_out) {
-  __shared__ int s_wave[kScanSingleThreads / 64];
-  __shared__ int s_run;
-  n = scan_len(n, dn);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_run = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += kScanSingleThreads * kScanItems) {
-    const int base = c0 + threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      v[k] = (base + k < n) ? in[base + k] : 0;
-      sum += v[k];
-    }
-    int x = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) s_wave[wave] = x;
-    __syncthreads();
-    int pre = s_run, all = 0;
-    for (int w = 0; w < kScanSingleThreads / 64; ++w) {
-      if (w < wave) pre += s_wave[w];
-      all += s_wave[w];
-    }
-    int run = pre + x - sum;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      if (base + k < n) out[base + k] = run;
-      run += v[k];
-    }
-    __syncthreads();  // every thread has read s_run and s_wave
-    if (threadIdx.x == 0) s_run += all;
-    __syncthreads();
-  }
-  if (total_out && threadIdx.x == 0) *total_out = s_run;
-}
-
-__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int* in, int* out, int n,
-                                                                    const int* dn, int* total_out) {
-  scan_single(in, out, n, dn, total_out);
-}
-
-static size_t scan_tmp_ints(int n) {
-  size_t t = 0;
-  while (n > kScanTile) {
-    n = (n + kScanTile - 1) / kScanTile;
-    t += 2 * size_t(n);
-  }
-  return t + 16;
-}
-
-// Tiles are laid out for n; with dn the kernels scan only the first *dn (<= n) values, and the
-// tile sums past them are zero, so the recursion over the sums needs no device length.
-static void scan_rec(const int* in, int* out, int n, const int* dn, int* total, int* tmp,
-                     hipStream_t s) {
-  const int nb = (n + kScanTile - 1) / kScanTile;
-  if (nb <= 1) {
-    k_scan_tile<<<1, kScanThreads, 0, s>>>(in, out, n, dn, nullptr, total);
-    HPM_LAUNCH_CHECK();
-    return;
-  }
-  if (n <= kScanSingleMax) {
-    k_scan_single<<<1, kScanSingleThreads, 0, s>>>(in, out, n, dn, total);
-    HPM_LAUNCH_CHECK();
-    return;
-  }
-  int* sums = tmp;
-  int* sums_scan = tmp + nb;
-  k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, dn, sums);
-  HPM_LAUNCH_CHECK();
-  scan_rec(sums, sums_scan, nb, nullptr, total, tmp + 2 * nb, s);
-  k_scan_tile<<<nb, kScanThreads, 0, s>>>(in, out, n, dn, sums_scan, nullptr);
-  HPM_LAUNCH_CHECK();
-}
-
-// out[i] = sum_{j<i} in[j]; *total (device int, may be null) = sum of all.
-void exclusive_scan_i32(const int* in, int* out, int n, int* total, DevBuf& tmp, hipStream_t s) {
-  if (n <= 0) return;
-  tmp.reserve(scan_tmp_ints(n) * sizeof(int));
-  int* t = tmp.as<int>();
-  // the last two ints of tmp hold a total when the caller passes none
-  scan_rec(in, out, n, nullptr, total, t, s);
+  total = all;
+  return pre + x - v;
 }
 
 // ---------------------------------------------------------------------------------------------
-// Morton keys
+// Stable LSD radix sort of (uint32 key, int32 value), 8 bits per pass, one launch per pass
 // ---------------------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_keys(int n, const T* x, const T* y, const T* z, double lo0, double lo1,
-                       double lo2, double hi0, double hi1, double hi2, double scale, int depth,
-                       uint32_t* keys, int* vals, int* box) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double px = double(x[i]), py = double(y[i]), pz = double(z[i]);
-  const int maxc = (1 << depth) - 1;
-  int bad = 0;
-  if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad = 2;
-  else if (!(px >= lo0 && px <= hi0 && py >= lo1 && py <= hi1 && pz >= lo2 && pz <= hi2)) bad = 1;
-  if (bad) {
-    box[bad == 2 ? Plan::kBoxNonfinite : Plan::kBoxOutOfBox] = 1;
-    keys[i] = 0;
-    vals[i] = i;
-    return;
-  }
-  // cube index floor((p - lo) * 2^D / size), clamped: the upper face belongs to the last cube
-  const int ix = min(max(int(floor((px - lo0) * scale)), 0), maxc);
-  const int iy = min(max(int(floor((py - lo1) * scale)), 0), maxc);
-  const int iz = min(max(int(floor((pz - lo2) * scale)), 0), maxc);
-  keys[i] = morton3(uint32_t(ix), uint32_t(iy), uint32_t(iz), depth);
-  vals[i] = i;
-}
-
-// ---------------------------------------------------------------------------------------------
-// Stable LSD radix sort of (uint32 key, int32 value), 8 bits per pass
-// ---------------------------------------------------------------------------------------------
+// The key kernel also counts every pass's digits over the whole input (the digit counts do not
+// depend on the order), so a pass needs only the counts of the tiles before its own for each
+// digit. A tile takes its index in the order workgroups start (an atomic counter), publishes its
+// own digit counts, and walks back over the tiles before it, adding their counts until one has
+// published its inclusive prefix; then it publishes its own inclusive prefix and scatters. Each
+// status word holds a flag (2 bits: 1 counts, 2 inclusive prefix) and the value together, read
+// and written as one 64-bit atomic, so no other ordering is needed. A tile waits only on tiles
+// that started before it; should one not have published after a long wait, the waiting tile
+// counts that tile's keys itself.
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 4;
-constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr unsigned long long kRsFlagCount = 1ull << 62, kRsFlagPrefix = 2ull << 62;
+constexpr unsigned long long kRsValue = (1ull << 62) - 1;
+constexpr int kRsSpin = 1 << 14;
+constexpr int kRsLook = 8;
+constexpr int kRsMaxPasses = 4;
 
-__global__ __launch_bounds__(kRsThreads) void k_radix_hist(const uint32_t* keys, int n, int shift,
-                                                           int* hist, int nblocks) {
-  __shared__ int cnt[256];
-  cnt[threadIdx.x] = 0;
+struct SortArgs {
+  int n;
+  int ntiles;
+  int rounds;           // a tile is rounds * 256 consecutive items
+  const uint32_t* kin;
+  const int* vin;
+  uint32_t* kout;
+  int* vout;
+  int shift;            // digit = (key >> shift) & 255
+  int pass;
+  unsigned long long* status;  // [passes][ntiles][256]
+  int* tile_ctr;               // [kRsMaxPasses] next tile index of each pass
+  const int* ghist;            // [kRsMaxPasses][256] digit counts of each pass
+  // last pass: the positions, gathered into sorted order
+  const void* x;
+  const void* y;
+  const void* z;
+  void* xs;
+  void* ys;
+  void* zs;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_keys(int n, const T* x, const T* y, const T* z, double lo0,
+                                              double lo1, double lo2, double hi0, double hi1,
+                                              double hi2, double scale, int depth, int passes,
+                                              uint32_t* keys, int* vals, int* box, int* ghist) {
+  __shared__ int s_h[kRsMaxPasses][256];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kRsMaxPasses; ++q) s_h[q][tid] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kRsTile;
-  for (int r = 0; r < kRsItems; ++r) {
-    const int i = base + r * kRsThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1);
+  const int maxc = (1 << depth) - 1;
+  for (int i = blockIdx.x * 256 + tid; i < n; i += gridDim.x * 256) {
+    const double px = double(x[i]), py = double(y[i]), pz = double(z[i]);
+    int bad = 0;
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad = 2;
+    else if (!(px >= lo0 && px <= hi0 && py >= lo1 && py <= hi1 && pz >= lo2 && pz <= hi2)) bad = 1;
+    uint32_t k = 0;
+    if (bad) {
+      box[bad == 2 ? Plan::kBoxNonfinite : Plan::kBoxOutOfBox] = 1;
+    } else {
+      // cube index floor((p - lo) * 2^D / size), clamped: the upper face belongs to the last cube
+      const int ix = min(max(int(floor((px - lo0) * scale)), 0), maxc);
+      const int iy = min(max(int(floor((py - lo1) * scale)), 0), maxc);
+      const int iz = min(max(int(floor((pz - lo2) * scale)), 0), maxc);
+      k = morton3(uint32_t(ix), uint32_t(iy), uint32_t(iz), depth);
+    }
+    keys[i] = k;
+    vals[i] = i;
+    for (int q = 0; q < passes; ++q) atomicAdd(&s_h[q][(k >> (8 * q)) & 255u], 1);
   }
   __syncthreads();
-  hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  for (int q = 0; q < passes; ++q)
+    if (s_h[q][tid]) atomicAdd(&ghist[q * 256 + tid], s_h[q][tid]);
 }
 
-// Items of a tile are taken in rounds of 256 in index order; within a round the rank of an
-// item among equal digits comes from wave ballots (lanes) and a per-digit prefix over the four
-// waves, so the output order is stable.
-__global__ __launch_bounds__(kRsThreads) void k_radix_scatter(const uint32_t* kin, const int* vin,
-                                                              uint32_t* kout, int* vout, int n,
-                                                              int shift, const int* offs,
-                                                              int nblocks) {
+template <typename T, bool LAST>
+__global__ __launch_bounds__(kRsThreads) void k_sort_pass(SortArgs a) {
+  __shared__ int s_tile;
+  __shared__ int s_cnt[256];
   __shared__ int run[256];
   __shared__ int wcnt[kRsThreads / 64][256];
+  __shared__ int s_w[kRsThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  run[tid] = offs[tid * nblocks + blockIdx.x];
-  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  const int base = blockIdx.x * kRsTile;
-  for (int r = 0; r < kRsItems; ++r) {
+  if (tid == 0) s_tile = atomicAdd(&a.tile_ctr[a.pass], 1);
+  s_cnt[tid] = 0;
+  __syncthreads();
+  const int tile = s_tile;
+  const int base = tile * a.rounds * kRsThreads;
+  for (int r = 0; r < a.rounds; ++r) {
     const int i = base + r * kRsThreads + tid;
-    const bool valid = i < n;
+    if (i < a.n) atomicAdd(&s_cnt[(a.kin[i] >> a.shift) & 255u], 1);
+  }
+  __syncthreads();
+  // thread d: the count of digit d in the tiles before this one
+  const unsigned long long own = (unsigned long long)s_cnt[tid];
+  unsigned long long* st = a.status + (size_t(a.pass) * a.ntiles) * 256;
+  __hip_atomic_store(&st[size_t(tile) * 256 + tid], (tile == 0 ? kRsFlagPrefix : kRsFlagCount) | own,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // the walk back reads kRsLook tiles' words at once (independent loads), nearest first
+  unsigned long long excl = 0;
+  bool done = tile == 0;
+  for (int j0 = tile - 1; !done && j0 >= 0; j0 -= kRsLook) {
+    unsigned long long win[kRsLook];
+#pragma unroll
+    for (int k = 0; k < kRsLook; ++k)
+      win[k] = (j0 - k >= 0) ? __hip_atomic_load(&st[size_t(j0 - k) * 256 + tid], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : 0ull;
+#pragma unroll
+    for (int k = 0; k < kRsLook; ++k) {
+      const int j = j0 - k;
+      if (done || j < 0) continue;
+      unsigned long long w = win[k];
+      for (int spin = 0; !(w >> 62) && spin < kRsSpin; ++spin)
+        w = __hip_atomic_load(&st[size_t(j) * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!(w >> 62)) {  // not published yet: count digit tid in tile j directly
+        const int jb = j * a.rounds * kRsThreads, je = min(a.n, jb + a.rounds * kRsThreads);
+        unsigned long long c = 0;
+        for (int i = jb; i < je; ++i) c += ((a.kin[i] >> a.shift) & 255u) == uint32_t(tid);
+        w = kRsFlagCount | c;
+      }
+      excl += w & kRsValue;
+      if ((w >> 62) == 2) done = true;
+    }
+  }
+  if (tile > 0)
+    __hip_atomic_store(&st[size_t(tile) * 256 + tid], kRsFlagPrefix | (excl + own), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  // first output position of digit tid: items of smaller digits, then of earlier tiles
+  int tot;
+  const int dstart = group_scan<kRsThreads>(a.ghist[a.pass * 256 + tid], s_w, tot);
+  run[tid] = dstart + int(excl);
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  // items in rounds of 256 in index order; within a round the rank of an item among equal digits
+  // comes from wave ballots (lanes) and a per-digit prefix over the four waves: a stable order
+  for (int r = 0; r < a.rounds; ++r) {
+    const int i = base + r * kRsThreads + tid;
+    const bool valid = i < a.n;
     uint32_t key = 0;
     int val = 0;
     if (valid) {
-      key = kin[i];
-      val = vin[i];
+      key = a.kin[i];
+      val = a.vin[i];
     }
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t d = (key >> a.shift) & 255u;
 #pragma unroll
     for (int w = 0; w < kRsThreads / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
@@ -283,64 +219,73 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_scatter(const uint32_t* ki
     __syncthreads();
     if (valid) {
       const int pos = wcnt[wave][d] + rank;
-      if (pos >= 0 && pos < n) {  // always true for a consistent histogram
-        kout[pos] = key;
-        vout[pos] = val;
+      if (pos >= 0 && pos < a.n) {  // always true for consistent counts
+        a.kout[pos] = key;
+        a.vout[pos] = val;
+        if constexpr (LAST) {
+          if (val >= 0 && val < a.n) {
+            static_cast<T*>(a.xs)[pos] = static_cast<const T*>(a.x)[val];
+            static_cast<T*>(a.ys)[pos] = static_cast<const T*>(a.y)[val];
+            static_cast<T*>(a.zs)[pos] = static_cast<const T*>(a.z)[val];
+          }
+        }
       }
     }
     __syncthreads();
   }
 }
 
-// Sorts n (key, value) pairs held in (ka, va); (kb, vb) is scratch of the same size. The result
-// ends in (ka, va).
-static void radix_sort(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int nbits,
-                       DevBuf& hist_buf, DevBuf& scan_tmp, hipStream_t s) {
-  if (n <= 0) return;
-  const int nblocks = (n + kRsTile - 1) / kRsTile;
-  hist_buf.reserve(size_t(256) * nblocks * sizeof(int) * 2);
-  int* hist = hist_buf.as<int>();
-  int* offs = hist + 256 * nblocks;
+// The sort state that the next build needs cleared (digit counts, tile counters, status words
+// of the tiles used), cleared after this build's passes by the tree's count kernel.
+struct SortClear {
+  int* ghist;
+  int* tile_ctr;
+  unsigned long long* status;
+  size_t status_words;
+};
+
+// Sorts the keys of k_keys (in tmp_keys, tmp_vals) into (keys, perm), gathering the positions
+// into (xs, ys, zs) on the last pass.
+template <typename T>
+static void sort_and_gather(Plan& p, int nbits, const void* x, const void* y, const void* z,
+                            hipStream_t s) {
+  const int n = int(p.n);
   const int passes = (nbits + 7) / 8;
-  uint32_t* k0 = ka;
-  int* v0 = va;
-  for (int pass = 0; pass < passes; ++pass) {
-    const int shift = 8 * pass;
-    k_radix_hist<<<nblocks, kRsThreads, 0, s>>>(ka, n, shift, hist, nblocks);
-    HPM_LAUNCH_CHECK();
-    exclusive_scan_i32(hist, offs, 256 * nblocks, nullptr, scan_tmp, s);
-    k_radix_scatter<<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, n, shift, offs, nblocks);
+  SortArgs a;
+  a.n = n;
+  a.rounds = n > (1 << 20) ? 16 : 4;
+  a.ntiles = std::max(1, (n + a.rounds * kRsThreads - 1) / (a.rounds * kRsThreads));
+  a.status = p.sort_status.as<unsigned long long>();
+  a.tile_ctr = p.sort_ctr.as<int>();
+  a.ghist = p.sort_ctr.as<int>() + kRsMaxPasses;
+  a.x = x;
+  a.y = y;
+  a.z = z;
+  a.xs = p.xs.p;
+  a.ys = p.ys.p;
+  a.zs = p.zs.p;
+  uint32_t *ka = p.tmp_keys.as<uint32_t>(), *kb = p.keys.as<uint32_t>();
+  int *va = p.tmp_vals.as<int>(), *vb = p.perm.as<int>();
+  for (int q = 0; q < passes; ++q) {
+    a.kin = ka;
+    a.vin = va;
+    a.kout = kb;
+    a.vout = vb;
+    a.shift = 8 * q;
+    a.pass = q;
+    if (q + 1 == passes) k_sort_pass<T, true><<<a.ntiles, kRsThreads, 0, s>>>(a);
+    else k_sort_pass<T, false><<<a.ntiles, kRsThreads, 0, s>>>(a);
     HPM_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (ka != k0) {
-    HPM_HIP(hipMemcpyAsync(k0, ka, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
-    HPM_HIP(hipMemcpyAsync(v0, va, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  // the sorted buffers are swapped in rather than copied
+  if (ka != p.keys.as<uint32_t>()) {
+    p.keys.swap(p.tmp_keys);
+    p.perm.swap(p.tmp_vals);
   }
 }
 
-// particle keys: sorted from (tmp_keys, tmp_vals) into (keys, perm); the sorted buffers are
-// swapped in rather than copied
-static void radix_sort_pairs(Plan& p, int nbits, hipStream_t s) {
-  const int n = int(p.n);
-  radix_sort(p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(), p.keys.as<uint32_t>(),
-             p.perm.as<int>(), n, nbits, p.hist, p.scan_tmp, s);
-  p.keys.swap(p.tmp_keys);
-  p.perm.swap(p.tmp_vals);
-}
-
-template <typename T>
-__global__ void k_gather3(int n, const int* perm, const T* x, const T* y, const T* z, T* xs, T* ys,
-                          T* zs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int j = perm[i];
-  if (j < 0 || j >= n) return;
-  xs[i] = x[j];
-  ys[i] = y[j];
-  zs[i] = z[j];
-}
 
 // ---------------------------------------------------------------------------------------------
 // Levels
@@ -351,12 +296,13 @@ __global__ void k_gather3(int n, const int* perm, const T* x, const T* y, const 
 // from a run to its sub-runs, so the cells that contain particle i are its runs of levels
 // 0 .. L(i), L(i) being the level of its leaf, and the cells that start at particle i are those
 // of levels d(i) .. L(i), d(i) being the first level at which its key prefix differs from that of
-// particle i - 1. Three launches build every level at once:
-//   count: per workgroup of particles, the cells and leaves that start in it on each level; the
-//          last workgroup to finish turns them into id bases (levels contiguous, each level in
-//          key order, which is Morton order) and writes the level table;
-//   emit:  the cells (key, coordinates, particle range, split flag), the leaf list, and a hash of
-//          cube id -> cell id;
+// particle i - 1. A few launches build every level at once:
+//   count: per workgroup of particles, the cells and leaves that start in it on each level;
+//   scan:  one workgroup turns them into id bases (levels contiguous, each level in key order,
+//          which is Morton order) and writes the level table;
+//   emit:  the cells (key, coordinates, particle range, split flag), the leaf list and the list of
+//          split cells;
+//   hash:  cube id -> cell id;
 //   link:  parent and child tables and the 27-cube neighbourhoods, by hash lookups.
 // ---------------------------------------------------------------------------------------------
 struct CellArrays {
@@ -387,11 +333,14 @@ struct TreeArgs {
   int uniform;
   int rounds;           // particles per thread: workgroup b takes [b rounds 256, (b+1) rounds 256)
   int* blk;             // [workgroups][kTreeSeq]: counts, then id bases
-  int* done;            // workgroups of the count kernel finished (its last one resets it)
   int* lev;             // level table
   int* box;             // mailbox words
-  int* zero_words;      // cleared by the count kernel for the later steps of the build (4 ints)
+  int* zero_words;      // cleared by the scan kernel for the later steps of the build (4 ints)
   unsigned long long* zero_pairs;  // near-zone pair count, likewise
+  int* sort_ctr;                   // the sort's tile counters and digit counts (cleared)
+  int sort_ctr_words;
+  unsigned long long* sort_status; // the sort's status words (cleared)
+  size_t sort_status_words;
   int64_t cap_cells;    // capacity of the cell arrays (emit and link do nothing above it)
   // emit / link
   CellArrays c;
@@ -404,26 +353,57 @@ struct TreeArgs {
   uint32_t gen;         // this build's generation: slots of other generations are empty
 };
 
+// The sorted keys as a workgroup sees them: [lo, hi) staged in LDS, the rest in device memory.
+struct KeyWin {
+  const uint32_t* g;
+  const uint32_t* s;
+  int lo, hi;
+  __device__ __forceinline__ uint32_t operator[](int j) const {
+    return (j >= lo && j < hi) ? s[j - lo] : g[j];
+  }
+};
+constexpr int kWinBefore = 128, kWinAfter = 384;  // around a round's 256 particles
+constexpr int kWinKeys = kWinBefore + kTreeThreads + kWinAfter;
+
+// stages the window of the round starting at particle base (all threads; ends with a barrier)
+__device__ __forceinline__ KeyWin stage_window(const uint32_t* keys, int n, int base,
+                                               uint32_t* s_keys) {
+  KeyWin w{keys, s_keys, max(0, base - kWinBefore), min(n, base + kTreeThreads + kWinAfter)};
+  for (int j = w.lo + int(threadIdx.x); j < w.hi; j += kTreeThreads) s_keys[j - w.lo] = keys[j];
+  __syncthreads();
+  return w;
+}
+
+// first index in [lo, hi) with keys[idx] >= v
+__device__ __forceinline__ int lower_bound_win(const KeyWin& keys, int lo, int hi, uint32_t v) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // first j in (i, hi] with keys[j] >= v (hi if none below hi); keys[i] < v
-__device__ __forceinline__ int gallop_fwd(const uint32_t* keys, int i, int hi, uint32_t v) {
+__device__ __forceinline__ int gallop_fwd(const KeyWin& keys, int i, int hi, uint32_t v) {
   int lo = i + 1, step = 1, j = i + 1;
   while (j < hi && keys[j] < v) {
     lo = j + 1;
     step <<= 1;
     j = i + step;
   }
-  return lower_bound_u32(keys, lo, min(j, hi), v);
+  return lower_bound_win(keys, lo, min(j, hi), v);
 }
 
 // first j in [0, i] with keys[j] >= v; keys[i] >= v
-__device__ __forceinline__ int gallop_back(const uint32_t* keys, int i, uint32_t v) {
+__device__ __forceinline__ int gallop_back(const KeyWin& keys, int i, uint32_t v) {
   int hi = i, step = 1, j = i - 1;
   while (j >= 0 && keys[j] >= v) {
     hi = j;
     step <<= 1;
     j = i - step;
   }
-  return lower_bound_u32(keys, max(j + 1, 0), hi, v);
+  return lower_bound_win(keys, max(j + 1, 0), hi, v);
 }
 
 // The runs that start at one particle, walked level by level.
@@ -435,14 +415,14 @@ struct Walk {
   bool live; // cells start here at the levels still to come (until the leaf)
 };
 
-__device__ __forceinline__ Walk walk_init(const TreeArgs& a, int i) {
+__device__ __forceinline__ Walk walk_init(const TreeArgs& a, const KeyWin& kw, int i) {
   Walk w{0u, i, kMaxLevels, 0, false};
   if (i >= a.n) return w;
-  const uint32_t k = a.keys[i];
+  const uint32_t k = kw[i];
   w.key = k;
   int d = 0;
   if (i > 0) {
-    const uint32_t x = k ^ a.keys[i - 1];
+    const uint32_t x = k ^ kw[i - 1];
     if (x == 0u) return w;  // same cube as the previous particle at every level
     d = a.depth - (31 - __clz(int(x))) / 3;
   }
@@ -451,8 +431,8 @@ __device__ __forceinline__ Walk walk_init(const TreeArgs& a, int i) {
     // the parent run (level d - 1) must be split: more than cap particles
     const int sh = 3 * (a.depth - d + 1);
     const uint32_t pre = k >> sh;
-    const int e = gallop_fwd(a.keys, i, a.n, (pre + 1u) << sh);
-    const int b = gallop_back(a.keys, i, pre << sh);
+    const int e = gallop_fwd(kw, i, a.n, (pre + 1u) << sh);
+    const int b = gallop_back(kw, i, pre << sh);
     if (e - b <= a.cap) return w;
     end = e;
   }
@@ -464,13 +444,13 @@ __device__ __forceinline__ Walk walk_init(const TreeArgs& a, int i) {
 
 // level l of the walk (called for l = 0, 1, ... in order): a cell starts here (cell), it is a
 // leaf (leaf), with cnt particles
-__device__ __forceinline__ void walk_step(const TreeArgs& a, Walk& w, int l, bool& cell, bool& leaf,
-                                          int& cnt) {
+__device__ __forceinline__ void walk_step(const TreeArgs& a, const KeyWin& kw, Walk& w, int l,
+                                          bool& cell, bool& leaf, int& cnt) {
   cell = leaf = false;
   cnt = 0;
   if (!w.live || l < w.lo) return;
   const int sh = 3 * (a.depth - l);
-  const int e = (l == 0) ? a.n : gallop_fwd(a.keys, w.i, w.end, ((w.key >> sh) + 1u) << sh);
+  const int e = (l == 0) ? a.n : gallop_fwd(kw, w.i, w.end, ((w.key >> sh) + 1u) << sh);
   cnt = e - w.i;
   cell = true;
   leaf = a.uniform ? (l >= a.depth) : (cnt <= a.cap || l >= a.depth);
@@ -478,71 +458,60 @@ __device__ __forceinline__ void walk_step(const TreeArgs& a, Walk& w, int l, boo
   if (leaf) w.live = false;
 }
 
-// exclusive scan of one value per thread over the workgroup (kTreeThreads), and the total
-__device__ __forceinline__ int group_scan(int v, int* s_w, int& total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) s_w[wave] = x;
-  __syncthreads();
-  int pre = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < kTreeThreads / 64; ++w) {
-    if (w < wave) pre += s_w[w];
-    all += s_w[w];
-  }
-  __syncthreads();
-  total = all;
-  return pre + x - v;
-}
-
 __global__ __launch_bounds__(kTreeThreads) void k_tree_count(TreeArgs a) {
   __shared__ int s_cnt[kTreeSeq];
-  __shared__ int s_w[kTreeThreads / 64];
-  __shared__ int s_last;
-  __shared__ int s_tot[kTreeSeq];
-  __shared__ int s_off[kTreeSeq];
+  __shared__ uint32_t s_keys[kWinKeys];
   const int tid = threadIdx.x, lane = tid & 63;
   if (tid < kTreeSeq) s_cnt[tid] = 0;
+  // the sort that ran before is done with its state: clear it for the next build
+  for (size_t w = size_t(blockIdx.x) * kTreeThreads + tid; w < a.sort_status_words;
+       w += size_t(gridDim.x) * kTreeThreads)
+    a.sort_status[w] = 0ull;
+  if (blockIdx.x == 0)
+    for (int w = tid; w < a.sort_ctr_words; w += kTreeThreads) a.sort_ctr[w] = 0;
   __syncthreads();
   for (int r = 0; r < a.rounds; ++r) {
-    const int i = (blockIdx.x * a.rounds + r) * kTreeThreads + tid;
-    Walk w = walk_init(a, i);
+    const int base = (blockIdx.x * a.rounds + r) * kTreeThreads, i = base + tid;
+    const KeyWin kw = stage_window(a.keys, a.n, base, s_keys);
+    Walk w = walk_init(a, kw, i);
     for (int l = 0; l < kMaxLevels; ++l) {
       bool cell, leaf;
       int cnt;
-      walk_step(a, w, l, cell, leaf, cnt);
+      walk_step(a, kw, w, l, cell, leaf, cnt);
       const uint64_t mc = __ballot(cell), ml = __ballot(leaf);
       if (lane == 0 && mc) atomicAdd(&s_cnt[l], __popcll(mc));
       if (lane == 0 && ml) atomicAdd(&s_cnt[kMaxLevels + l], __popcll(ml));
     }
+    __syncthreads();  // the window is read before the next round stages its own
   }
   __syncthreads();
   if (tid < kTreeSeq) a.blk[size_t(blockIdx.x) * kTreeSeq + tid] = s_cnt[tid];
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(a.done, 1) == int(gridDim.x) - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // the last workgroup: bases of every workgroup, level-major (thread t takes a chunk of them)
-  const int nb = gridDim.x, per = (nb + kTreeThreads - 1) / kTreeThreads;
-  const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
-  for (int q = 0; q < kTreeSeq; ++q) {
-    int sum = 0;
-    for (int b = b0; b < b1; ++b) sum += a.blk[size_t(b) * kTreeSeq + q];
-    int tot;
-    int run = group_scan(sum, s_w, tot);
-    if (tid == 0) s_tot[q] = tot;
-    for (int b = b0; b < b1; ++b) {
-      const int c = a.blk[size_t(b) * kTreeSeq + q];
-      a.blk[size_t(b) * kTreeSeq + q] = run;  // within the level; the level offset is added below
-      run += c;
+}
+
+// One workgroup: the id bases of every count workgroup (levels contiguous, level-major; one wave
+// scans a sequence over the workgroups in chunks of 64), the level table, its copy in the
+// mailbox, and the words the later launches of the build accumulate into, cleared.
+constexpr int kTreeScanThreads = 1024;
+__global__ __launch_bounds__(kTreeScanThreads) void k_tree_scan(TreeArgs a, int nb) {
+  __shared__ int s_tot[kTreeSeq];
+  __shared__ int s_off[kTreeSeq];
+  __shared__ int s_lev[kLevWords];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = wave; q < kTreeSeq; q += kTreeScanThreads / 64) {
+    int run = 0;
+    for (int c0 = 0; c0 < nb; c0 += 64) {
+      const int b = c0 + lane;
+      const int v = b < nb ? a.blk[size_t(b) * kTreeSeq + q] : 0;
+      int x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (b < nb) a.blk[size_t(b) * kTreeSeq + q] = run + x - v;  // within the level
+      run += __shfl(x, 63, 64);
     }
+    if (lane == 0) s_tot[q] = run;
   }
   __syncthreads();
   if (tid == 0) {
@@ -553,32 +522,38 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_count(TreeArgs a) {
       oc += s_tot[l];
       ol += s_tot[kMaxLevels + l];
     }
-    int* lev = a.lev;
+    for (int w = 0; w < kLevWords; ++w) s_lev[w] = 0;
     for (int l = 0; l < 16; ++l) {
-      lev[kLevOff + l] = l < kMaxLevels ? s_off[l] : oc;
-      lev[kLevCnt + l] = l < kMaxLevels ? s_tot[l] : 0;
+      s_lev[kLevOff + l] = l < kMaxLevels ? s_off[l] : oc;
+      s_lev[kLevCnt + l] = l < kMaxLevels ? s_tot[l] : 0;
     }
-    lev[kLevCells] = oc;
-    lev[kLevLeaves] = ol;
-    lev[kLevLeavesLt2] = s_tot[kMaxLevels] + s_tot[kMaxLevels + 1];
-    int nlev = 0, ps = 0;
+    s_lev[kLevCells] = oc;
+    s_lev[kLevLeaves] = ol;
+    s_lev[kLevLeavesLt2] = s_tot[kMaxLevels] + s_tot[kMaxLevels + 1];
+    int ps = 0;
     for (int l = 0; l < 12; ++l) {
-      lev[kLevLeafOff + l] = l < kMaxLevels ? s_off[kMaxLevels + l] : ol;
-      lev[kLevSplitOff + l] = ps;  // split cells of levels 1 .. l-1
+      s_lev[kLevLeafOff + l] = l < kMaxLevels ? s_off[kMaxLevels + l] : ol;
+      s_lev[kLevSplitOff + l] = ps;  // split cells of levels 1 .. l-1
       if (l >= 1 && l < kMaxLevels) ps += s_tot[l] - s_tot[kMaxLevels + l];
-      if (l < kMaxLevels && s_tot[l] > 0) nlev = l + 1;
     }
-    for (int w = 0; w < kLevWords; ++w) a.box[Plan::kBoxLev + w] = lev[w];
-    a.box[Plan::kBoxLeaves] = ol;
-    a.box[Plan::kBoxLeavesLt2] = lev[kLevLeavesLt2];
-    for (int l = 1; l < nlev; ++l) a.box[Plan::kBoxCellLevels + l] = lev[kLevSplitOff + l];
-    for (int w = 0; w < 4; ++w) a.zero_words[w] = 0;
-    *a.zero_pairs = 0ull;
-    *a.done = 0;
   }
   __syncthreads();
-  for (int b = b0; b < b1; ++b)
-    for (int q = 0; q < kTreeSeq; ++q) a.blk[size_t(b) * kTreeSeq + q] += s_off[q];
+  if (tid < kLevWords) {
+    a.lev[tid] = s_lev[tid];
+    a.box[Plan::kBoxLev + tid] = s_lev[tid];
+  }
+  if (tid >= 64 && tid < 64 + 12) {  // split-list bounds of levels 1 .. L-1
+    const int l = tid - 64;
+    if (l >= 1 && s_lev[kLevCnt + l] > 0) a.box[Plan::kBoxCellLevels + l] = s_lev[kLevSplitOff + l];
+  }
+  if (tid == 128) {
+    a.box[Plan::kBoxLeaves] = s_lev[kLevLeaves];
+    a.box[Plan::kBoxLeavesLt2] = s_lev[kLevLeavesLt2];
+    for (int w = 0; w < 4; ++w) a.zero_words[w] = 0;
+    *a.zero_pairs = 0ull;
+  }
+  for (size_t w = tid; w < size_t(nb) * kTreeSeq; w += kTreeScanThreads)
+    a.blk[w] += s_off[w % kTreeSeq];
 }
 
 // multiplicative (Fibonacci) hashing: the top "bits" bits of id times 2^32 / golden ratio
@@ -620,6 +595,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
   __shared__ int s_run[kTreeSeq];
   __shared__ int s_w[2][kTreeThreads / 64];
   __shared__ int s_lev[kLevWords];
+  __shared__ uint32_t s_keys[kWinKeys];
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;  // the host grows the arrays and re-runs
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < kTreeSeq) s_run[tid] = a.blk[size_t(blockIdx.x) * kTreeSeq + tid];
@@ -627,12 +603,13 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   __syncthreads();
   for (int r = 0; r < a.rounds; ++r) {
-    const int i = (blockIdx.x * a.rounds + r) * kTreeThreads + tid;
-    Walk w = walk_init(a, i);
+    const int base = (blockIdx.x * a.rounds + r) * kTreeThreads, i = base + tid;
+    const KeyWin kw = stage_window(a.keys, a.n, base, s_keys);
+    Walk w = walk_init(a, kw, i);
     for (int l = 0; l < kMaxLevels; ++l) {
       bool cell, leaf;
       int cnt;
-      walk_step(a, w, l, cell, leaf, cnt);
+      walk_step(a, kw, w, l, cell, leaf, cnt);
       const uint64_t mc = __ballot(cell), ml = __ballot(leaf);
       if (lane == 0) {
         s_w[0][wave] = __popcll(mc);
@@ -672,7 +649,6 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
         else if (l >= 1)
           a.splits[s_lev[kLevSplitOff + l] + (id - s_lev[kLevOff + l]) -
                    (lrank - s_lev[kLevLeafOff + l])] = id;
-        chash_insert(a, cube_id(l, key), id);
       }
       __syncthreads();  // every thread has read s_run and s_w
       if (tid == 0) {
@@ -682,6 +658,18 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
       __syncthreads();
     }
   }
+}
+
+// thread per cell: its cube id -> cell id into the hash (a launch of its own, so that the emit
+// kernel's level loop does not wait on the atomics)
+__global__ __launch_bounds__(256) void k_tree_hash(TreeArgs a) {
+  __shared__ int s_off[kMaxLevels + 1];
+  const int ncells = a.lev[kLevCells];
+  if (int64_t(ncells) > a.cap_cells) return;
+  if (threadIdx.x <= kMaxLevels) s_off[threadIdx.x] = a.lev[kLevOff + threadIdx.x];
+  __syncthreads();
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += gridDim.x * blockDim.x)
+    chash_insert(a, cube_id(level_of(g, s_off, kMaxLevels), a.c.key[g]), g);
 }
 
 // thread per (cell, neighbour entry): the neighbour entry of the 27-cube neighbourhood (x
@@ -780,43 +768,46 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   p.tmp_vals.reserve(size_t(n) * 4);
   clear_box(p, Plan::kBoxOutOfBox, 2, s);
 
-  const double scale = double(1 << D) / pr.box_size;
-  const double hi0 = pr.box_lo[0] + pr.box_size, hi1 = pr.box_lo[1] + pr.box_size,
-               hi2 = pr.box_lo[2] + pr.box_size;
-  if (p.prec == HPM_F32) {
-    k_keys<float><<<nblk(n, 256), 256, 0, s>>>(n, (const float*)x, (const float*)y,
-                                               (const float*)z, pr.box_lo[0], pr.box_lo[1],
-                                               pr.box_lo[2], hi0, hi1, hi2, scale, D,
-                                               p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
-                                               p.dbox);
-  } else {
-    k_keys<double><<<nblk(n, 256), 256, 0, s>>>(n, (const double*)x, (const double*)y,
-                                                (const double*)z, pr.box_lo[0], pr.box_lo[1],
-                                                pr.box_lo[2], hi0, hi1, hi2, scale, D,
-                                                p.tmp_keys.as<uint32_t>(), p.tmp_vals.as<int>(),
-                                                p.dbox);
-  }
-  HPM_LAUNCH_CHECK();
-  // invalid positions got key 0, so the build below stays well defined; the flags are checked
-  // at the synchronisation after the levels
-
-  radix_sort_pairs(p, 3 * D, s);
-
   p.xs.reserve(size_t(n) * p.elem);
   p.ys.reserve(size_t(n) * p.elem);
   p.zs.reserve(size_t(n) * p.elem);
   p.ms.reserve(size_t(n) * p.elem);
-  if (p.prec == HPM_F32)
-    k_gather3<float><<<nblk(n, 256), 256, 0, s>>>(n, p.perm.as<int>(), (const float*)x,
-                                                  (const float*)y, (const float*)z,
-                                                  p.xs.as<float>(), p.ys.as<float>(),
-                                                  p.zs.as<float>());
-  else
-    k_gather3<double><<<nblk(n, 256), 256, 0, s>>>(n, p.perm.as<int>(), (const double*)x,
-                                                   (const double*)y, (const double*)z,
-                                                   p.xs.as<double>(), p.ys.as<double>(),
-                                                   p.zs.as<double>());
-  HPM_LAUNCH_CHECK();
+  // sort state: digit counts and tile counters, and the tiles' status words; all zero between
+  // builds (cleared by the count kernel after the passes; cleared here if a build stopped short)
+  const int passes = (3 * D + 7) / 8;
+  const int rounds = n > (1 << 20) ? 16 : 4;
+  const int ntiles = std::max(1, nblk(n, rounds * kRsThreads));
+  const size_t status_words = size_t(passes) * ntiles * 256;
+  bool fresh = reserve_cleared(p.sort_ctr, size_t(kRsMaxPasses) * 257 * 4, s);
+  fresh = reserve_cleared(p.sort_status, status_words * 8, s) || fresh;
+  if (!p.sort_clean && !fresh) {
+    HPM_HIP(hipMemsetAsync(p.sort_ctr.p, 0, p.sort_ctr.bytes, s));
+    HPM_HIP(hipMemsetAsync(p.sort_status.p, 0, p.sort_status.bytes, s));
+  }
+  p.sort_clean = false;
+
+  const double scale = double(1 << D) / pr.box_size;
+  const double hi0 = pr.box_lo[0] + pr.box_size, hi1 = pr.box_lo[1] + pr.box_size,
+               hi2 = pr.box_lo[2] + pr.box_size;
+  int* ghist = p.sort_ctr.as<int>() + kRsMaxPasses;
+  const int kgrid = std::max(1, std::min(nblk(n, 1024), 1024));  // about 4 keys per thread
+  if (p.prec == HPM_F32) {
+    k_keys<float><<<kgrid, 256, 0, s>>>(n, (const float*)x, (const float*)y, (const float*)z,
+                                        pr.box_lo[0], pr.box_lo[1], pr.box_lo[2], hi0, hi1, hi2,
+                                        scale, D, passes, p.tmp_keys.as<uint32_t>(),
+                                        p.tmp_vals.as<int>(), p.dbox, ghist);
+    HPM_LAUNCH_CHECK();
+    sort_and_gather<float>(p, 3 * D, x, y, z, s);
+  } else {
+    k_keys<double><<<kgrid, 256, 0, s>>>(n, (const double*)x, (const double*)y, (const double*)z,
+                                         pr.box_lo[0], pr.box_lo[1], pr.box_lo[2], hi0, hi1, hi2,
+                                         scale, D, passes, p.tmp_keys.as<uint32_t>(),
+                                         p.tmp_vals.as<int>(), p.dbox, ghist);
+    HPM_LAUNCH_CHECK();
+    sort_and_gather<double>(p, 3 * D, x, y, z, s);
+  }
+  // invalid positions got key 0, so the build below stays well defined; the flags are checked
+  // at the synchronisation after the levels
 
   // capacity of the cell arrays: the cells a tree of this kind usually has (grown and the emit
   // and link launches repeated when the count says more)
@@ -842,18 +833,23 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   a.rounds = std::max(1, nblk(nblk(n, kTreeThreads), kTreeMaxGroups));
   const int groups = std::max(1, nblk(n, kTreeThreads * a.rounds));
   p.tree_blk.reserve(size_t(groups) * kTreeSeq * 4);
-  reserve_cleared(p.tree_done, 16, s);
   p.dlev.reserve(kLevWords * sizeof(int));
   a.blk = p.tree_blk.as<int>();
-  a.done = p.tree_done.as<int>();
   a.lev = p.dlev.as<int>();
   a.box = p.dbox;
-  p.vcount.reserve(4 * sizeof(int));  // cleared by the count kernel
+  p.vcount.reserve(4 * sizeof(int));  // cleared by the scan kernel
   p.pairs.reserve(16);
   a.zero_words = p.vcount.as<int>();
   a.zero_pairs = p.pairs.as<unsigned long long>();
+  a.sort_ctr = p.sort_ctr.as<int>();
+  a.sort_ctr_words = kRsMaxPasses * 257;
+  a.sort_status = p.sort_status.as<unsigned long long>();
+  a.sort_status_words = status_words;
   k_tree_count<<<groups, kTreeThreads, 0, s>>>(a);
   HPM_LAUNCH_CHECK();
+  k_tree_scan<<<1, kTreeScanThreads, 0, s>>>(a, groups);
+  HPM_LAUNCH_CHECK();
+  p.sort_clean = true;
   const int* hl = p.hbox + Plan::kBoxLev;
   for (int attempt = 0;; ++attempt) {
     reserve_cube_hash(p, s);
@@ -870,6 +866,8 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
     a.hmask = uint32_t((size_t(1) << p.chash_bits) - 1);
     a.gen = p.tree_gen;
     k_tree_emit<<<groups, kTreeThreads, 0, s>>>(a);
+    HPM_LAUNCH_CHECK();
+    k_tree_hash<<<std::max(1, std::min(nblk(p.cap_cells, 256), 4096)), 256, 0, s>>>(a);
     HPM_LAUNCH_CHECK();
     k_tree_link<<<std::max(1, std::min(nblk(p.cap_cells * 27, 256), 8192)), 256, 0, s>>>(a);
     HPM_LAUNCH_CHECK();
@@ -894,8 +892,9 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   while (!uniform && p.hbox[Plan::kBoxVirtFull]) {
     if (p.vhash_bits >= 30) fail(HPM_ERR_NO_MEMORY, "too many virtual cubes");
     reserve_virt_set(p, p.vhash_bits + 2, s);
-    HPM_HIP(hipMemsetAsync(p.vcount.p, 0, 3 * sizeof(int), s));
+    HPM_HIP(hipMemsetAsync(p.vcount.p, 0, 2 * sizeof(int), s));
     enqueue_virt_insert(p, s);
+    enqueue_near_lists(p, s);  // (copies the two words to the mailbox)
     sync_box(p, s);
   }
   p.nlevels = 0;
@@ -906,8 +905,6 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   }
   p.ncells = hl[kLevCells];
   for (int l = p.nlevels; l <= kMaxLevelsHost; ++l) p.level_off[l] = int(p.ncells);
-  p.dlevel.reserve(sizeof(p.level_off));
-  HPM_HIP(hipMemcpyAsync(p.dlevel.p, p.level_off, sizeof(p.level_off), hipMemcpyHostToDevice, s));
   p.nleaves = p.hbox[Plan::kBoxLeaves];
   p.nleaves_lt2 = (p.nlevels > 2) ? p.hbox[Plan::kBoxLeavesLt2] : p.nleaves;
   p.nvirt = uniform ? 0 : p.hbox[Plan::kBoxVirt];
@@ -941,7 +938,7 @@ struct VirtArgs {
   uint32_t mask;         // slots - 1
   int bits;              // slots = 2^bits
   uint32_t gen;
-  int* count;            // [0] cubes listed, [1] the set is full, [2] finish counter
+  int* count;            // [0] cubes listed, [1] the set is full
   uint32_t* vkeys;       // cube id of each v
   int* box;
 };
@@ -958,11 +955,10 @@ __device__ __forceinline__ void parent_range(const int* lev, int& first, int& en
 // One workgroup per parent of targets (grid-stride), one thread per slot of its 6^3 block: a
 // nonempty virtual cube in the interaction zone of some child (every block cube except the 8
 // children's own positions) joins the set; the thread that adds a new id takes the next index v
-// and records the id at vkeys[v]. A full set raises count[1]. The last workgroup to finish copies
-// the two words to the mailbox.
+// and records the id at vkeys[v]. A full set raises count[1]. (The near-zone list launch that
+// follows copies both words to the mailbox.)
 __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
   __shared__ int s_off[kMaxLevels + 1];
-  __shared__ int s_last;
   const int tid = threadIdx.x;
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
   if (tid <= kMaxLevels) s_off[tid] = a.lev[kLevOff + tid];
@@ -1010,15 +1006,6 @@ __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
     }
     if (!placed) atomicExch(&a.count[1], 1);
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&a.count[2], 1) == int(gridDim.x) - 1);
-  __syncthreads();
-  if (!s_last || tid != 0) return;
-  __threadfence();
-  a.box[Plan::kBoxVirt] = __hip_atomic_load(&a.count[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  a.box[Plan::kBoxVirtFull] = __hip_atomic_load(&a.count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  a.count[2] = 0;
 }
 
 // Workgroups [0, nt): the source gridlet id of every slot of the 6^3 block of each parent of
@@ -1121,7 +1108,8 @@ static void reserve_virt_set(Plan& p, int min_bits, hipStream_t s) {
 }
 
 static void enqueue_virt_insert(Plan& p, hipStream_t s) {
-  k_virt_insert<<<std::max(1, std::min<int>(int(p.cap_cells), 2048)), 256, 0, s>>>(virt_args(p));
+  // about one parent per workgroup (the parents are fewer than the cells)
+  k_virt_insert<<<std::max(1, std::min<int>(int(p.cap_cells), 16384)), 256, 0, s>>>(virt_args(p));
   HPM_LAUNCH_CHECK();
 }
 

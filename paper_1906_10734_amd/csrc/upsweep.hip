@@ -270,7 +270,7 @@ static void p2m_rows(Plan& p, const int* list, int first, int rows, const int* r
   a.row_level = row_level;
   a.first = first;
   a.count = rows;
-  a.level_off = p.dlevel.as<int>();
+  a.level_off = p.dlev.as<int>() + kLevOff;
   a.nlevels = p.nlevels;
   a.coord = p.ccoord.as<int>();
   a.pb = p.cpb.as<int>();
@@ -322,7 +322,7 @@ void build_p2m_rows(Plan& p, hipStream_t s) {
   p.p2m_level.reserve(size_t(p.p2m_rows) * 4);
   k_p2m_rows<<<nblk(p.p2m_rows, 256), 256, 0, s>>>(nl2, int(p.nleaves_lt2), p.leaves.as<int>(), nv,
                                                    int(p.ncells), p.vlevel.as<int>(),
-                                                   p.dlevel.as<int>(), p.nlevels,
+                                                   p.dlev.as<int>() + kLevOff, p.nlevels,
                                                    p.p2m_list.as<int>(), p.p2m_level.as<int>());
   HPM_LAUNCH_CHECK();
 }
