@@ -24,6 +24,7 @@
 namespace hpm {
 
 constexpr int kP2PChunk = 1024;
+constexpr int kP2PTile = 256;  // sources staged in LDS at a time (a divisor of the chunk)
 
 // The targets of a leaf with K particles in pieces of at most 64: a wave splits its 64 lanes into
 // G = floor(64 / k) groups over the sources of a k-target piece, so k in 33..55 (G = 1, at most
@@ -410,15 +411,15 @@ struct alignas(4 * sizeof(T)) SrcP {
 };
 
 // Item (leaf, first target t0, piece size kp, first source s0): lanes split as (target tl < kp,
-// source group grp < 64/kp) (lanes past the last whole group idle); sources are staged 64 at a
-// time in LDS (position and mass in one 4-vector). Each lane sums a tile's pair potentials in
+// source group grp < 64/kp) (lanes past the last whole group idle); sources are staged kP2PTile
+// at a time in LDS (position and mass in one 4-vector). Each lane sums a tile's pair potentials in
 // plain arithmetic and adds the tile's sum to its running total with compensation (Kahan); the
 // groups' partial sums are combined in group order through LDS. The self pair is recognised by
 // its place in the source sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
 template <typename T, int KER>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
-  __shared__ SrcP<T> s_src[64];
+  __shared__ SrcP<T> s_src[kP2PTile];
   __shared__ T s_part[5][64];
   const int lane = threadIdx.x;
   const int4 it = a.items[blockIdx.x];
@@ -466,21 +467,24 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     fy = fma(-mi3, dy, fy);
     fz = fma(-mi3, dz, fz);
   };
-  for (int tile = s0; tile < s_end; tile += 64) {
-    const int sidx = tile + lane;
+  for (int tile = s0; tile < s_end; tile += kP2PTile) {
     __syncthreads();
-    if (sidx < s_end) {
-      int lo = 0, hi = 27;  // largest r with s_pre[r] <= sidx
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= sidx) lo = mid;
-        else hi = mid;
+#pragma unroll
+    for (int k = 0; k < kP2PTile / 64; ++k) {
+      const int sidx = tile + lane + 64 * k;
+      if (sidx < s_end) {
+        int lo = 0, hi = 27;  // largest r with s_pre[r] <= sidx
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= sidx) lo = mid;
+          else hi = mid;
+        }
+        const int j = s_rb[lo] + (sidx - s_pre[lo]);
+        s_src[lane + 64 * k] = SrcP<T>{a.xs[j], a.ys[j], a.zs[j], a.ms[j]};
       }
-      const int j = s_rb[lo] + (sidx - s_pre[lo]);
-      s_src[lane] = SrcP<T>{a.xs[j], a.ys[j], a.zs[j], a.ms[j]};
     }
     __syncthreads();
-    const int cnt = min(64, s_end - tile);
+    const int cnt = min(kP2PTile, s_end - tile);
     if (valid) {
       pt = T(0);
       if (tile < self_hi && tile + cnt > self_lo) {  // the tile may hold the target itself
