@@ -258,6 +258,8 @@ size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
   b += c * (6 * 4 + 8 * 4 + 27 * 4);        // cell arrays (key, coords, range, parent, flags,
                                             // children, neighbours)
   b += c * (9 * 4 + 3 * 4 + 216 * 4 / 8);   // level scratch, leaf list, block tables of parents
+  b += np * 8 + np / 8;                     // radix-sort status words, level counts per workgroup
+  b += c * (2 * 12 + 4 * 16);               // cube hash, virtual-cube set
   b += c * (2 * M * s + ML * s + 2 * kpad * s + 2 * s + 8);  // gridlets of cells and virtual
                                                               // cubes, locals, fit rows
   b += c * (27 * 8 + 8 + 4 * (16 + 64 * 5 * s));  // near-zone ranges and work items
