@@ -342,8 +342,11 @@ hpm_status hpm_plan_bytes_estimate(const hpm_problem* problem, int64_t n, int64_
  * request with a problem seen before rebuilds an idle plan of that problem (no table build,
  * no allocation once the plan is large enough). When the head does not fit, idle plans are
  * released, least recently used first; if it still does not fit and nothing else runs, the
- * request fails with HPM_ERR_NO_MEMORY. Once a plan has served a request, its measured size
- * replaces the estimate in the total. Requests in flight on different workers overlap on the
+ * request fails with HPM_ERR_NO_MEMORY. The estimate can be below what a clumped set's tree
+ * needs; once the tree is built (before the evaluation buffers are sized) the request fails
+ * with HPM_ERR_NO_MEMORY if its plan would hold more than its reservation plus the budget left
+ * free at admission. Once a plan has served a request, its measured size replaces the estimate
+ * in the total. Requests in flight on different workers overlap on the
  * device; each result is the one the same problem and particles give alone (the kernels do
  * not depend on what else runs).
  *

@@ -102,12 +102,42 @@ static void drain_tree(Plan& p) {
   p.tree_pending = false;
 }
 
+// Device bytes the plan will hold once its evaluation buffers are sized for the tree just built.
+static size_t projected_bytes(const Plan& p) {
+  auto need = [](const DevBuf& b, size_t bytes) { return bytes > b.bytes ? bytes - b.bytes : size_t(0); };
+  const size_t cells = size_t(p.ncells), nv = size_t(p.nvirt), e = p.elem;
+  const size_t rows = size_t(std::max<int64_t>(p.nleaves - p.nleaves_lt2 + p.nvirt, 1));
+  const size_t items = size_t(std::max<int64_t>(p.n_items, 1));
+  const size_t parents = p.nlevels > 2 ? size_t(p.level_off[p.nlevels - 1] - p.level_off[1]) : 0;
+  size_t extra = need(p.gridlet, (cells + nv) * p.M * e) + need(p.local, cells * p.ML * e) +
+                 need(p.moments, rows * p.tab.kpad * e) + need(p.lofs, cells * 2 * e) +
+                 need(p.m2l_mean, cells * 8) + need(p.items, items * 16) +
+                 need(p.partial, items * 64 * 5 * e) + need(p.p2m_list, rows * 4) +
+                 need(p.p2m_level, rows * 4) + need(p.blocks, parents * 216 * 4) +
+                 need(p.vlevel, nv * 4) + need(p.vlist, nv * 4);
+  if (int64_t(cells + nv) > p.cap_cells)  // the cell arrays grow for the virtual cubes
+    extra += size_t(int64_t(cells + nv) - p.cap_cells) * (6 + 8 + 27) * 4;
+  if (p.prob.m2l_mode != HPM_M2L_GRID && p.nlevels > 2) {
+    const size_t spec = cell_modes(p.ng, p.ext) * 2 * e;
+    const size_t ntg = cells - size_t(p.level_off[2]);
+    extra += need(p.cell_src, (ntg + nv + 1) * spec) + need(p.cell_tgt, ntg * spec);
+  }
+  return p.device_bytes() + extra;
+}
+
 void rebuild_plan(Plan& p, int64_t n, const void* x, const void* y, const void* z, hipStream_t s) {
   p.valid = false;
   drain_tree(p);
   if (p.timing) HPM_HIP(hipEventRecord(p.tree_ev[0], s));
   p.n = n;
   build_tree(p, x, y, z, s);
+  if (p.byte_cap) {
+    const size_t want = projected_bytes(p);
+    if (want > p.byte_cap)
+      fail(HPM_ERR_NO_MEMORY, "the tree of this set needs " + std::to_string(want) +
+                                  " bytes of device memory, more than the " +
+                                  std::to_string(p.byte_cap) + " the budget leaves");
+  }
   finish_virtual(p, s);
   const size_t cells = size_t(p.ncells);
   p.gridlet.reserve((cells + size_t(p.nvirt)) * p.M * p.elem);

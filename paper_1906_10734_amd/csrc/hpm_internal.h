@@ -237,6 +237,10 @@ struct Plan {
   // words live in device memory (copied to hbox_store by sync_box), and it has no side stream
   // and no timing events
   bool noalloc = false;
+  // device bytes the plan may hold once its tree is known (0: no limit): a rebuild whose tree
+  // needs more fails with HPM_ERR_NO_MEMORY before the evaluation buffers are sized (the serving
+  // runtime sets it from the budget left at admission)
+  size_t byte_cap = 0;
   int hbox_store[kBoxWords] = {0};
   // a second stream (default priority) on which the near-zone sums run beside the far-field
   // chain of an execution, with the events that fork it from and join it to the caller's stream

@@ -184,6 +184,8 @@ void hpm_server_s::worker(int slot) {
     r->slot = slot;
     r->start_ms = now_ms();
     std::unique_ptr<hpm_plan_s> plan = std::move(entry->plan);
+    // the plan may hold its own bytes, this request's reservation and the budget still free
+    const size_t cap = budget ? entry->bytes + reserved + (budget > held ? budget - held : 0) : 0;
     lk.unlock();
 
     evicted.clear();  // frees the released plans' device memory before this request allocates
@@ -192,8 +194,10 @@ void hpm_server_s::worker(int slot) {
     const hpm_status st = guarded([&] {
       if (fresh) {
         plan.reset(new hpm_plan_s());
+        plan->p.byte_cap = cap;
         create_plan(plan->p, &r->prob, r->n, r->x, r->y, r->z, s);
       } else {
+        plan->p.byte_cap = cap;
         rebuild_plan(plan->p, r->n, r->x, r->y, r->z, s);
       }
       execute_plan(plan->p, r->m, r->phi, r->ax, r->ay, r->az, s);
