@@ -261,7 +261,7 @@ size_t Plan::device_bytes() const {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
       &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
-      &item_off, &items, &partial, &pairs, &leaf_of, &cell_src, &cell_tgt, &cell_plist,
+      &item_off, &items, &partial, &pairs, &leaf_of, &near_group_items, &cell_src, &cell_tgt, &cell_plist,
       &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
       &tmp_keys, &tmp_vals, &sort_ctr, &sort_status, &tree_blk, &chash_slot, &chash_val};
   size_t total = 0;

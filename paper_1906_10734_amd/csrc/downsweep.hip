@@ -164,36 +164,45 @@ struct NearArgs {
   int* near_rb;  // [nleaves][27]
   int* near_re;
   int* item_cnt;  // per leaf: number of work items
-  int* item_off;  // their exclusive prefix sum
+  int* item_off;  // their offset in the item list (within the workgroup's chunk until filled)
   int* leaf_of;   // leaf list index of each sorted particle
   unsigned long long* pairs;
   const int* vcount;  // the virtual-cube listing's words (count, full)
+  int* group_items;   // per workgroup of k_near_lists: its items, then their exclusive prefix
   int* box;
 };
 
 constexpr int kNearThreads = 256;
+constexpr int kNearLanes = 32;                              // lanes per leaf
+constexpr int kNearPerGroup = kNearThreads / kNearLanes;   // leaves per workgroup iteration
 using u64 = unsigned long long;
-constexpr int kNearLanes = 32;  // lanes per leaf
 
-// 32 lanes per leaf, grid-stride over the leaves: lane k < 27 finds the sorted particle range of
-// near cube k (a real cell's range, or the part of a coarser leaf's range with the cube's key
-// prefix); the lanes mark the leaf's particles with its list index; the leaf's targets times
-// sources give its pairs and, cut into pieces and chunks, its work items.
-__global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a) {
+// 32 lanes per leaf; workgroup b takes the contiguous leaves [b L, (b+1) L), eight at a time:
+// lane k < 27 finds the sorted particle range of near cube k (a real cell's range, or the part of
+// a coarser leaf's range with the cube's key prefix); the lanes mark the leaf's particles with
+// its list index; the leaf's targets times sources give its pairs and, cut into pieces and
+// chunks, its work items. Each leaf's item offset within its workgroup's chunk goes to item_off,
+// the chunk's total to group_items[b]; the item offsets are completed by k_fill_items.
+__global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a, int per_group) {
   __shared__ int s_off[kMaxLevels + 1];
   __shared__ u64 s_pairs;
-  const int tid = threadIdx.x, k = tid % kNearLanes;
+  __shared__ int s_cnt[kNearPerGroup];
+  __shared__ int s_run;
+  const int tid = threadIdx.x, k = tid % kNearLanes, slot = tid / kNearLanes;
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
   const int nl = a.lev[kLevLeaves];
   if (tid <= kMaxLevels) s_off[tid] = a.lev[kLevOff + tid];
-  if (tid == 0) s_pairs = 0ull;
+  if (tid == 0) {
+    s_pairs = 0ull;
+    s_run = 0;
+  }
   __syncthreads();
-  unsigned long long pairs = 0ull;
-  const int per_group = kNearThreads / kNearLanes;
+  u64 pairs = 0ull;
+  const int first = blockIdx.x * per_group, last = min(nl, first + per_group);
   // the trip count is the same for the whole workgroup (the lane shuffles below need every lane)
-  for (int base = blockIdx.x * per_group; base < nl; base += gridDim.x * per_group) {
-    const int li = base + tid / kNearLanes;
-    const bool live = li < nl;
+  for (int base = first; base < last; base += kNearPerGroup) {
+    const int li = base + slot;
+    const bool live = li < last;
     const int g = live ? a.leaves[li] : 0;
     const int l = live ? level_of(g, s_off, kMaxLevels) : 0;
     int rb = 0, re = 0;
@@ -218,40 +227,50 @@ __global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a) {
     int S = re - rb;
 #pragma unroll
     for (int o = kNearLanes / 2; o > 0; o >>= 1) S += __shfl_xor(S, o, kNearLanes);
-    if (!live) continue;
-    const int b = a.pb[g], e = a.pe[g];
-    for (int j = b + k; j < e; j += kNearLanes) a.leaf_of[j] = li;
-    if (k == 0) {
+    int items = 0;
+    if (live) {
+      const int b = a.pb[g], e = a.pe[g];
+      for (int j = b + k; j < e; j += kNearLanes) a.leaf_of[j] = li;
       const int K = e - b;
       const int ns = (S + kP2PChunk - 1) / kP2PChunk;
-      a.item_cnt[li] = target_pieces(K) * max(ns, 1);
-      pairs += (unsigned long long)K * (unsigned long long)S;
+      items = target_pieces(K) * max(ns, 1);
+      if (k == 0) pairs += (u64)K * (u64)S;
     }
+    if (k == 0) s_cnt[slot] = items;
+    __syncthreads();
+    if (live && k == 0) {
+      int pre = s_run;
+      for (int q = 0; q < slot; ++q) pre += s_cnt[q];
+      a.item_cnt[li] = items;
+      a.item_off[li] = pre;  // within the workgroup's chunk
+    }
+    __syncthreads();  // every leaf has read s_run and s_cnt
+    if (tid == 0)
+      for (int q = 0; q < kNearPerGroup; ++q) s_run += s_cnt[q];
+    __syncthreads();
   }
   if (k == 0 && pairs) atomicAdd(&s_pairs, pairs);
   __syncthreads();
-  if (tid == 0 && s_pairs) atomicAdd(a.pairs, s_pairs);
+  if (tid == 0) {
+    if (s_pairs) atomicAdd(a.pairs, s_pairs);
+    a.group_items[blockIdx.x] = s_run;
+  }
 }
 
-// One workgroup: exclusive scan of the item counts into offsets (chunks of 4096, four
-// consecutive counts per thread), their total into the mailbox, with the two words of the
-// virtual-cube listing that ran before.
+// One workgroup: the exclusive scan of the workgroups' item totals (their bases), the total into
+// the mailbox, with the two words of the virtual-cube listing that ran before.
 constexpr int kNearScanThreads = 1024;
-__global__ __launch_bounds__(kNearScanThreads) void k_near_scan(NearArgs a) {
+__global__ __launch_bounds__(kNearScanThreads) void k_near_scan(NearArgs a, int groups) {
   __shared__ int s_w[kNearScanThreads / 64];
   __shared__ int s_run;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;
-  const int nl = a.lev[kLevLeaves];
   if (tid == 0) s_run = 0;
   __syncthreads();
-  for (int c0 = 0; c0 < nl; c0 += 4 * kNearScanThreads) {
-    const int i = c0 + 4 * tid;
-    int v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = (i + k < nl) ? a.item_cnt[i + k] : 0;
-    const int sum = (v[0] + v[1]) + (v[2] + v[3]);
-    int x = sum;
+  for (int c0 = 0; c0 < groups; c0 += kNearScanThreads) {
+    const int i = c0 + tid;
+    const int v = i < groups ? a.group_items[i] : 0;
+    int x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(x, o, 64);
@@ -259,17 +278,13 @@ __global__ __launch_bounds__(kNearScanThreads) void k_near_scan(NearArgs a) {
     }
     if (lane == 63) s_w[wave] = x;
     __syncthreads();
-    int run = s_run + x - sum, all = 0;
+    int run = s_run + x - v, all = 0;
 #pragma unroll
     for (int w = 0; w < kNearScanThreads / 64; ++w) {
       if (w < wave) run += s_w[w];
       all += s_w[w];
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i + k < nl) a.item_off[i + k] = run;
-      run += v[k];
-    }
+    if (i < groups) a.group_items[i] = run;
     __syncthreads();  // every thread has read s_run and s_w
     if (tid == 0) s_run += all;
     __syncthreads();
@@ -281,9 +296,11 @@ __global__ __launch_bounds__(kNearScanThreads) void k_near_scan(NearArgs a) {
   }
 }
 
-__global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, const int* pe,
-                             const int* leaves, const int* near_rb, const int* near_re,
-                             int4* items) {
+// Completes each leaf's item offset (its workgroup's base plus its offset within the chunk) and
+// writes its work items.
+__global__ void k_fill_items(int nleaves, int per_group, const int* group_base, int* item_off,
+                             const int* pb, const int* pe, const int* leaves, const int* near_rb,
+                             const int* near_re, int4* items) {
   const int li = blockIdx.x * blockDim.x + threadIdx.x;
   if (li >= nleaves) return;
   int S = 0;
@@ -291,7 +308,8 @@ __global__ void k_fill_items(int nleaves, const int* item_off, const int* pb, co
   const int g = leaves[li];
   const int K = pe[g] - pb[g];
   const int ns = max((S + kP2PChunk - 1) / kP2PChunk, 1);
-  int it = item_off[li];
+  int it = group_base[li / per_group] + item_off[li];
+  item_off[li] = it;
   for (int t = 0; t < K;) {
     const Piece pc = target_piece(K, t);
     for (int sc = 0; sc < ns; ++sc) items[it++] = make_int4(li, pc.first, pc.size, sc * kP2PChunk);
@@ -325,11 +343,17 @@ void enqueue_near_lists(Plan& p, hipStream_t s) {
   a.leaf_of = p.leaf_of.as<int>();
   a.pairs = p.pairs.as<unsigned long long>();
   a.vcount = p.vcount.as<int>();
+  // contiguous chunks of leaves per workgroup, sized for the capacity (the leaf count is read on
+  // the device): at most 4096 workgroups, at least 8 leaves each
+  const int per = std::max<int>(kNearPerGroup, int(nblk(int64_t(cap), 4096)));
+  p.near_per_group = (per + kNearPerGroup - 1) / kNearPerGroup * kNearPerGroup;
+  p.near_groups = std::max(1, nblk(int64_t(cap), p.near_per_group));
+  p.near_group_items.reserve(size_t(p.near_groups) * 4);
+  a.group_items = p.near_group_items.as<int>();
   a.box = p.dbox;
-  const int groups = std::max(1, std::min(nblk(int64_t(cap), kNearThreads / kNearLanes), 2048));
-  k_near_lists<<<groups, kNearThreads, 0, s>>>(a);
+  k_near_lists<<<p.near_groups, kNearThreads, 0, s>>>(a, p.near_per_group);
   HPM_LAUNCH_CHECK();
-  k_near_scan<<<1, kNearScanThreads, 0, s>>>(a);
+  k_near_scan<<<1, kNearScanThreads, 0, s>>>(a, p.near_groups);
   HPM_LAUNCH_CHECK();
 }
 
@@ -340,7 +364,8 @@ void finish_near_lists(Plan& p, hipStream_t s) {
   p.items.reserve(size_t(std::max(total, 1)) * sizeof(int4));
   p.partial.reserve(size_t(std::max(total, 1)) * 64 * 5 * p.elem);
   if (nl <= 0) return;
-  k_fill_items<<<nblk(nl, 256), 256, 0, s>>>(nl, p.item_off.as<int>(), p.cpb.as<int>(),
+  k_fill_items<<<nblk(nl, 256), 256, 0, s>>>(nl, p.near_per_group, p.near_group_items.as<int>(),
+                                             p.item_off.as<int>(), p.cpb.as<int>(),
                                              p.cpe.as<int>(), p.leaves.as<int>(),
                                              p.near_rb.as<int>(), p.near_re.as<int>(),
                                              p.items.as<int4>());

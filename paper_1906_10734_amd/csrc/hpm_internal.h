@@ -204,6 +204,8 @@ struct Plan {
   // near-zone lists and the P2P work items (see downsweep.hip)
   DevBuf near_rb, near_re, item_cnt, item_off, items, partial, pairs;
   DevBuf leaf_of;  // [n] leaf list index of each sorted particle
+  DevBuf near_group_items;  // per workgroup of the near-list kernel: item total, then its base
+  int near_per_group = 8, near_groups = 1;  // leaves per workgroup of that kernel, workgroups
   int64_t n_items = 0;
   int64_t p2p_pairs = 0;
   int m2l_slots = 0;  // workgroups of a source-to-target launch

@@ -235,6 +235,11 @@ __global__ __launch_bounds__(kRsThreads) void k_sort_pass(SortArgs a) {
   }
 }
 
+// Tile size of the sort passes in rounds of 256 keys: 1024 keys up to 2^20 (at most 1024 tiles,
+// all resident at once), larger tiles above, so that the walk back over tiles still running
+// stays short.
+static int sort_rounds(int n) { return n <= (1 << 20) ? 4 : (n <= (1 << 22) ? 16 : 64); }
+
 // The sort state that the next build needs cleared (digit counts, tile counters, status words
 // of the tiles used), cleared after this build's passes by the tree's count kernel.
 struct SortClear {
@@ -253,7 +258,7 @@ static void sort_and_gather(Plan& p, int nbits, const void* x, const void* y, co
   const int passes = (nbits + 7) / 8;
   SortArgs a;
   a.n = n;
-  a.rounds = n > (1 << 20) ? 16 : 4;
+  a.rounds = sort_rounds(n);
   a.ntiles = std::max(1, (n + a.rounds * kRsThreads - 1) / (a.rounds * kRsThreads));
   a.status = p.sort_status.as<unsigned long long>();
   a.tile_ctr = p.sort_ctr.as<int>();
@@ -323,7 +328,7 @@ static CellArrays cells_of(Plan& p) {
 
 constexpr int kTreeThreads = 256;
 constexpr int kTreeSeq = 2 * kMaxLevels;  // per workgroup: cells of each level, leaves of each
-constexpr int kTreeMaxGroups = 2048;      // the count kernel's workgroups (rounds absorb the rest)
+constexpr int kTreeMaxGroups = 16384;     // the count kernel's workgroups (rounds absorb the rest)
 
 struct TreeArgs {
   const uint32_t* keys;  // sorted keys at depth D
@@ -499,17 +504,25 @@ __global__ __launch_bounds__(kTreeScanThreads) void k_tree_scan(TreeArgs a, int 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int q = wave; q < kTreeSeq; q += kTreeScanThreads / 64) {
     int run = 0;
-    for (int c0 = 0; c0 < nb; c0 += 64) {
-      const int b = c0 + lane;
-      const int v = b < nb ? a.blk[size_t(b) * kTreeSeq + q] : 0;
-      int x = v;
+    for (int c0 = 0; c0 < nb; c0 += 4 * 64) {  // four chunks of 64 read at once
+      int v[4];
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
+      for (int u = 0; u < 4; ++u) {
+        const int b = c0 + 64 * u + lane;
+        v[u] = b < nb ? a.blk[size_t(b) * kTreeSeq + q] : 0;
       }
-      if (b < nb) a.blk[size_t(b) * kTreeSeq + q] = run + x - v;  // within the level
-      run += __shfl(x, 63, 64);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = c0 + 64 * u + lane;
+        int x = v[u];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        if (b < nb) a.blk[size_t(b) * kTreeSeq + q] = run + x - v[u];  // within the level
+        run += __shfl(x, 63, 64);
+      }
     }
     if (lane == 0) s_tot[q] = run;
   }
@@ -775,7 +788,7 @@ void build_tree(Plan& p, const void* x, const void* y, const void* z, hipStream_
   // sort state: digit counts and tile counters, and the tiles' status words; all zero between
   // builds (cleared by the count kernel after the passes; cleared here if a build stopped short)
   const int passes = (3 * D + 7) / 8;
-  const int rounds = n > (1 << 20) ? 16 : 4;
+  const int rounds = sort_rounds(n);
   const int ntiles = std::max(1, nblk(n, rounds * kRsThreads));
   const size_t status_words = size_t(passes) * ntiles * 256;
   bool fresh = reserve_cleared(p.sort_ctr, size_t(kRsMaxPasses) * 257 * 4, s);
