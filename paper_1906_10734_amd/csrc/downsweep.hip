@@ -344,8 +344,8 @@ void enqueue_near_lists(Plan& p, hipStream_t s) {
   a.pairs = p.pairs.as<unsigned long long>();
   a.vcount = p.vcount.as<int>();
   // contiguous chunks of leaves per workgroup, sized for the capacity (the leaf count is read on
-  // the device): at most 4096 workgroups, at least 8 leaves each
-  const int per = std::max<int>(kNearPerGroup, int(nblk(int64_t(cap), 4096)));
+  // the device): at most 16384 workgroups, at least 8 leaves each
+  const int per = std::max<int>(kNearPerGroup, int(nblk(int64_t(cap), 16384)));
   p.near_per_group = (per + kNearPerGroup - 1) / kNearPerGroup * kNearPerGroup;
   p.near_groups = std::max(1, nblk(int64_t(cap), p.near_per_group));
   p.near_group_items.reserve(size_t(p.near_groups) * 4);

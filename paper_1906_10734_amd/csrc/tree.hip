@@ -504,15 +504,15 @@ __global__ __launch_bounds__(kTreeScanThreads) void k_tree_scan(TreeArgs a, int 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int q = wave; q < kTreeSeq; q += kTreeScanThreads / 64) {
     int run = 0;
-    for (int c0 = 0; c0 < nb; c0 += 4 * 64) {  // four chunks of 64 read at once
-      int v[4];
+    for (int c0 = 0; c0 < nb; c0 += 16 * 64) {  // sixteen chunks of 64 read at once
+      int v[16];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int b = c0 + 64 * u + lane;
         v[u] = b < nb ? a.blk[size_t(b) * kTreeSeq + q] : 0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int b = c0 + 64 * u + lane;
         int x = v[u];
 #pragma unroll
