@@ -98,7 +98,7 @@ def cpu_info() -> dict:
 
 
 def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, kernel="newton",
-             screening=0.0, m2l="grid", extended=False, overlap=True):
+             screening=0.0, m2l="grid", extended=False, overlap=True, fp32_strict=False):
     """Times `steps` full solves (rebuild + execute); returns timing dict and outputs."""
     p = parts.astype(np.float32 if prec == "f32" else np.float64)
     dt = torch.float32 if prec == "f32" else torch.float64
@@ -107,6 +107,8 @@ def run_path(hpm, torch, parts, prec: str, ng: int, steps: int, warmup: int, ker
                        kernel=kernel, screening=screening, m2l=m2l, extended=extended)
     plan = hpm.Plan(prob, x, y, z)
     plan.set_overlap(overlap)
+    if fp32_strict:
+        plan.set_fp32_strict(True)
     out = [torch.empty(p.n, dtype=dt, device="cuda") for _ in range(4)]
     for _ in range(warmup):
         plan.rebuild(x, y, z)
@@ -540,6 +542,19 @@ def main():
 
     f32_rms, f32_max = ferr(out32)
 
+    # the same FP32 solve with no FP64 arithmetic in the source-to-target step and L2L
+    # (float-float inverse x sums, means and constants)
+    r32s, out32s, _ = run_path(hpm, torch, parts, "f32", ng, args.steps, 1, fp32_strict=True)
+    s_rms, s_max = ferr(out32s)
+    fp32_strict = {"value": round(args.n / (r32s["ms_per_step"] * 1e-3), 1),
+                   "ms_per_step": round(r32s["ms_per_step"], 4),
+                   "m2l_ms": round(r32s["stages"]["m2l"] / max(r32s["stages"]["n_exec"], 1), 4),
+                   "force_err_rms": s_rms, "force_err_max": s_max,
+                   "phi_max_rel_diff_to_default": float(
+                       ((out32s[0] - out32[0]).abs() / out32[0].abs().clamp_min(1e-30)).max()),
+                   "note": "FP32 path with the source-to-target step's inverse x sums and means and "
+                           "L2L's constants in float-float instead of FP64"}
+
     # the screened kernel (kernel independence, Sec. 4) on the same workload, FP32, with its
     # own direct-sum reference
     lam = 0.05
@@ -754,6 +769,7 @@ def main():
                  "force_err_rms": f64_rms, "force_err_max": f64_max},
         "fp32_over_fp64": round(value / v64, 3),
         "force_err_rms": f32_rms, "force_err_max": f32_max,
+        "fp32_strict": fp32_strict,
         "phi_rel_rms_f32_vs_f64": phi_f32_vs_f64,
         "stage_ms_per_step": {k: round(v / max(r32["stages"]["n_exec"], 1), 4)
                               for k, v in r32["stages"].items() if k not in ("n_exec", "n_build")},

@@ -232,6 +232,19 @@ hpm_status hpm_plan_set_route(hpm_plan* plan, int32_t m2l_mode);
 hpm_status hpm_plan_set_overlap(hpm_plan* plan, int32_t on);
 
 /*
+ * FP32 arithmetic throughout the padded-grid route's source-to-target step: on = 1 makes the
+ * kernel form its inverse x sums (Sec. 2.1, the last inverse transform, pruned to the target's
+ * nodes) and each target's mean in float-float arithmetic (pairs of floats, error-free sums and
+ * FMA products, twiddles as float pairs from the FP64-built tables) instead of double, and L2L
+ * (Sec. 2.4) add the local constants in float-float; on = 0 (the default) uses double there.
+ * Other routes are unchanged. The results agree with the default to FP32 rounding of the inverse
+ * transforms' inputs.
+ * Errors: HPM_ERR_INVALID_ARG (NULL plan, on not 0 or 1), HPM_ERR_UNSUPPORTED (an FP64 plan, or
+ * N_g other than 4 and 6).
+ */
+hpm_status hpm_plan_set_fp32_strict(hpm_plan* plan, int32_t on);
+
+/*
  * Chooses the route by measurement: for every route the plan can use, one untimed evaluation
  * and then reps (1..1000) timed ones with masses m (device, n elements), outputs overwritten
  * (device, as hpm_plan_execute), HIP events on "stream"; keeps the fastest for later

@@ -262,7 +262,7 @@ size_t Plan::device_bytes() const {
       &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &near_group_items, &cell_src, &cell_tgt, &cell_plist,
-      &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell,
+      &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell, &tab.twff,
       &tmp_keys, &tmp_vals, &sort_ctr, &sort_status, &tree_blk, &chash_slot, &chash_val};
   size_t total = 0;
   for (const DevBuf* b : bufs) total += b->bytes;
@@ -401,6 +401,18 @@ hpm_status hpm_plan_set_overlap(hpm_plan* plan, int32_t on) {
     if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
     if (on != 0 && on != 1) fail(HPM_ERR_INVALID_ARG, "on must be 0 or 1");
     plan->p.overlap = on != 0;
+  });
+}
+
+hpm_status hpm_plan_set_fp32_strict(hpm_plan* plan, int32_t on) {
+  return guarded([&] {
+    if (!plan) fail(HPM_ERR_INVALID_ARG, "plan is NULL");
+    if (on != 0 && on != 1) fail(HPM_ERR_INVALID_ARG, "on must be 0 or 1");
+    const Plan& p = plan->p;
+    if (on && (p.prec != HPM_F32 || (p.ng != 4 && p.ng != 6)))
+      fail(HPM_ERR_UNSUPPORTED, "the all-FP32 source-to-target step is built for FP32 plans at "
+                                "ng = 4 and 6");
+    plan->p.fp32_strict = on != 0;
   });
 }
 

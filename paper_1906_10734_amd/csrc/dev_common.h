@@ -117,4 +117,49 @@ __device__ __forceinline__ void neumaier_add(T& s, T& c, T x) {
   s = t;
 }
 
+// Float-float arithmetic (a value as an unevaluated sum hi + lo of two floats, about 48 bits),
+// from error-free transformations: Knuth's two-sum and the FMA two-product.
+struct ff32 {
+  float hi, lo;
+};
+
+__device__ __forceinline__ ff32 ff_two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ ff32 ff_two_prod(float a, float b) {
+  const float p = a * b;
+  return {p, fmaf(a, b, -p)};
+}
+
+// renormalised sum of two float-float values
+__device__ __forceinline__ ff32 ff_add(ff32 a, ff32 b) {
+  const ff32 s = ff_two_sum(a.hi, b.hi);
+  const float e = s.lo + (a.lo + b.lo);
+  const float hi = s.hi + e;
+  return {hi, e - (hi - s.hi)};
+}
+
+__device__ __forceinline__ ff32 ff_neg(ff32 a) { return {-a.hi, -a.lo}; }
+
+// a float times a float-float value
+__device__ __forceinline__ ff32 ff_mul(float a, ff32 b) {
+  ff32 p = ff_two_prod(a, b.hi);
+  p.lo = fmaf(a, b.lo, p.lo);
+  const float hi = p.hi + p.lo;
+  return {hi, p.lo - (hi - p.hi)};
+}
+
+// a float-float value divided by a positive integer d (< 2^24)
+__device__ __forceinline__ ff32 ff_div(ff32 a, int d) {
+  const float fd = float(d), inv = 1.0f / fd;
+  const float q = a.hi * inv;
+  const ff32 r = ff_add(a, ff_neg(ff_two_prod(q, fd)));  // a - q d
+  const float q2 = r.hi * inv;
+  const float hi = q + q2;
+  return {hi, q2 - (hi - q)};
+}
+
 }  // namespace hpm

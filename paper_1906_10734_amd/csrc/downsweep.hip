@@ -63,12 +63,12 @@ __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
 // (the parent's part, the transpose of the separable child-to-parent matrix; absent at level 2),
 // then dPhi^C = v - mean(v) and c^C = c^P + mean(v) (+ the mean of the source-to-target result
 // when that kernel delivers it apart from a zero-mean gridlet; the constant is then summed in
-// double). One workgroup per cell.
+// double, or in float-float when that mean comes as a float pair). One workgroup per cell.
 template <typename T, int NG>
 __global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int* __restrict__ parent,
                                              const int* __restrict__ coord, const T* __restrict__ t1,
                                              T* __restrict__ local, T* __restrict__ lofs,
-                                             const double* __restrict__ m2l_mean) {
+                                             const double* __restrict__ m2l_mean, int mean_ff) {
   constexpr int M = NG * NG * NG;
   constexpr int PER = (M + 255) / 256;
   __shared__ T s_in[M], s_a[M], s_b[M];
@@ -130,7 +130,15 @@ __global__ __launch_bounds__(256) void k_l2l(int off, int has_parent, const int*
     if (e < M) local[size_t(g) * M + e] = w[r] - mean;
   }
   if (tid == 0) {
-    if (m2l_mean) {
+    if (m2l_mean && mean_ff) {
+      // the source-to-target mean as a float pair: the constant summed in float-float
+      if constexpr (sizeof(T) == 4) {
+        ff32 c = ff_add(reinterpret_cast<const ff32*>(m2l_mean)[g], ff32{float(mean), 0.0f});
+        if (has_parent) c = ff_add(c, ff32{float(lofs[2 * P]), float(lofs[2 * P + 1])});
+        lofs[2 * g] = T(c.hi);
+        lofs[2 * g + 1] = T(c.lo);
+      }
+    } else if (m2l_mean) {
       double c = m2l_mean[g] + double(mean);
       if (has_parent) c += double(lofs[2 * P]) + double(lofs[2 * P + 1]);
       const T hi = T(c);
@@ -748,7 +756,8 @@ static void l2l_t(Plan& p, int level, hipStream_t s) {
   if (cnt <= 0) return;
   k_l2l<T, NG><<<cnt, 256, 0, s>>>(off, level >= 3 ? 1 : 0, p.cparent.as<int>(), p.ccoord.as<int>(),
                                    p.tab.l2l.as<T>(), p.local.as<T>(), p.lofs.as<T>(),
-                                   p.m2l_split ? p.m2l_mean.as<double>() : nullptr);
+                                   p.m2l_split ? p.m2l_mean.as<double>() : nullptr,
+                                   p.m2l_mean_ff ? 1 : 0);
   HPM_LAUNCH_CHECK();
 }
 

@@ -147,6 +147,7 @@ struct Tables {
                  // and y only, at z offsets d <= 4 N_g, [d][ky][kx], / n^2
   DevBuf gcell;  // cell-by-cell and shared-transform routes only: [levels 2..L][343 offsets][(2N_g)^2 (N_g+1)] complex,
                  // transform of the cyclic Green array of each source cube offset, / (2 N_g)^3
+  DevBuf twff;   // FP32 plans: [8 N_g] e^{+2 pi i m / n} as {cos hi, sin hi, cos lo, sin lo}
   int kpad = 0, mpad = 0;
   int ghat_levels = 0;
   int gcell_levels = 0;
@@ -201,6 +202,11 @@ struct Plan {
   DevBuf lofs;  // [cells][2]: constant part of the local potential (compensated pair)
   DevBuf m2l_mean;          // [cells] double: mean of the source-to-target result, when split
   bool m2l_split = false;   // the source-to-target kernel writes (mean, zero-mean gridlet)
+  // FP32 plans on the padded-grid route at N_g = 4 and 6: the source-to-target kernel's inverse
+  // x sums and mean, and L2L's constant, in float-float arithmetic instead of double (the mean
+  // is then stored as a float pair in m2l_mean's slot)
+  bool fp32_strict = false;
+  bool m2l_mean_ff = false;  // m2l_mean holds float pairs (set by the kernel launch)
   // near-zone lists and the P2P work items (see downsweep.hip)
   DevBuf near_rb, near_re, item_cnt, item_off, items, partial, pairs;
   DevBuf leaf_of;  // [n] leaf list index of each sorted particle

@@ -56,6 +56,7 @@ struct M2LArgs {
   const T* gridlet;
   T* local;
   double* m2l_mean;  // z-slab kernel: mean of each target's result (the gridlet part is zero-mean)
+  const float4* twff;  // FP32 plans: e^{+2 pi i m / n} as {cos hi, sin hi, cos lo, sin lo}
   const T* ghat;
   const T* gxy;
   double lo0, lo1, lo2, size;
@@ -522,9 +523,13 @@ __device__ __forceinline__ void slab_sum(const M2LArgs<T>& a, const int* s_src, 
   }
 }
 
-template <typename T, int NG, int EXT>
+// STRICT (FP32 plans, N_g = 4 and 6): the inverse x sums and the mean in float-float arithmetic
+// against float-float twiddles from the tables, the mean stored as a float pair; no FP64
+// arithmetic in the kernel.
+template <typename T, int NG, int EXT, bool STRICT = false>
 __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   using S = SlabShape<T, NG, EXT>;
+  static_assert(!STRICT || (sizeof(T) == 4 && !S::wide), "float-float inverse: FP32, N_g <= 6");
   constexpr int n = S::n, H = S::H, NT = S::NT, D = S::D, PER = S::PER, ENT = S::ENT,
                 ZW = S::ZW, ZG = S::ZG, NL = S::NL, ML = S::ML;
   static_assert(S::fits, "slab buffers exceed the LDS budget");
@@ -537,12 +542,17 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   __shared__ double s_red[NT / 64];
   __shared__ cplx<double> s_tw[n];  // e^{+2 pi i m / n}
   __shared__ T s_green[S::green_lds ? D * H * H : 1];  // [d][ky folded][kx]
+  __shared__ float4 s_twf[STRICT ? n : 1];
   const int tid = threadIdx.x;
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
   for (int m = tid; m < n; m += NT) {
-    double sv, cv;
-    sincospi(2.0 * m / n, &sv, &cv);
-    s_tw[m] = {cv, sv};
+    if constexpr (STRICT) {
+      s_twf[m] = a.twff[m];
+    } else {
+      double sv, cv;
+      sincospi(2.0 * m / n, &sv, &cv);
+      s_tw[m] = {cv, sv};
+    }
   }
   int green_level = -1;
 
@@ -629,35 +639,75 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
     // x^-1 (Hermitian half spectrum): out = sum_k w_k Re(F_k e^{+2 pi i k X / n}), w_k = 1 at
     // k = 0 and n/2, 2 otherwise; X = (2 + c_x) N_g - EXT + xx
     const int Xt = (2 + t.cx) * NG - EXT;
-    for (int q = tid; q < ML; q += NT) {
-      const int xx = q % NL, row = q / NL;
-      const int X = Xt + xx;
-      const cplx<typename S::RedT>* F = red + size_t(row) * H;
-      double acc = 0.0;
-      int m = 0;
-      for (int k = 0; k < H; ++k) {
-        const cplx<double> f = {double(F[k].re), double(F[k].im)};
-        const cplx<double> w = s_tw[m];
-        const double v = f.re * w.re - f.im * w.im;
-        acc += (k == 0 || k == n / 2) ? v : 2.0 * v;
-        m += X;
-        if (m >= n) m -= n;
+    if constexpr (STRICT) {
+      // the same sums in float-float: each product of a float spectrum value and a float-float
+      // twiddle formed exactly to float-float precision, the terms added with renormalisation
+      ff32* s_outf = reinterpret_cast<ff32*>(s_out);
+      for (int q = tid; q < ML; q += NT) {
+        const int xx = q % NL, row = q / NL;
+        const int X = Xt + xx;
+        const cplx<typename S::RedT>* F = red + size_t(row) * H;
+        ff32 acc = {0.0f, 0.0f};
+        int m = 0;
+        for (int k = 0; k < H; ++k) {
+          const float4 w = s_twf[m];
+          ff32 v = ff_add(ff_mul(float(F[k].re), ff32{w.x, w.z}),
+                          ff_neg(ff_mul(float(F[k].im), ff32{w.y, w.w})));
+          if (!(k == 0 || k == n / 2)) v = {2.0f * v.hi, 2.0f * v.lo};
+          acc = ff_add(acc, v);
+          m += X;
+          if (m >= n) m -= n;
+        }
+        s_outf[q] = acc;
       }
-      s_out[q] = acc;
-    }
-    __syncthreads();
-    // result = mean (double, per target) + zero-mean gridlet (T)
-    double part = 0.0;
-    for (int e = tid; e < ML; e += NT) part += s_out[e];
-    part = wave_sum(part);
-    if ((tid & 63) == 0) s_red[tid >> 6] = part;
-    __syncthreads();
-    double mean = 0.0;
+      __syncthreads();
+      // result = mean (a float pair, per target) + zero-mean gridlet
+      ff32* s_redf = reinterpret_cast<ff32*>(s_red);
+      ff32 part = {0.0f, 0.0f};
+      for (int e = tid; e < ML; e += NT) part = ff_add(part, s_outf[e]);
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) mean += s_red[w];
-    mean *= 1.0 / ML;
-    for (int e = tid; e < ML; e += NT) a.local[size_t(t.g) * ML + e] = T(s_out[e] - mean);
-    if (tid == 0) a.m2l_mean[t.g] = mean;
+      for (int o = 32; o > 0; o >>= 1)
+        part = ff_add(part, ff32{__shfl_xor(part.hi, o, 64), __shfl_xor(part.lo, o, 64)});
+      if ((tid & 63) == 0) s_redf[tid >> 6] = part;
+      __syncthreads();
+      ff32 sum = {0.0f, 0.0f};
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) sum = ff_add(sum, s_redf[w]);
+      const ff32 mean = ff_div(sum, ML);
+      for (int e = tid; e < ML; e += NT)
+        a.local[size_t(t.g) * ML + e] = ff_add(s_outf[e], ff_neg(mean)).hi;
+      if (tid == 0) reinterpret_cast<ff32*>(a.m2l_mean)[t.g] = mean;
+    } else {
+      for (int q = tid; q < ML; q += NT) {
+        const int xx = q % NL, row = q / NL;
+        const int X = Xt + xx;
+        const cplx<typename S::RedT>* F = red + size_t(row) * H;
+        double acc = 0.0;
+        int m = 0;
+        for (int k = 0; k < H; ++k) {
+          const cplx<double> f = {double(F[k].re), double(F[k].im)};
+          const cplx<double> w = s_tw[m];
+          const double v = f.re * w.re - f.im * w.im;
+          acc += (k == 0 || k == n / 2) ? v : 2.0 * v;
+          m += X;
+          if (m >= n) m -= n;
+        }
+        s_out[q] = acc;
+      }
+      __syncthreads();
+      // result = mean (double, per target) + zero-mean gridlet (T)
+      double part = 0.0;
+      for (int e = tid; e < ML; e += NT) part += s_out[e];
+      part = wave_sum(part);
+      if ((tid & 63) == 0) s_red[tid >> 6] = part;
+      __syncthreads();
+      double mean = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) mean += s_red[w];
+      mean *= 1.0 / ML;
+      for (int e = tid; e < ML; e += NT) a.local[size_t(t.g) * ML + e] = T(s_out[e] - mean);
+      if (tid == 0) a.m2l_mean[t.g] = mean;
+    }
   }
 }
 
@@ -837,7 +887,18 @@ static void m2l_t(Plan& p, hipStream_t s) {
   int grid = ((a.ntargets + 7) / 8) * 8;
   if (grid > p.m2l_slots) grid = p.m2l_slots;
   p.m2l_split = m2l_kind<T, NG>() == 1;
+  p.m2l_mean_ff = false;
   if constexpr (m2l_kind<T, NG>() == 1) {
+    if constexpr (sizeof(T) == 4 && (NG == 4 || NG == 6)) {
+      if (p.fp32_strict) {
+        a.twff = p.tab.twff.as<float4>();
+        p.m2l_mean_ff = true;
+        if (p.ext) k_m2l_slab<T, NG, 1, true><<<grid, SlabShape<T, NG, 1>::NT, 0, s>>>(a);
+        else k_m2l_slab<T, NG, 0, true><<<grid, SlabShape<T, NG>::NT, 0, s>>>(a);
+        HPM_LAUNCH_CHECK();
+        return;
+      }
+    }
     if (p.ext) {
       if constexpr (NG == 4 || NG == 6) k_m2l_slab<T, NG, 1><<<grid, SlabShape<T, NG, 1>::NT, 0, s>>>(a);
       else fail(HPM_ERR_UNSUPPORTED, "no extended padded-grid kernel for this gridlet");

@@ -365,6 +365,7 @@ template <typename T, int NG, int EXT, bool SHARED = false>
 static void cells_t(Plan& p, hipStream_t s) {
   using S = CellShape<NG, EXT>;
   p.m2l_split = SHARED || sizeof(T) == 4;
+  p.m2l_mean_ff = false;  // this route's means are doubles
   if (p.nlevels <= 2) return;
   CellArgs<T> a;
   a.first_cell = p.level_off[2];

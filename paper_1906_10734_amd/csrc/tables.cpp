@@ -287,6 +287,19 @@ void build_tables(Plan& p, int max_levels, hipStream_t s) {
     p.tab.gcell_levels = nlev;
   }
   if (p.prec == HPM_F32) {
+    // e^{+2 pi i m / n} as float pairs (hi, lo) per component, for the all-FP32 inverse
+    // transform: {cos hi, sin hi, cos lo, sin lo}
+    const int nn = 8 * p.ng;
+    std::vector<double> tw(size_t(nn) * 4);
+    for (int m = 0; m < nn; ++m) {
+      const double c = std::cos(2.0 * M_PI * m / nn), sn = std::sin(2.0 * M_PI * m / nn);
+      const float ch = float(c), sh = float(sn);
+      tw[4 * m] = ch;
+      tw[4 * m + 1] = sh;
+      tw[4 * m + 2] = float(c - double(ch));
+      tw[4 * m + 3] = float(sn - double(sh));
+    }
+    upload<float>(p.tab.twff, tw, s);
     upload<float>(p.tab.fitw, w, s);
     upload<float>(p.tab.m2m, t1, s);
     upload<float>(p.tab.l2l, t1l, s);

@@ -92,6 +92,7 @@ SIGNATURES = {
                               _vp, _vp, _vp, _vp]),
     "hpm_plan_set_route": (_i32, [_vp, _i32]),
     "hpm_plan_set_overlap": (_i32, [_vp, _i32]),
+    "hpm_plan_set_fp32_strict": (_i32, [_vp, _i32]),
     "hpm_plan_autotune": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_i32),
                                  ctypes.POINTER(_d)]),
     "hpm_plan_bytes_estimate": (_i32, [ctypes.POINTER(HpmProblem), _i64,
@@ -237,6 +238,11 @@ class Plan:
         _check(_lib.hpm_plan_execute(self._h, _dev(m, dt, n, "m"), _dev(phi, dt, n, "phi"),
                                      _dev(ax, dt, n, "ax"), _dev(ay, dt, n, "ay"),
                                      _dev(az, dt, n, "az"), _stream(stream)), "hpm_plan_execute")
+
+    def set_fp32_strict(self, on: bool):
+        """hpm_plan_set_fp32_strict: float-float instead of double in the padded-grid route's
+        inverse x sums, target means and L2L constants (FP32 plans, N_g 4 and 6)."""
+        _check(_lib.hpm_plan_set_fp32_strict(self._h, 1 if on else 0), "hpm_plan_set_fp32_strict")
 
     def set_overlap(self, on: bool):
         """hpm_plan_set_overlap: near-zone sums beside the source-to-target step (True) or in
