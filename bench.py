@@ -583,7 +583,7 @@ def main():
     nbytes = m2l_bytes_per_target(ng, 4) * n_t
     gbs = nbytes / (m2l_ms * 1e-3) / 1e9
     tflops = flops / (m2l_ms * 1e-3) / 1e12
-    kernel = f"k_m2l_slab<float, {ng}, 0>" if ng >= 4 else f"k_m2l<float, {ng}>"
+    kernel = f"k_m2l_slab<float, {ng}, 0, false>" if ng >= 4 else f"k_m2l<float, {ng}>"
     ctr = counters_from_profile(f"m2l_ng{ng}_f32_plummer2p18_counters", "m2l.hip")
     valu = None
     if ctr and ctr.get("valu_insts_per_launch"):
