@@ -94,3 +94,28 @@ def test_rebuild_outgrowing_the_cell_arrays():
             assert np.array_equal(c["split"], lev.split), l
             assert np.array_equal(c["parent"], lev.parent), l
         plan.close()
+
+
+@pytest.mark.parametrize("n", [2 ** 21 + 12345, 2 ** 22 + 7])
+def test_large_sets_sort_and_levels_match_oracle(n):
+    # sets past 2^20 and 2^22 keys, where the sort passes use larger tiles (4096 and 16384 keys):
+    # the permutation (stable key order) and every level's cells equal the oracle's tree
+    import torch
+    from paper_1906_10734_amd import hpm
+    from synth import plummer_sphere
+    log(f"[tree] plummer n={n}")
+    p = plummer_sphere(n, 77).astype(np.float32)
+    x, y, z, _ = device(p, torch)
+    kw = dict(leaf_capacity=64, max_depth=10)
+    plan = hpm.Plan(gpu_problem(4, "f32", kw), x, y, z)
+    t = Tree(p.as_f64().positions(), leaf_capacity=64, max_depth=10)
+    assert np.array_equal(plan.perm(), t.perm)
+    info = plan.info()
+    assert info["cells_per_level"] == [len(l) for l in t.levels]
+    for l, lev in enumerate(t.levels):
+        c = plan.cells(l)
+        assert np.array_equal(c["pb"], lev.pb), l
+        assert np.array_equal(c["pe"], lev.pe), l
+        assert np.array_equal(c["split"], lev.split), l
+        assert np.array_equal(c["parent"], lev.parent), l
+    plan.close()
