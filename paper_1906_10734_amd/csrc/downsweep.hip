@@ -24,7 +24,14 @@
 namespace hpm {
 
 constexpr int kP2PChunk = 1024;
-constexpr int kP2PTile = 256;  // sources staged in LDS at a time (a divisor of the chunk)
+// Sources staged in LDS at a time: 256 in FP32; 192 in FP64, which keeps a workgroup's LDS at
+// 11 KB so that two fit beside the FP64 source-to-target kernel's 133 KB on a CU.
+template <typename T>
+constexpr int p2p_tile() { return sizeof(T) == 4 ? 256 : 192; }
+// A tile plus the pads of equal group slices: G L <= cnt + 2 G - 1 for G <= 16 (the bank skew
+// below), cnt + G - 1 for G <= 64.
+template <typename T>
+constexpr int p2p_slots() { return p2p_tile<T>() + 64; }
 
 // The targets of a leaf with K particles in pieces of at most 64: a wave splits its 64 lanes into
 // G = floor(64 / k) groups over the sources of a k-target piece, so k in 33..55 (G = 1, at most
@@ -398,6 +405,7 @@ struct P2PArgs {
   T* partial;  // [item][64][5]: phi, phi compensation, ax, ay, az (without G)
   T eps2;
   T inv_lam;  // 1 / screening length (screened kernel)
+  T padx, pady, padz;  // a point outside the root cell (box_lo - box_size on each axis)
 };
 
 // 1/sqrt(x). In single precision the hardware reciprocal square root (about 1 ulp); the softened
@@ -443,16 +451,35 @@ struct alignas(4 * sizeof(T)) SrcP {
   T x, y, z, m;
 };
 
+// Element j of a particle array. Single precision addresses it with a 32-bit byte offset
+// (n <= 2^30), which lets the load take the array base from scalar registers.
+template <typename T>
+__device__ __forceinline__ T load_at(const T* base, int j) {
+  if constexpr (sizeof(T) == 4) {
+    const uint32_t off = uint32_t(j) << 2;
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+  } else {
+    return base[uint32_t(j)];
+  }
+}
+
 // Item (leaf, first target t0, piece size kp, first source s0): lanes split as (target tl < kp,
-// source group grp < 64/kp) (lanes past the last whole group idle); sources are staged kP2PTile
-// at a time in LDS (position and mass in one 4-vector). Each lane sums a tile's pair potentials in
-// plain arithmetic and adds the tile's sum to its running total with compensation (Kahan); the
-// groups' partial sums are combined in group order through LDS. The self pair is recognised by
-// its place in the source sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
+// source group grp < G = 64/kp) (lanes past the last whole group idle). Sources are staged
+// p2p_tile at a time in LDS (position and mass in one 4-vector). Each group takes L =
+// ceil(cnt / G) of a tile's cnt sources, so every lane runs the same trip count: in FP32 the
+// contiguous slice [grp L, grp L + L), in FP64 the slots grp, grp + G, ... The slots past cnt
+// hold massless sources at a point outside the root cell: their pair terms are finite and their
+// products with the zero mass are exact zeros, so they change no sum. For FP32 slices and
+// G <= 16, L is bumped off multiples of 8 so that two groups' 16-byte reads in one LDS pass fall
+// in different banks. Each lane sums a tile's pair potentials in plain arithmetic and adds the
+// tile's sum to its running total with compensation (Kahan); the groups' partial sums are
+// combined in group order through LDS. The self pair is recognised by its place in the source
+// sequence: the target leaf's own cube is entry 13 of its 27 near cubes.
 template <typename T, int KER>
 __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ int s_rb[27], s_pre[28];
-  __shared__ SrcP<T> s_src[kP2PTile];
+  constexpr int kTile = p2p_tile<T>(), kSlots = p2p_slots<T>();
+  __shared__ SrcP<T> s_src[kSlots];
   __shared__ T s_part[5][64];
   const int lane = threadIdx.x;
   const int4 it = a.items[blockIdx.x];
@@ -472,6 +499,9 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   }
   __syncthreads();
   const int S = s_pre[27];
+  // FP32 reads group slices (immediate LDS offsets); FP64 reads the groups' sources interleaved,
+  // whose 32-byte reads of one pass are contiguous and so never share a bank.
+  constexpr bool kSlices = sizeof(T) == 4;
   const int G = 64 / kp;
   const int tl = lane % kp, grp = lane / kp;
   const int i = pb + t0 + tl;
@@ -487,6 +517,18 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   const int s_end = min(S, s0 + kP2PChunk);
   // the piece's own targets occupy [self_lo, self_hi) of the source sequence
   const int self_lo = s_pre[13] + (pb + t0 - s_rb[13]), self_hi = self_lo + kp;
+  // Staging cursor: the near cube r holding this lane's next source (the largest r with
+  // s_pre[r] <= source). A lane's sources only increase, so r only moves forward.
+  int r = 0;
+  {
+    const int first = min(s0 + lane, S - 1);
+    int hi = 27;
+    while (hi - r > 1) {
+      const int mid = (r + hi) >> 1;
+      if (s_pre[mid] <= first) r = mid;
+      else hi = mid;
+    }
+  }
   T pt = T(0);  // potential of the current tile
   auto pair = [&](const SrcP<T>& q, bool skip) {
     const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
@@ -500,31 +542,48 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     fy = fma(-mi3, dy, fy);
     fz = fma(-mi3, dz, fz);
   };
-  for (int tile = s0; tile < s_end; tile += kP2PTile) {
-    __syncthreads();
+  for (int tile = s0; tile < s_end; tile += kTile) {
+    const int cnt = min(kTile, s_end - tile);
+    int L = (cnt + G - 1) / G;
+    if (kSlices && G <= 16 && (L & 7) == 0) ++L;
+    const int slots = G * L;  // <= kSlots
+    // FP32 has all loads of the tile in flight before the first LDS write. FP64 stages one slot
+    // per lane at a time: that keeps the kernel within the 104 VGPRs per SIMD lane that the FP64
+    // source-to-target kernel (406 per wave) leaves free, so the two can share a SIMD when the
+    // near zone runs beside it.
+    constexpr int kStage = kSlots / 64;
+    constexpr int kBatch = sizeof(T) == 4 ? kStage : 1;
+    if (kBatch < kStage) __syncthreads();  // the previous tile's reads are done
+    for (int k0 = 0; k0 < kStage; k0 += kBatch) {
+      SrcP<T> v[kBatch];
 #pragma unroll
-    for (int k = 0; k < kP2PTile / 64; ++k) {
-      const int sidx = tile + lane + 64 * k;
-      if (sidx < s_end) {
-        int lo = 0, hi = 27;  // largest r with s_pre[r] <= sidx
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] <= sidx) lo = mid;
-          else hi = mid;
+      for (int k = 0; k < kBatch; ++k) {
+        const int q = lane + 64 * (k0 + k);
+        v[k] = SrcP<T>{a.padx, a.pady, a.padz, T(0)};
+        if (q < cnt) {
+          const int sidx = tile + q;
+          while (s_pre[r + 1] <= sidx) ++r;  // s_pre[27] = S > sidx ends it
+          const int j = s_rb[r] + (sidx - s_pre[r]);
+          v[k] = SrcP<T>{load_at(a.xs, j), load_at(a.ys, j), load_at(a.zs, j), load_at(a.ms, j)};
         }
-        const int j = s_rb[lo] + (sidx - s_pre[lo]);
-        s_src[lane + 64 * k] = SrcP<T>{a.xs[j], a.ys[j], a.zs[j], a.ms[j]};
       }
+      if (kBatch == kStage) __syncthreads();  // the previous tile's reads are done
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k)
+        if (lane + 64 * (k0 + k) < slots) s_src[lane + 64 * (k0 + k)] = v[k];
     }
     __syncthreads();
-    const int cnt = min(kP2PTile, s_end - tile);
     if (valid) {
+      // this group's e-th source: slot grp L + e (slices) or grp + e G (interleaved)
+      const SrcP<T>* src = s_src + (kSlices ? grp * L : grp);
+      const int step = kSlices ? 1 : G;
       pt = T(0);
       if (tile < self_hi && tile + cnt > self_lo) {  // the tile may hold the target itself
-        for (int e = grp; e < cnt; e += G) pair(s_src[e], tile + e == self);
+        const int own = self - tile;                 // the target's slot in the tile
+        for (int e = 0; e < L; ++e) pair(src[e * step], (kSlices ? grp * L + e : grp + e * G) == own);
       } else {
 #pragma unroll 4
-        for (int e = grp; e < cnt; e += G) pair(s_src[e], false);
+        for (int e = 0; e < L; ++e) pair(src[e * step], false);
       }
       const T yv = pt - phc;  // Kahan: ph += pt
       const T tv = ph + yv;
@@ -778,6 +837,9 @@ static void p2p_t(Plan& p, hipStream_t s) {
   b.partial = p.partial.as<T>();
   b.eps2 = T(p.prob.softening * p.prob.softening);
   b.inv_lam = (p.prob.kernel == HPM_KERNEL_YUKAWA) ? T(1.0 / p.prob.screening) : T(0);
+  b.padx = T(p.prob.box_lo[0] - p.prob.box_size);
+  b.pady = T(p.prob.box_lo[1] - p.prob.box_size);
+  b.padz = T(p.prob.box_lo[2] - p.prob.box_size);
   if (p.prob.kernel == HPM_KERNEL_YUKAWA) k_p2p<T, HPM_KERNEL_YUKAWA><<<int(p.n_items), 64, 0, s>>>(b);
   else k_p2p<T, HPM_KERNEL_NEWTON><<<int(p.n_items), 64, 0, s>>>(b);
   HPM_LAUNCH_CHECK();
