@@ -400,15 +400,76 @@ __device__ __forceinline__ int gallop_fwd(const KeyWin& keys, int i, int hi, uin
   return lower_bound_win(keys, lo, min(j, hi), v);
 }
 
-// first j in [0, i] with keys[j] >= v; keys[i] >= v
-__device__ __forceinline__ int gallop_back(const KeyWin& keys, int i, uint32_t v) {
+// first j in [floor, i] with keys[j] >= v; keys[i] >= v and keys[floor] < v
+__device__ __forceinline__ int gallop_back(const KeyWin& keys, int i, int floor, uint32_t v) {
   int hi = i, step = 1, j = i - 1;
-  while (j >= 0 && keys[j] >= v) {
+  while (keys[j] >= v) {  // ends at floor at the latest
     hi = j;
     step <<= 1;
-    j = i - step;
+    j = max(i - step, floor);
   }
-  return lower_bound_win(keys, max(j + 1, 0), hi, v);
+  return lower_bound_win(keys, j + 1, hi, v);
+}
+
+// First j in [lo, hi) with keys[j] >= v (hi if none) for every lane with `far`, the wave working
+// on one lane's search at a time: a round probes 64 evenly spaced keys of the bracket and keeps
+// the part between the last probe below v and the first at or above it, so a bracket of m keys
+// takes about log_64 m rounds of parallel loads instead of 2 log_2 m dependent ones. Called by
+// the whole wave; lanes without `far` get res back unchanged.
+__device__ __forceinline__ int wave_lower_bound(const KeyWin& keys, bool far, int lo, int hi,
+                                                uint32_t v, int res) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pend = __ballot(far);
+  while (pend) {
+    const int src = __ffsll((unsigned long long)pend) - 1;
+    pend &= pend - 1;
+    int l = __shfl(lo, src, 64), h = __shfl(hi, src, 64);
+    const uint32_t vv = uint32_t(__shfl(int(v), src, 64));
+    // the answer lies in [l, h]: keys before l are below vv, and h is the bracket's end or holds
+    // a key at or above vv
+    while (h - l > 64) {
+      const int step = (h - l + 63) >> 6;
+      const int q = l + (lane + 1) * step - 1;
+      const uint64_t m = __ballot(q < h && keys[q] >= vv);
+      if (m) {
+        const int f = __ffsll((unsigned long long)m) - 1;
+        h = l + (f + 1) * step - 1;
+        l += f * step;
+      } else {
+        l += ((h - l) / step) * step;  // past the last probe below h
+      }
+    }
+    const int q = l + lane;
+    const uint64_t m = __ballot(q < h && keys[q] >= vv);
+    if (lane == src) res = m ? l + __ffsll((unsigned long long)m) - 1 : h;
+  }
+  return res;
+}
+
+// first j in (i, hi] with keys[j] >= v (hi if none below hi), keys[i] < v, for the lanes with
+// `need` (i inside the window); whole wave
+__device__ __forceinline__ int search_fwd(const KeyWin& kw, bool need, int i, int hi, uint32_t v) {
+  int res = hi;
+  bool far = false;
+  const int wend = min(hi, kw.hi);
+  if (need) {
+    if (wend > i + 1 && kw[wend - 1] >= v) res = gallop_fwd(kw, i, wend - 1, v);
+    else far = wend < hi;  // else every key below hi is below v
+  }
+  return wave_lower_bound(kw, far, wend, hi, v, res);
+}
+
+// first j in [0, i] with keys[j] >= v, keys[i] >= v, for the lanes with `need` (i inside the
+// window); whole wave
+__device__ __forceinline__ int search_back(const KeyWin& kw, bool need, int i, uint32_t v) {
+  int res = 0;
+  bool far = false;
+  const int wbeg = kw.lo;
+  if (need) {
+    if (kw[wbeg] < v) res = gallop_back(kw, i, wbeg, v);
+    else far = wbeg > 0;  // else the answer is 0
+  }
+  return wave_lower_bound(kw, far, 0, wbeg, v, res);
 }
 
 // The runs that start at one particle, walked level by level.
@@ -420,46 +481,48 @@ struct Walk {
   bool live; // cells start here at the levels still to come (until the leaf)
 };
 
+// whole wave (the searches are shared)
 __device__ __forceinline__ Walk walk_init(const TreeArgs& a, const KeyWin& kw, int i) {
   Walk w{0u, i, kMaxLevels, 0, false};
-  if (i >= a.n) return w;
-  const uint32_t k = kw[i];
-  w.key = k;
+  bool cand = i < a.n;
   int d = 0;
-  if (i > 0) {
-    const uint32_t x = k ^ kw[i - 1];
-    if (x == 0u) return w;  // same cube as the previous particle at every level
-    d = a.depth - (31 - __clz(int(x))) / 3;
+  if (cand) {
+    w.key = kw[i];
+    if (i > 0) {
+      const uint32_t x = w.key ^ kw[i - 1];
+      if (x == 0u) cand = false;  // same cube as the previous particle at every level
+      else d = a.depth - (31 - __clz(int(x))) / 3;
+    }
   }
-  int end = a.n;
-  if (d >= 1 && !a.uniform) {
-    // the parent run (level d - 1) must be split: more than cap particles
-    const int sh = 3 * (a.depth - d + 1);
-    const uint32_t pre = k >> sh;
-    const int e = gallop_fwd(kw, i, a.n, (pre + 1u) << sh);
-    const int b = gallop_back(kw, i, pre << sh);
-    if (e - b <= a.cap) return w;
-    end = e;
+  // the parent run (level d - 1) must be split: more than cap particles
+  const bool check = cand && d >= 1 && !a.uniform;
+  const int sh = check ? 3 * (a.depth - d + 1) : 0;
+  const uint32_t pre = w.key >> sh;
+  const int e = search_fwd(kw, check, i, a.n, (pre + 1u) << sh);
+  const int b = search_back(kw, check, i, pre << sh);
+  if (check && e - b <= a.cap) cand = false;
+  if (cand) {
+    w.lo = d;
+    w.end = check ? e : a.n;
+    w.live = true;
   }
-  w.lo = d;
-  w.end = end;
-  w.live = true;
   return w;
 }
 
-// level l of the walk (called for l = 0, 1, ... in order): a cell starts here (cell), it is a
-// leaf (leaf), with cnt particles
+// level l of the walk (called for l = 0, 1, ... in order by the whole wave): a cell starts here
+// (cell), it is a leaf (leaf), with cnt particles
 __device__ __forceinline__ void walk_step(const TreeArgs& a, const KeyWin& kw, Walk& w, int l,
                                           bool& cell, bool& leaf, int& cnt) {
   cell = leaf = false;
   cnt = 0;
-  if (!w.live || l < w.lo) return;
+  const bool act = w.live && l >= w.lo;
   const int sh = 3 * (a.depth - l);
-  const int e = (l == 0) ? a.n : gallop_fwd(kw, w.i, w.end, ((w.key >> sh) + 1u) << sh);
-  cnt = e - w.i;
+  const int e = search_fwd(kw, act && l > 0, w.i, w.end, ((w.key >> sh) + 1u) << sh);
+  if (!act) return;
+  cnt = (l == 0 ? a.n : e) - w.i;
   cell = true;
   leaf = a.uniform ? (l >= a.depth) : (cnt <= a.cap || l >= a.depth);
-  w.end = e;
+  w.end = w.i + cnt;
   if (leaf) w.live = false;
 }
 
