@@ -259,7 +259,7 @@ void execute_plan(Plan& p, const void* m, void* phi, void* ax, void* ay, void* a
 size_t Plan::device_bytes() const {
   const DevBuf* bufs[] = {
       &keys, &perm, &xs, &ys, &zs, &ms, &ckey, &ccoord, &cpb, &cpe, &cparent, &cflags, &child8,
-      &nbr27, &leaves, &vkeys, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlev, &gridlet,
+      &nbr27, &leaves, &vcubes, &vlevel, &vlist, &vhash_keys, &vhash_vals, &vcount, &blocks, &dlev, &gridlet,
       &local, &moments, &p2m_list, &p2m_level, &lofs, &m2l_mean, &near_rb, &near_re, &item_cnt,
       &item_off, &items, &partial, &pairs, &leaf_of, &near_group_items, &cell_src, &cell_tgt, &cell_plist,
       &tab.m2m, &tab.l2l, &tab.fitw, &tab.ghat, &tab.gxy, &tab.gcell, &tab.twff,
@@ -289,7 +289,7 @@ size_t plan_bytes_estimate(const hpm_problem& pr, int64_t n) {
                                             // children, neighbours)
   b += c * (9 * 4 + 3 * 4 + 216 * 4 / 8);   // level scratch, leaf list, block tables of parents
   b += np * 8 + np / 8;                     // radix-sort status words, level counts per workgroup
-  b += c * (2 * 12 + 4 * 16);               // cube hash, virtual-cube set
+  b += c * (2 * 12 + 4 * 24);               // cube hash, virtual-cube set
   b += c * (2 * M * s + ML * s + 2 * kpad * s + 2 * s + 8);  // gridlets of cells and virtual
                                                               // cubes, locals, fit rows
   b += c * (27 * 8 + 8 + 4 * (16 + 64 * 5 * s));  // near-zone ranges and work items

@@ -180,7 +180,8 @@ struct Plan {
   DevBuf leaves;
   // virtual cubes (interaction-zone cubes inside coarser leaves), cell ids ncells .. ncells+nvirt-1
   int64_t nvirt = 0;
-  DevBuf vkeys;   // [nvirt] cube ids (1 << 3l | level-l Morton key), in the order found
+  DevBuf vcubes;  // [nvirt][3]: cube id (1 << 3l | level-l Morton key), first and end sorted
+                  // particle; in the order found
   DevBuf vlevel;  // [nvirt] level
   DevBuf vlist;   // [nvirt] cell id ncells + v
   // the set of virtual cube ids while they are listed: open addressing, 2^vhash_bits slots of

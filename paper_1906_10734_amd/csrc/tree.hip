@@ -556,9 +556,10 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_count(TreeArgs a) {
   if (tid < kTreeSeq) a.blk[size_t(blockIdx.x) * kTreeSeq + tid] = s_cnt[tid];
 }
 
-// One workgroup: the id bases of every count workgroup (levels contiguous, level-major; one wave
-// scans a sequence over the workgroups in chunks of 64), the level table, its copy in the
-// mailbox, and the words the later launches of the build accumulate into, cleared.
+// One workgroup: the id bases of every count workgroup within each level (one wave scans a
+// sequence over the workgroups in chunks of 64; the emit kernel adds the level's offset), the
+// level table (levels contiguous, level-major), its copy in the mailbox, and the words the later
+// launches of the build accumulate into, cleared.
 constexpr int kTreeScanThreads = 1024;
 __global__ __launch_bounds__(kTreeScanThreads) void k_tree_scan(TreeArgs a, int nb) {
   __shared__ int s_tot[kTreeSeq];
@@ -628,8 +629,6 @@ __global__ __launch_bounds__(kTreeScanThreads) void k_tree_scan(TreeArgs a, int 
     for (int w = 0; w < 4; ++w) a.zero_words[w] = 0;
     *a.zero_pairs = 0ull;
   }
-  for (size_t w = tid; w < size_t(nb) * kTreeSeq; w += kTreeScanThreads)
-    a.blk[w] += s_off[w % kTreeSeq];
 }
 
 // multiplicative (Fibonacci) hashing: the top "bits" bits of id times 2^32 / golden ratio
@@ -674,7 +673,10 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree_emit(TreeArgs a) {
   __shared__ uint32_t s_keys[kWinKeys];
   if (int64_t(a.lev[kLevCells]) > a.cap_cells) return;  // the host grows the arrays and re-runs
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < kTreeSeq) s_run[tid] = a.blk[size_t(blockIdx.x) * kTreeSeq + tid];
+  // this workgroup's first id on each level: its base within the level plus the level's offset
+  if (tid < kTreeSeq)
+    s_run[tid] = a.blk[size_t(blockIdx.x) * kTreeSeq + tid] +
+                 a.lev[tid < kMaxLevels ? kLevOff + tid : kLevLeafOff + tid - kMaxLevels];
   if (tid < kLevWords) s_lev[tid] = a.lev[tid];
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   __syncthreads();
@@ -1015,7 +1017,7 @@ struct VirtArgs {
   int bits;              // slots = 2^bits
   uint32_t gen;
   int* count;            // [0] cubes listed, [1] the set is full
-  uint32_t* vkeys;       // cube id of each v
+  int* vcubes;           // [v][3]: cube id, first and end sorted particle
   int* box;
 };
 
@@ -1031,7 +1033,7 @@ __device__ __forceinline__ void parent_range(const int* lev, int& first, int& en
 // One workgroup per parent of targets (grid-stride), one thread per slot of its 6^3 block: a
 // nonempty virtual cube in the interaction zone of some child (every block cube except the 8
 // children's own positions) joins the set; the thread that adds a new id takes the next index v
-// and records the id at vkeys[v]. A full set raises count[1]. (The near-zone list launch that
+// and records the id and the cube's particle range at vcubes[v]. A full set raises count[1]. (The near-zone list launch that
 // follows copies both words to the mailbox.)
 __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
   __shared__ int s_off[kMaxLevels + 1];
@@ -1074,7 +1076,9 @@ __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
                     (unsigned long long)mine) == cur) {
         const int v = atomicAdd(&a.count[0], 1);
         a.hval[h] = v;
-        a.vkeys[v] = id;
+        a.vcubes[3 * v] = int(id);
+        a.vcubes[3 * v + 1] = vb;
+        a.vcubes[3 * v + 2] = ve;
         placed = true;
         break;
       }
@@ -1090,13 +1094,13 @@ __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
 // and level of virtual cube v, stored at cell id ncells + v.
 __global__ __launch_bounds__(256) void k_virt_finish(VirtArgs a, int first, int nt, int ncells,
                                                      int nvirt, int* table, int* coord, int* pb,
-                                                     int* pe, int* vlevel, int* vlist, int n) {
+                                                     int* pe, int* vlevel, int* vlist) {
   __shared__ int s_off[kMaxLevels + 1];
   const int tid = threadIdx.x;
   if (int(blockIdx.x) >= nt) {
     const int v = (blockIdx.x - nt) * 256 + tid;
     if (v >= nvirt) return;
-    const uint32_t id = a.vkeys[v];
+    const uint32_t id = uint32_t(a.vcubes[3 * v]);
     const int l = cube_id_level(id);
     const uint32_t key = id ^ (1u << (3 * l));
     int x = 0, y = 0, z = 0;
@@ -1105,12 +1109,9 @@ __global__ __launch_bounds__(256) void k_virt_finish(VirtArgs a, int first, int 
       y |= int((key >> (3 * b + 1)) & 1u) << b;
       z |= int((key >> (3 * b + 2)) & 1u) << b;
     }
-    const int shift = 3 * (a.depth - l);
-    const int b0 = lower_bound_u32(a.keys, 0, n, key << shift);
-    const int e0 = lower_bound_u32(a.keys, b0, n, (key + 1u) << shift);
     coord[ncells + v] = pack_coord(x, y, z);
-    pb[ncells + v] = b0;
-    pe[ncells + v] = e0;
+    pb[ncells + v] = a.vcubes[3 * v + 1];
+    pe[ncells + v] = a.vcubes[3 * v + 2];
     vlevel[v] = l;
     vlist[v] = ncells + v;
     return;
@@ -1163,7 +1164,7 @@ static VirtArgs virt_args(Plan& p) {
   a.mask = uint32_t((size_t(1) << p.vhash_bits) - 1);
   a.gen = p.tree_gen;
   a.count = p.vcount.as<int>();
-  a.vkeys = p.vkeys.as<uint32_t>();
+  a.vcubes = p.vcubes.as<int>();
   a.box = p.dbox;
   return a;
 }
@@ -1180,7 +1181,7 @@ static void reserve_virt_set(Plan& p, int min_bits, hipStream_t s) {
   p.vhash_keys.reserve(slots * 8);
   HPM_HIP(hipMemsetAsync(p.vhash_keys.p, 0, slots * 8, s));
   p.vhash_vals.reserve(slots * 4);
-  p.vkeys.reserve(slots * 4);
+  p.vcubes.reserve(slots * 12);
 }
 
 static void enqueue_virt_insert(Plan& p, hipStream_t s) {
@@ -1203,7 +1204,7 @@ void finish_virtual(Plan& p, hipStream_t s) {
   p.blocks.reserve(size_t(nt) * 216 * 4);
   k_virt_finish<<<nt + nblk(nv, 256), 256, 0, s>>>(
       virt_args(p), first, nt, int(p.ncells), nv, p.blocks.as<int>(), p.ccoord.as<int>(),
-      p.cpb.as<int>(), p.cpe.as<int>(), p.vlevel.as<int>(), p.vlist.as<int>(), int(p.n));
+      p.cpb.as<int>(), p.cpe.as<int>(), p.vlevel.as<int>(), p.vlist.as<int>());
   HPM_LAUNCH_CHECK();
 }
 
