@@ -84,14 +84,26 @@ __device__ __forceinline__ int coord_y(int c) { return (c >> 10) & 1023; }
 __device__ __forceinline__ int coord_z(int c) { return (c >> 20) & 1023; }
 __device__ __forceinline__ int pack_coord(int x, int y, int z) { return x | (y << 10) | (z << 20); }
 
-// first index in [lo, hi) with keys[idx] >= v
-__device__ __forceinline__ int lower_bound_u32(const uint32_t* keys, int lo, int hi, uint32_t v) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (keys[mid] < v) lo = mid + 1;
-    else hi = mid;
+// [first index with keys >= v0, first index with keys >= v1) within [lo, hi), v0 <= v1: the two
+// bisections run in lockstep, so the loads of a step do not wait on each other
+__device__ __forceinline__ void key_range_u32(const uint32_t* keys, int lo, int hi, uint32_t v0,
+                                              uint32_t v1, int& b, int& e) {
+  int l0 = lo, h0 = hi, l1 = lo, h1 = hi;
+  while (l0 < h0 || l1 < h1) {
+    const int m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
+    const uint32_t k0 = l0 < h0 ? keys[m0] : 0u;
+    const uint32_t k1 = l1 < h1 ? keys[m1] : 0u;
+    if (l0 < h0) {
+      if (k0 < v0) l0 = m0 + 1;
+      else h0 = m0;
+    }
+    if (l1 < h1) {
+      if (k1 < v1) l1 = m1 + 1;
+      else h1 = m1;
+    }
   }
-  return lo;
+  b = l0;
+  e = l1;
 }
 
 // level of a global cell id from the per-level offsets (levels are contiguous in id space)

@@ -233,8 +233,7 @@ __global__ __launch_bounds__(kNearThreads) void k_near_lists(NearArgs a, int per
                   qz = coord_z(pc) + k / 9 - 1;
         const uint32_t key = morton3(uint32_t(qx), uint32_t(qy), uint32_t(qz), l);
         const int shift = 3 * (a.depth - l);
-        rb = lower_bound_u32(a.keys, a.pb[c], a.pe[c], key << shift);
-        re = lower_bound_u32(a.keys, rb, a.pe[c], (key + 1u) << shift);
+        key_range_u32(a.keys, a.pb[c], a.pe[c], key << shift, (key + 1u) << shift, rb, re);
       }
       a.near_rb[size_t(li) * 27 + k] = rb;
       a.near_re[size_t(li) * 27 + k] = re;

@@ -1054,8 +1054,8 @@ __global__ __launch_bounds__(256) void k_virt_insert(VirtArgs a) {
     if (z.coarse < 0) continue;
     const int shift = 3 * (a.depth - l);
     const int cb = a.pb[z.coarse], ce = a.pe[z.coarse];
-    const int vb = lower_bound_u32(a.keys, cb, ce, z.key << shift);
-    const int ve = lower_bound_u32(a.keys, vb, ce, (z.key + 1u) << shift);
+    int vb, ve;
+    key_range_u32(a.keys, cb, ce, z.key << shift, (z.key + 1u) << shift, vb, ve);
     if (ve <= vb) continue;
     const uint32_t id = cube_id(l, z.key);
     const uint64_t mine = (uint64_t(a.gen) << 32) | id;

@@ -152,14 +152,21 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
       wreg[f] = (e < KC * MP2 && k < kpad && c < mpad) ? W[size_t(k) * mpad + c] : T(0);
     }
   };
-  load_w(0);
-  for (int k0 = 0; k0 < kpad; k0 += KC) {
-    T av[KS];
+  // the same chunk rows of this lane's Q row, likewise one chunk ahead
+  T an[KS];
+  auto load_a = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
       const int k = k0 + 4 * q + kk;
-      av[q] = (arow_ok && k < kpad) ? Q[size_t(arow) * kpad + k] : T(0);
+      an[q] = (arow_ok && k < kpad) ? Q[size_t(arow) * kpad + k] : T(0);
     }
+  };
+  load_w(0);
+  load_a(0);
+  for (int k0 = 0; k0 < kpad; k0 += KC) {
+    T av[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) av[q] = an[q];
     __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -167,7 +174,10 @@ __global__ __launch_bounds__(256) void k_fit_gemm(const T* __restrict__ Q, const
       if (e < KC * MP2) sW[e] = wreg[f];
     }
     __syncthreads();
-    if (k0 + KC < kpad) load_w(k0 + KC);  // next chunk in flight during this one's MFMAs
+    if (k0 + KC < kpad) {  // next chunk in flight during this one's MFMAs
+      load_w(k0 + KC);
+      load_a(k0 + KC);
+    }
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
       const T* wrow = sW + (4 * q + kk) * MP2 + c0 * 16 + i;
