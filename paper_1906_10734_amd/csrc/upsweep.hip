@@ -52,7 +52,6 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
   constexpr int M = NG * NG * NG;
   constexpr int PER = (M + 63) / 64;
   __shared__ T s_b[3][64][NG];
-  __shared__ T s_m[64];
   __shared__ int s_off[kMaxLevels + 1];
   const int lane = threadIdx.x;
   if (lane <= kMaxLevels) s_off[lane] = a.level_off[lane];
@@ -83,13 +82,13 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < NG; ++k) bx[k] = by[k] = bz[k] = T(0);
     }
+    // the mass goes into the x factor: each term is (m P_a(x)) P_b(y) P_c(z), evaluated left to right
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
-      s_b[0][lane][k] = bx[k];
+      s_b[0][lane][k] = mj * bx[k];
       s_b[1][lane][k] = by[k];
       s_b[2][lane][k] = bz[k];
     }
-    s_m[lane] = mj;
     __syncthreads();
     const int cnt = min(64, pe - j0);
 #pragma unroll
@@ -98,7 +97,7 @@ __global__ __launch_bounds__(64) void k_p2m_moments(P2MArgs<T> a) {
       if (nidx < M) {
         const int nx = nidx % NG, ny = (nidx / NG) % NG, nz = nidx / (NG * NG);
         T s = acc[r];
-        for (int jj = 0; jj < cnt; ++jj) s += s_m[jj] * s_b[0][jj][nx] * s_b[1][jj][ny] * s_b[2][jj][nz];
+        for (int jj = 0; jj < cnt; ++jj) s += s_b[0][jj][nx] * s_b[1][jj][ny] * s_b[2][jj][nz];
         acc[r] = s;
       }
     }
