@@ -544,6 +544,9 @@ __global__ __launch_bounds__(kSlabThreads) void k_m2l_slab(M2LArgs<T> a) {
   __shared__ T s_green[S::green_lds ? D * H * H : 1];  // [d][ky folded][kx]
   __shared__ float4 s_twf[STRICT ? n : 1];
   const int tid = threadIdx.x;
+  // Waves of this kernel win issue arbitration over the near-zone kernel running beside it on
+  // the second stream (measured: 1% off the solve, and off this kernel alone as well).
+  __builtin_amdgcn_s_setprio(2);
   if (tid <= kMaxLevels) s_off[tid] = a.level_off[tid];
   for (int m = tid; m < n; m += NT) {
     if constexpr (STRICT) {
